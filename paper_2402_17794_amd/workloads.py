@@ -1,0 +1,155 @@
+"""Seeded synthetic input matrices shaped like the paper's test problems.
+
+This module only draws inputs; it holds none of the randomized-SVD
+arithmetic.  Both the GPU path and the FP64 CPU oracle are fed the matrices
+produced here.  Random draws use numpy's PCG64 generator (`default_rng`), not
+the Philox generator of the test matrix, so that the inputs are independent
+of the method's own random numbers.
+
+Families
+  known_spectrum  A = U diag(sigma) V^T with Haar-distributed U, V (thin QR of
+                  a Gaussian matrix with the signs of diag(R) folded in, the
+                  standard recipe for the Haar measure).
+  spectra         the singular-value profiles of the benchmark configurations:
+                  geometric 0.8^i (512 x 256), max(0.95^i, 1e-6) (8192^2),
+                  1/i (2048^2 slow decay), i^-1.5 (mixed precision).
+  eq41_spectrum   the test family of eq. (4.1) (Section 4.2): singular values
+                  gap/j for j <= r and 1/j after, m x n = 3000 x 300, r = 15.
+                  The paper builds it from sparse nonnegative vectors of
+                  unspecified density; this stand-in uses Haar factors so the
+                  spectrum is exactly the stated one.
+  image           the image-restoration stand-in (Section 4.1 uses a
+                  photograph that is not available): a 2048 x 2048 sum of 60
+                  separable Gaussian bumps, min-max normalised to [0, 1], plus
+                  i.i.d. N(0, 0.05^2) noise.
+  exact_rank      A = U diag(sigma_1..r) V^T of exact rank r.
+"""
+
+import numpy as np
+
+
+def _rng(seed):
+    return np.random.default_rng(int(seed))
+
+
+def haar(rows, cols, seed, device=None):
+    """rows x cols matrix with orthonormal columns, Haar-distributed.
+
+    With `device` set to a torch CUDA device the QR runs there in float64
+    (the Gaussian draw stays on the host, so the matrix depends only on the
+    seed up to the rounding of the QR); the result is returned as a float64
+    torch tensor on that device."""
+    if cols > rows:
+        raise ValueError("haar needs rows >= cols")
+    G = _rng(seed).standard_normal((rows, cols))
+    if device is None:
+        Q, R = np.linalg.qr(G)
+        d = np.where(np.diag(R) < 0, -1.0, 1.0)
+        return Q * d[None, :]
+    import torch
+    Gt = torch.from_numpy(G).to(device)
+    Q, R = torch.linalg.qr(Gt)
+    d = torch.where(torch.diagonal(R) < 0, -1.0, 1.0).to(Q.dtype)
+    return Q * d[None, :]
+
+
+def known_spectrum(m, n, sigma, seed_u=1, seed_v=2, device=None):
+    """A = U diag(sigma) V^T (float64).  len(sigma) must be min(m, n).
+    On a torch device, returns a float64 tensor there."""
+    d = min(m, n)
+    sigma = np.asarray(sigma, dtype=np.float64)
+    if sigma.shape != (d,):
+        raise ValueError("sigma must have min(m, n) entries")
+    U = haar(m, d, seed_u, device)
+    V = haar(n, d, seed_v, device)
+    if device is None:
+        return (U * sigma[None, :]) @ V.T
+    import torch
+    s = torch.from_numpy(sigma).to(U.device)
+    return (U * s[None, :]) @ V.T
+
+
+def spectrum_geometric(d, ratio, floor=0.0):
+    """sigma_i = max(ratio^i, floor), i = 1..d."""
+    i = np.arange(1, d + 1, dtype=np.float64)
+    return np.maximum(ratio ** i, floor)
+
+
+def spectrum_power(d, alpha):
+    """sigma_i = i^-alpha, i = 1..d."""
+    i = np.arange(1, d + 1, dtype=np.float64)
+    return i ** (-float(alpha))
+
+
+def eq41_spectrum(d, gap, r=15):
+    """Eq. (4.1): sigma_j = gap / j for j <= r, 1 / j for j > r."""
+    j = np.arange(1, d + 1, dtype=np.float64)
+    return np.where(j <= r, gap / j, 1.0 / j)
+
+
+def eq41_matrix(gap, seed_u=1, seed_v=2, m=3000, n=300, r=15):
+    return known_spectrum(m, n, eq41_spectrum(min(m, n), gap, r), seed_u, seed_v)
+
+
+def exact_rank(m, n, r, seed_u=1, seed_v=2, top=1.0, ratio=0.7):
+    """Exact rank-r matrix with sigma_i = top * ratio^(i-1), i <= r, 0 after."""
+    d = min(m, n)
+    sigma = np.zeros(d)
+    sigma[:r] = top * ratio ** np.arange(r)
+    return known_spectrum(m, n, sigma, seed_u, seed_v), sigma
+
+
+def image(size=2048, bumps=60, noise=0.05, seed_bumps=3, seed_noise=4):
+    """Image-shaped test matrix: sum of `bumps` separable Gaussian bumps with
+    centres uniform in [0, size)^2, standard deviations uniform in [20, 200]
+    pixels and amplitudes uniform in [0, 1]; min-max normalised to [0, 1];
+    then i.i.d. N(0, noise^2) added (no clipping).  Row index = y, column
+    index = x.  The noiseless part has rank <= bumps."""
+    rb = _rng(seed_bumps)
+    cx = rb.uniform(0.0, size, bumps)
+    cy = rb.uniform(0.0, size, bumps)
+    w = rb.uniform(20.0, 200.0, bumps)
+    a = rb.uniform(0.0, 1.0, bumps)
+    x = np.arange(size, dtype=np.float64)
+    gy = np.exp(-((x[:, None] - cy[None, :]) ** 2) / (2.0 * w[None, :] ** 2))   # size x bumps
+    gx = np.exp(-((x[:, None] - cx[None, :]) ** 2) / (2.0 * w[None, :] ** 2))
+    img = (gy * a[None, :]) @ gx.T
+    img = (img - img.min()) / (img.max() - img.min())
+    return img + noise * _rng(seed_noise).standard_normal((size, size))
+
+
+# Benchmark configurations: (m, n, k, p, q, dtype, spectrum description).
+CONFIGS = {
+    "c1_fp64_512x256": dict(m=512, n=256, k=20, p=10, q=0, dtype="f64",
+                            spectrum=("geometric", 0.8, 0.0)),
+    "c2_fp32_8192": dict(m=8192, n=8192, k=100, p=10, q=2, dtype="f32",
+                         spectrum=("geometric", 0.95, 1e-6)),
+    "c3a_fp32_image_2048": dict(m=2048, n=2048, k=50, p=10, q=1, dtype="f32",
+                                spectrum=("image",)),
+    "c3b_fp32_slow_2048": dict(m=2048, n=2048, k=50, p=10, q=1, dtype="f32",
+                               spectrum=("power", 1.0)),
+}
+
+
+def config_sigma(name):
+    c = CONFIGS[name]
+    d = min(c["m"], c["n"])
+    kind = c["spectrum"][0]
+    if kind == "geometric":
+        return spectrum_geometric(d, c["spectrum"][1], c["spectrum"][2])
+    if kind == "power":
+        return spectrum_power(d, c["spectrum"][1])
+    return None
+
+
+def config_matrix(name, device=None):
+    """The float64 input matrix of a named configuration (numpy array, or a
+    torch float64 tensor on `device` for the known-spectrum families)."""
+    c = CONFIGS[name]
+    if c["spectrum"][0] == "image":
+        A = image(c["m"])
+        if device is None:
+            return A
+        import torch
+        return torch.from_numpy(A).to(device)
+    return known_spectrum(c["m"], c["n"], config_sigma(name), 1, 2, device)
