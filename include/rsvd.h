@@ -1,0 +1,169 @@
+/*
+ * rsvd.h - C ABI of the MI355X (gfx950) randomized SVD library (librsvd.so).
+ *
+ * The library computes the randomized SVD of Algorithm 4 of the thesis
+ * (Chapter 3, Section 3.3, "accuracy enhanced randomized SVD with
+ * orthonormalization"): for an m x n matrix A, target rank k, oversampling p
+ * and power exponent q, with l = min(k + p, min(m, n)):
+ *
+ *   Omega  = n x l standard Gaussian test matrix          (step 1)
+ *   Y      = A Omega,  Q = orth(Y)                          (steps 2-3)
+ *   q times: W = orth(A^T Q),  Q = orth(A W)               (steps 4-5)
+ *   B      = Q^T A,  B = U~ Sigma V^T,  U = Q U~            (steps 6-8)
+ *
+ * truncated to the top k singular triplets (Section 3.1, after Algorithm 2).
+ * Algorithm 2 (Section 3.1) is the case q = 0.  The error measure
+ * ||A - Q Q^T A|| of Theorems 2, 3 and 6 is available as an option.
+ *
+ * Conventions
+ *  - Every matrix is dense, real and ROW-MAJOR with a leading dimension `ld`
+ *    (elements between the starts of consecutive rows, ld >= cols).
+ *  - All matrix and vector arguments are DEVICE pointers on the handle's
+ *    device unless stated otherwise.  The caller owns every buffer; the
+ *    library never frees caller memory and keeps no pointer after a call
+ *    returns (asynchronous work enqueued on `stream` still uses them).
+ *  - Work is enqueued asynchronously on the caller's `stream`
+ *    (a hipStream_t passed as void*; NULL is the null stream).  Argument
+ *    errors are detected on the host before anything is enqueued and
+ *    returned synchronously.  Numerical conditions are reported in the
+ *    device `info` word (bit flags below), readable after the stream is
+ *    synchronised.
+ *  - A handle is not thread-safe; use one per host thread.
+ *  - Omega is never stored: it is generated inside the sketch kernel from
+ *    (seed, row, column) by Philox4x32-10 and the Box-Muller transform
+ *    (see rsvd_omega for the exact element definition), so a solve is a
+ *    pure function of (A, k, p, q, seed).
+ */
+#ifndef RSVD_H
+#define RSVD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RSVD_OK = 0,
+    RSVD_ERR_INVALID_ARG = 1,      /* bad pointer, size, leading dimension or parameter */
+    RSVD_ERR_UNSUPPORTED = 2,      /* valid request this build does not implement */
+    RSVD_ERR_NO_MEMORY = 3,        /* a host or device allocation failed */
+    RSVD_ERR_WORKSPACE_TOO_SMALL = 4,
+    RSVD_ERR_DEVICE = 5            /* a HIP runtime call failed */
+} rsvd_status;
+
+typedef enum {
+    RSVD_F64 = 0,                  /* double: all arithmetic in FP64 (FP64 MFMA) */
+    RSVD_F32 = 1                   /* float: products with A on FP32 MFMA, FP32
+                                      accumulation; Gram, Cholesky, small SVD FP64 */
+} rsvd_dtype;
+
+/* Bits of the device `info` word written by rsvd_solve / rsvd_orth. */
+#define RSVD_INFO_QR_FALLBACK        1  /* CholeskyQR broke down (rank-deficient or
+                                           too ill-conditioned Y); Householder QR used */
+#define RSVD_INFO_SHIFTED_CHOLESKY   2  /* small SVD: Gram of B singular; a diagonal
+                                           shift was used (B rank-deficient) */
+#define RSVD_INFO_JACOBI_NOT_CONVERGED 4 /* small SVD hit the sweep cap */
+#define RSVD_INFO_NONFINITE          8  /* NaN or Inf met in a Gram matrix */
+
+typedef struct rsvd_handle rsvd_handle;
+
+/* Input matrix A: rows x cols, row-major, leading dimension ld (elements).
+ * For RSVD_F32, ld must be a multiple of 4 and data 16-byte aligned; for
+ * RSVD_F64 a multiple of 2 and 16-byte aligned. */
+typedef struct {
+    const void* data;
+    int32_t dtype;                 /* rsvd_dtype */
+    int32_t reserved0;
+    int64_t rows, cols, ld;
+} rsvd_matrix;
+
+/* Parameters of Algorithm 4 (inputs A, k, p, q of the algorithm statement). */
+typedef struct {
+    int64_t k;                     /* target rank, 1 <= k <= min(m, n) */
+    int64_t p;                     /* oversampling, p >= 0; l = min(k + p, min(m, n)) */
+    int64_t q;                     /* power iterations, q >= 0 (q = 0: Algorithm 2) */
+    uint64_t seed;                 /* key of the Philox test matrix */
+    int32_t residual;              /* 0: none; 2: Frobenius norm of A - Q Q^T A */
+    int32_t return_full_l;         /* 0: return the top k triplets; 1: all l */
+    int32_t force_householder;     /* 1: always orthonormalise by Householder QR */
+    int32_t reserved0;
+} rsvd_params;
+
+/* Outputs.  r = k, or l when return_full_l is set.  U and Vt have the
+ * dtype of A.  S, residual are doubles.  Q (optional) receives the final
+ * m x l orthonormal basis of Stage 1. */
+typedef struct {
+    void* U;  int64_t ldu;         /* m x r, row-major, ldu >= r */
+    double* S;                     /* r singular values, descending */
+    void* Vt; int64_t ldvt;        /* r x n, row-major, ldvt >= n */
+    double* residual;              /* nullable; [0] = reserved (0), [1] = ||A - QQ^T A||_F */
+    int32_t* info;                 /* required; RSVD_INFO_* bit flags */
+    void* Q;  int64_t ldq;         /* nullable; m x l, row-major, ldq >= l */
+} rsvd_result;
+
+/* Create a handle bound to HIP device `device`.  Allocates a small amount of
+ * device memory (counters) and queries the device.  *out is NULL on error. */
+rsvd_status rsvd_create(rsvd_handle** out, int device);
+rsvd_status rsvd_destroy(rsvd_handle* h);
+
+/* l actually used for (m, n, k, p): min(k + p, min(m, n)). */
+int64_t rsvd_l_used(int64_t m, int64_t n, int64_t k, int64_t p);
+
+/* Bytes of device workspace rsvd_solve needs for this problem. */
+rsvd_status rsvd_workspace_size(const rsvd_handle* h, const rsvd_matrix* A,
+                                const rsvd_params* params, size_t* bytes);
+
+/* Enqueue one randomized SVD (Algorithm 4) of A on `stream`.  `workspace`
+ * is device memory of at least rsvd_workspace_size bytes, owned by the
+ * caller, not used concurrently by another call, 256-byte aligned.  No
+ * device memory is allocated by this call. */
+rsvd_status rsvd_solve(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* params,
+                       const rsvd_result* out, void* workspace, size_t workspace_bytes,
+                       void* stream);
+
+const char* rsvd_status_string(rsvd_status s);
+
+/* ---- Single steps of the path, for testing each kernel on its own. ---- */
+
+/* The test matrix of Algorithm 4 step 1, materialised (the solve never does
+ * this).  Element (i, j), 0 <= i < n, 0 <= j < l, comes from the
+ * Philox4x32-10 block with counter (i / 4, j, stream_id, 0) and key
+ * (seed mod 2^32, seed / 2^32): words (w0, w1) serve rows 4g, 4g+1 and
+ * (w2, w3) rows 4g+2, 4g+3; with u1 = ((wa >> 8) + 1) 2^-24 and
+ * u2 = (wb >> 8) 2^-24 the even row is sqrt(-2 ln u1) cos(2 pi u2) and the
+ * odd row sqrt(-2 ln u1) sin(2 pi u2), evaluated in the precision of
+ * `dtype`.  out: n x l row-major, ld >= l. */
+rsvd_status rsvd_omega(int32_t dtype, uint64_t seed, uint32_t stream_id, int64_t n, int64_t l,
+                       void* out, int64_t ld, void* stream);
+
+/* Raw Philox4x32-10 words: for each of `count` counter pairs (g, j) in
+ * ctr (device, 2*count uint32), writes the 4 words of block
+ * (g, j, stream_id, 0) under key (seed) to out (device, 4*count uint32). */
+rsvd_status rsvd_philox_words(uint64_t seed, uint32_t stream_id, const uint32_t* ctr, int64_t count,
+                              uint32_t* out, void* stream);
+
+/* Y = A X (trans = 0; X is n x ncols, Y is m x ncols) or Y = A^T X
+ * (trans = 1; X is m x ncols, Y is n x ncols) with the solve's MFMA kernels.
+ * If X is NULL and trans = 0, X is the test matrix Omega(seed) (generated in
+ * the kernel).  ncols <= 512.  Uses `workspace` (rsvd_gemm_workspace_size). */
+rsvd_status rsvd_gemm_workspace_size(const rsvd_matrix* A, int32_t trans, int64_t ncols, size_t* bytes);
+rsvd_status rsvd_gemm(rsvd_handle* h, const rsvd_matrix* A, int32_t trans, const void* X, int64_t ldx,
+                      uint64_t seed, int64_t ncols, void* Y, int64_t ldy,
+                      void* workspace, size_t workspace_bytes, void* stream);
+
+/* orth of Algorithms 1-4: Q (rows x l, ldq) = orthonormal basis of range(Y)
+ * (rows x l, ldy), l <= rows, by CholeskyQR2 (FP64 Gram and Cholesky) with a
+ * Householder QR fallback; diag(R) > 0 so Q is the Q factor of the thin QR.
+ * info: device int32, RSVD_INFO_* flags OR-ed in (caller zeroes it). */
+rsvd_status rsvd_orth_workspace_size(int32_t dtype, int64_t rows, int64_t l, size_t* bytes);
+rsvd_status rsvd_orth(rsvd_handle* h, int32_t dtype, int64_t rows, int64_t l, const void* Y, int64_t ldy,
+                      void* Q, int64_t ldq, int32_t force_householder, int32_t* info,
+                      void* workspace, size_t workspace_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSVD_H */

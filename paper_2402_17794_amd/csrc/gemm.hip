@@ -1,0 +1,371 @@
+// Skinny products with the large matrix A on MFMA (gfx950).
+//
+// Every pass over A in Algorithm 4 is a product of A (or A^T) with a thin
+// matrix of l columns: the sketch Y = A Omega (step 2), the power-loop
+// products Z = A^T Q and Y = A W (steps 4-5) and the projection
+// B^T = A^T Q (step 6).  These passes are the tau_A (k + p) terms of the cost
+// model in Section 3.1.1 and dominate the run time.
+//
+// Kernel shape.  A workgroup of 4 wavefronts owns BM output rows and all
+// L = 16 * LT output columns (the whole thin dimension), and one slice of
+// the reduction dimension (split-K, `splits` slices).  Each wavefront owns
+// 16 * RT rows and issues 16x16x4 MFMAs over RT x LT accumulator tiles, so
+// one LDS fragment of A feeds LT MFMAs and one fragment of X feeds RT.
+// A is streamed HBM -> registers -> LDS once per workgroup with 16-byte
+// loads, one tile ahead of the MFMAs.  The thin operand comes either from
+// device memory or, for the sketch, from the counter-based generator
+// evaluated straight into LDS (Omega never touches HBM).
+//
+// Split-K reduction is deterministic: every slice writes its partial tile,
+// the last slice to finish (device-scope counter) sums all slices in slice
+// order and writes Y, then resets the counter.  Block ids map slice-fastest,
+// so with 8 slices each XCD (ids are dealt round-robin over the 8 XCDs)
+// holds one K slice of every row tile and reads one slice of the thin
+// operand into its own L2.
+#include <algorithm>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "philox.hpp"
+
+namespace rsvd {
+
+template <typename T> struct GemmTile;
+template <> struct GemmTile<float> { static constexpr int RT = 2, BK = 32; };
+template <> struct GemmTile<double> { static constexpr int RT = 1, BK = 16; };
+
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { using type = float4; static constexpr int n = 4; };
+template <> struct Vec16<double> { using type = double2; static constexpr int n = 2; };
+
+template <typename T>
+__device__ __forceinline__ void vec_store(T* dst, const typename Vec16<T>::type& v) {
+    *reinterpret_cast<typename Vec16<T>::type*>(dst) = v;
+}
+template <typename T>
+__device__ __forceinline__ T vget(const typename Vec16<T>::type& v, int i);
+template <> __device__ __forceinline__ float vget<float>(const float4& v, int i) {
+    return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
+}
+template <> __device__ __forceinline__ double vget<double>(const double2& v, int i) { return i == 0 ? v.x : v.y; }
+template <typename T>
+__device__ __forceinline__ void vset(typename Vec16<T>::type& v, int i, T x);
+template <> __device__ __forceinline__ void vset<float>(float4& v, int i, float x) {
+    if (i == 0) v.x = x; else if (i == 1) v.y = x; else if (i == 2) v.z = x; else v.w = x;
+}
+template <> __device__ __forceinline__ void vset<double>(double2& v, int i, double x) {
+    if (i == 0) v.x = x; else v.y = x;
+}
+
+// LDS strides chosen so that the 4 lane groups of an MFMA fragment read hit
+// disjoint banks.
+template <typename T, int L> struct Strides {
+    static constexpr int BK = GemmTile<T>::BK;
+    static constexpr int BM = 64 * GemmTile<T>::RT;
+    static constexpr int SA_NN = BK + 16 / (int)sizeof(T);
+    static constexpr int SA_TN = BM + 64 / (int)sizeof(T);
+    static constexpr int SB = (sizeof(T) == 4) ? ((L % 32 == 16) ? L : L + 16)
+                                               : ((L % 32 == 16) ? L + 8 : L + 8);
+};
+
+template <typename T, bool TRANS, bool OMEGA, int LT>
+__global__ __launch_bounds__(256) void skinny_gemm_kernel(GemmArgs g) {
+    constexpr int RT = GemmTile<T>::RT;
+    constexpr int BK = GemmTile<T>::BK;
+    constexpr int BM = 64 * RT;
+    constexpr int L = 16 * LT;
+    constexpr int VEC = Vec16<T>::n;
+    using V = typename Vec16<T>::type;
+    using S = Strides<T, L>;
+    constexpr int SA = TRANS ? S::SA_TN : S::SA_NN;
+    constexpr int SB = S::SB;
+    constexpr int A_ELEMS = TRANS ? BK * SA : BM * SA;
+    constexpr int NVA = BM * BK / VEC / 256;                   // A vectors per thread
+    constexpr int NVB = (BK * L / VEC + 255) / 256;            // X vectors per thread
+    constexpr int NOB = (BK / 4 * L + 255) / 256;              // Omega blocks per thread
+
+    __shared__ __attribute__((aligned(16))) T As[A_ELEMS];
+    __shared__ __attribute__((aligned(16))) T Bs[BK * SB];
+
+    const T* __restrict__ A = static_cast<const T*>(g.A);
+    const T* __restrict__ X = static_cast<const T*>(g.X);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int splits = g.splits;
+    const int split = blockIdx.x % splits;
+    const int tile = blockIdx.x / splits;
+    const int64_t row0 = (int64_t)tile * BM;
+    const int64_t kchunk = round_up(ceil_div(g.K, splits), BK);
+    const int64_t kbeg = (int64_t)split * kchunk;
+    const int64_t kend = min(g.K, kbeg + kchunk);
+    const bool avec = ((g.lda % VEC) == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+    const bool xvec = !OMEGA && ((g.ldx % VEC) == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
+
+    using Acc = typename Acc4<T>::type;
+    Acc acc[RT][LT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int t = 0; t < LT; ++t) acc[r][t] = Acc{0, 0, 0, 0};
+
+    V ra[NVA];
+    V rb[OMEGA ? 1 : NVB];
+    T ro[OMEGA ? NOB : 1][4];
+
+    auto load_a = [&](int64_t k0) {
+#pragma unroll
+        for (int it = 0; it < NVA; ++it) {
+            const int idx = tid + 256 * it;
+            int64_t row, col;                   // element (row, col) of A in memory
+            if (!TRANS) { row = row0 + idx / (BK / VEC); col = k0 + (idx % (BK / VEC)) * VEC; }
+            else        { row = k0 + idx / (BM / VEC);   col = row0 + (idx % (BM / VEC)) * VEC; }
+            const int64_t rlim = TRANS ? kend : g.M;      // rows of A valid here
+            const int64_t clim = TRANS ? g.M : kend;      // cols of A valid here
+            V v;
+            if (row < rlim && avec && col + VEC <= clim) {
+                v = *reinterpret_cast<const V*>(A + row * g.lda + col);
+            } else {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e)
+                    vset<T>(v, e, (row < rlim && col + e < clim) ? A[row * g.lda + col + e] : T(0));
+            }
+            ra[it] = v;
+        }
+    };
+    auto store_a = [&]() {
+#pragma unroll
+        for (int it = 0; it < NVA; ++it) {
+            const int idx = tid + 256 * it;
+            if (!TRANS) vec_store<T>(&As[(idx / (BK / VEC)) * SA + (idx % (BK / VEC)) * VEC], ra[it]);
+            else        vec_store<T>(&As[(idx / (BM / VEC)) * SA + (idx % (BM / VEC)) * VEC], ra[it]);
+        }
+    };
+    auto load_b = [&](int64_t k0) {
+        if constexpr (OMEGA) {
+#pragma unroll
+            for (int it = 0; it < NOB; ++it) {
+                const int idx = tid + 256 * it;
+                const int gi = idx / L, j = idx % L;
+                const int64_t r = k0 + 4 * gi;
+                if (idx < BK / 4 * L && j < g.ncols && r < kend) {
+                    omega_block<T>(g.seed, 0u, (uint32_t)(r >> 2), (uint32_t)j, ro[it]);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (r + e >= kend) ro[it][e] = T(0);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) ro[it][e] = T(0);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int it = 0; it < NVB; ++it) {
+                const int idx = tid + 256 * it;
+                const int rr = idx / (L / VEC), c = (idx % (L / VEC)) * VEC;
+                const int64_t r = k0 + rr;
+                V v;
+                if (idx < BK * L / VEC && r < kend && xvec && c + VEC <= g.ncols) {
+                    v = *reinterpret_cast<const V*>(X + r * g.ldx + c);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e)
+                        vset<T>(v, e, (idx < BK * L / VEC && r < kend && c + e < g.ncols) ? X[r * g.ldx + c + e] : T(0));
+                }
+                rb[it] = v;
+            }
+        }
+    };
+    auto store_b = [&]() {
+        if constexpr (OMEGA) {
+#pragma unroll
+            for (int it = 0; it < NOB; ++it) {
+                const int idx = tid + 256 * it;
+                if (idx < BK / 4 * L) {
+                    const int gi = idx / L, j = idx % L;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) Bs[(4 * gi + e) * SB + j] = ro[it][e];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int it = 0; it < NVB; ++it) {
+                const int idx = tid + 256 * it;
+                if (idx < BK * L / VEC) vec_store<T>(&Bs[(idx / (L / VEC)) * SB + (idx % (L / VEC)) * VEC], rb[it]);
+            }
+        }
+    };
+
+    const int wm = wave * 16 * RT;
+    const int li = lane & 15, lk = lane >> 4;
+    if (kbeg < kend) {
+        load_a(kbeg);
+        load_b(kbeg);
+        for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+            __syncthreads();
+            store_a();
+            store_b();
+            __syncthreads();
+            if (k0 + BK < kend) {       // prefetch the next tile while the MFMAs run
+                load_a(k0 + BK);
+                load_b(k0 + BK);
+            }
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 4) {
+                T a[RT];
+#pragma unroll
+                for (int r = 0; r < RT; ++r)
+                    a[r] = TRANS ? As[(kk + lk) * SA + wm + 16 * r + li] : As[(wm + 16 * r + li) * SA + kk + lk];
+#pragma unroll
+                for (int t = 0; t < LT; ++t) {
+                    const T b = Bs[(kk + lk) * SB + 16 * t + li];
+#pragma unroll
+                    for (int r = 0; r < RT; ++r) acc[r][t] = mfma16x16x4(a[r], b, acc[r][t]);
+                }
+            }
+        }
+    }
+
+    // Epilogue.
+    T* __restrict__ Y = static_cast<T*>(g.Y);
+    if (splits == 1) {
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int t = 0; t < LT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t row = row0 + wm + 16 * r + acc_row<T>(lk, v);
+                    const int col = 16 * t + li;
+                    if (row < g.M && col < g.wcols) Y[row * g.ldy + col] = acc[r][t][v];
+                }
+        return;
+    }
+    T* __restrict__ P = static_cast<T*>(g.partials);
+    const int64_t pstride = g.M * L;
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int t = 0; t < LT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = row0 + wm + 16 * r + acc_row<T>(lk, v);
+                if (row < g.M) P[split * pstride + row * L + 16 * t + li] = acc[r][t][v];
+            }
+    __threadfence();
+    __syncthreads();
+    __shared__ int last;
+    if (tid == 0) last = (atomicAdd(&g.counters[tile], 1) == splits - 1);
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    const int rows_here = (int)min<int64_t>(BM, g.M - row0);
+    for (int idx = tid; idx < rows_here * (L / VEC); idx += 256) {
+        const int rr = idx / (L / VEC), c = (idx % (L / VEC)) * VEC;
+        const int64_t off = (row0 + rr) * L + c;
+        V sum = *reinterpret_cast<const V*>(P + off);
+        for (int s = 1; s < splits; ++s) {
+            const V x = *reinterpret_cast<const V*>(P + s * pstride + off);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) vset<T>(sum, e, vget<T>(sum, e) + vget<T>(x, e));
+        }
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+            if (c + e < g.wcols) Y[(row0 + rr) * g.ldy + c + e] = vget<T>(sum, e);
+    }
+    if (tid == 0) g.counters[tile] = 0;
+}
+
+template <typename T, bool TRANS, bool OMEGA>
+static hipError_t dispatch_lt(const GemmArgs& a, int LT, dim3 grid, hipStream_t s) {
+#define RSVD_LT_CASE(N) \
+    case N: hipLaunchKernelGGL((skinny_gemm_kernel<T, TRANS, OMEGA, N>), grid, dim3(256), 0, s, a); break;
+    switch (LT) {
+        RSVD_LT_CASE(1) RSVD_LT_CASE(2) RSVD_LT_CASE(3) RSVD_LT_CASE(4) RSVD_LT_CASE(5) RSVD_LT_CASE(6)
+        RSVD_LT_CASE(7) RSVD_LT_CASE(8) RSVD_LT_CASE(9) RSVD_LT_CASE(10) RSVD_LT_CASE(11) RSVD_LT_CASE(12)
+        RSVD_LT_CASE(13) RSVD_LT_CASE(14) RSVD_LT_CASE(15) RSVD_LT_CASE(16) RSVD_LT_CASE(17) RSVD_LT_CASE(18)
+        default: return hipErrorInvalidValue;
+    }
+#undef RSVD_LT_CASE
+    return hipGetLastError();
+}
+
+static int bm_of(int dtype) { return dtype == 0 ? 64 * GemmTile<double>::RT : 64 * GemmTile<float>::RT; }
+static int bk_of(int dtype) { return dtype == 0 ? GemmTile<double>::BK : GemmTile<float>::BK; }
+
+int gemm_row_tiles(int dtype, int64_t M) { return (int)ceil_div(M, bm_of(dtype)); }
+
+// Split count: aim for about two workgroups per CU (256 CUs) with at least
+// eight K tiles per slice; at most 16 slices.
+static int choose_splits(int dtype, int64_t M, int64_t K) {
+    const int tiles = gemm_row_tiles(dtype, M);
+    const int64_t ktiles = ceil_div(K, bk_of(dtype));
+    int s = (int)ceil_div(512, tiles);
+    s = (int)std::min<int64_t>(s, std::max<int64_t>(1, ktiles / 8));
+    s = std::max(1, std::min(s, 16));
+    if (s > 1 && s < 8 && 8 <= ktiles / 8) s = 8;      // one slice per XCD when it fits
+    return s;
+}
+
+size_t gemm_partials_elems(int dtype, int64_t M, int64_t K, int ncols, int* splits_out) {
+    const int s = choose_splits(dtype, M, K);
+    if (splits_out) *splits_out = s;
+    const int L = (int)round_up(ncols, 16);
+    return s > 1 ? (size_t)s * (size_t)M * (size_t)L : 0;
+}
+
+hipError_t launch_gemm(int dtype, GemmArgs a, hipStream_t s) {
+    if (a.ncols < 1 || a.ncols > kMaxL || a.M < 0 || a.K < 0) return hipErrorInvalidValue;
+    if (a.M == 0) return hipSuccess;
+    const int LT = (int)ceil_div(a.ncols, 16);
+    const bool omega = (a.X == nullptr);
+    if (omega && a.trans) return hipErrorInvalidValue;
+    dim3 grid(gemm_row_tiles(dtype, a.M) * a.splits);
+    if (dtype == 0) {
+        if (a.trans) return dispatch_lt<double, true, false>(a, LT, grid, s);
+        return omega ? dispatch_lt<double, false, true>(a, LT, grid, s) : dispatch_lt<double, false, false>(a, LT, grid, s);
+    }
+    if (a.trans) return dispatch_lt<float, true, false>(a, LT, grid, s);
+    return omega ? dispatch_lt<float, false, true>(a, LT, grid, s) : dispatch_lt<float, false, false>(a, LT, grid, s);
+}
+
+// ---- test entry points: Omega materialised, raw Philox words ----
+template <typename T>
+__global__ void omega_kernel(uint64_t seed, uint32_t stream, int64_t n, int64_t l, T* out, int64_t ld) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t groups = ceil_div(n, 4);
+    if (idx >= groups * l) return;
+    const int64_t gidx = idx / l, j = idx % l;
+    T z[4];
+    omega_block<T>(seed, stream, (uint32_t)gidx, (uint32_t)j, z);
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        if (4 * gidx + e < n) out[(4 * gidx + e) * ld + j] = z[e];
+}
+
+hipError_t launch_omega(int dtype, uint64_t seed, uint32_t stream, int64_t n, int64_t l, void* out, int64_t ld,
+                        hipStream_t s) {
+    const int64_t total = ceil_div(n, 4) * l;
+    if (total == 0) return hipSuccess;
+    dim3 grid((unsigned)ceil_div(total, 256));
+    if (dtype == 0) hipLaunchKernelGGL(omega_kernel<double>, grid, dim3(256), 0, s, seed, stream, n, l, (double*)out, ld);
+    else hipLaunchKernelGGL(omega_kernel<float>, grid, dim3(256), 0, s, seed, stream, n, l, (float*)out, ld);
+    return hipGetLastError();
+}
+
+__global__ void philox_words_kernel(uint64_t seed, uint32_t stream, const uint32_t* ctr, int64_t count,
+                                    uint32_t* out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const Philox4 w = philox4x32_10(ctr[2 * i], ctr[2 * i + 1], stream, 0u, (uint32_t)seed, (uint32_t)(seed >> 32));
+#pragma unroll
+    for (int e = 0; e < 4; ++e) out[4 * i + e] = w.x[e];
+}
+
+hipError_t launch_philox_words(uint64_t seed, uint32_t stream, const uint32_t* ctr, int64_t count, uint32_t* out,
+                               hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(philox_words_kernel, dim3((unsigned)ceil_div(count, 256)), dim3(256), 0, s, seed, stream, ctr,
+                       count, out);
+    return hipGetLastError();
+}
+
+}  // namespace rsvd

@@ -1,0 +1,108 @@
+// Internal launcher interface between the host driver and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rsvd {
+
+// Largest padded width L = 16 * LT supported by the product kernels.
+constexpr int kMaxLT = 18;
+constexpr int kMaxL = 16 * kMaxLT;
+
+// Status flags kept in device memory for one orthonormalisation / solve.
+struct DevFlags {
+    int orth_fail;      // CholeskyQR breakdown in the current orth -> Householder
+    int info;           // RSVD_INFO_* bits accumulated over the solve
+    int pad[62];
+};
+
+// ---- skinny products with A (gemm.hip) ----
+struct GemmArgs {
+    const void* A; int64_t lda;
+    int trans;                 // 0: Y = A X (M = rows of A, K = cols); 1: Y = A^T X
+    int64_t M, K;              // output rows, reduction length
+    const void* X; int64_t ldx;  // K x ncols; NULL with trans = 0 -> Omega(seed)
+    uint64_t seed;
+    int ncols;                 // valid columns of X / Y (<= kMaxL)
+    int wcols;                 // columns of Y to write (ncols or L)
+    void* Y; int64_t ldy;
+    void* partials;            // splits * M * L elements (splits > 1)
+    int* counters;             // ceil(M / BM) ints, zero on entry, zero on exit
+    int splits;
+};
+size_t gemm_partials_elems(int dtype, int64_t M, int64_t K, int ncols, int* splits_out);
+int gemm_row_tiles(int dtype, int64_t M);
+hipError_t launch_gemm(int dtype, GemmArgs a, hipStream_t s);
+
+// ---- Gram, Cholesky, apply, Householder (orth.hip) ----
+// G (L x L, double, full symmetric) = Y^T Y for Y rows x L (dtype), ld = ldy.
+// partials: gram_partials_elems doubles; counters: gram_pairs ints.
+size_t gram_partials_elems(int64_t rows, int L);
+int gram_pairs(int L);
+hipError_t launch_gram(int dtype, const void* Y, int64_t ldy, int64_t rows, int L, double* G,
+                       double* partials, int* counters, const DevFlags* skip_if_fail, hipStream_t s);
+
+// Cholesky G = R^T R and R^{-1} for the leading l x l block (single workgroup).
+// mode 0 (orth pass 1): on breakdown set flags->orth_fail = 1 (else 0).
+// mode 1 (orth pass 2): skip if orth_fail; on breakdown set orth_fail = 1.
+// mode 2 (small SVD): on breakdown retry with a diagonal shift, report it in
+//                     info and store the shift in *shift_out.
+// work: L*L doubles of device scratch (used when L is too large for LDS).
+hipError_t launch_chol(const double* G, int l, int L, double* R, double* Rinv, DevFlags* flags, int mode,
+                       double* shift_out, double* work, hipStream_t s);
+
+// out[rows x ncols_out] = in[rows x L] * M[L x ncols_out] with FP64 accumulation.
+// transpose_out: write out^T (ncols_out x rows, ld = ldo).  colscale (nullable):
+// multiply output column c by colscale[c].  skip_if_fail: return at once if
+// flags->orth_fail is set.  argmax (nullable, with transpose_out): per-block
+// index/value of the largest |entry| of each output column.
+hipError_t launch_apply(int dtype, const void* in, int64_t ldi, int64_t rows, int L, const double* M, int ldm,
+                        int ncols_out, void* out, int64_t ldo, int transpose_out, const double* colscale,
+                        const DevFlags* skip_if_fail, double* argmax_val, int* argmax_idx, hipStream_t s);
+int apply_blocks(int64_t rows);
+
+// Householder QR fallback (single workgroup); runs only if flags->orth_fail
+// (or `force`).  H, Qw: rows * L doubles each.  Sets RSVD_INFO_QR_FALLBACK.
+hipError_t launch_householder(int dtype, const void* Y, int64_t ldy, int64_t rows, int l, int L, void* Q,
+                              int64_t ldq, double* H, double* Qw, DevFlags* flags, int force, hipStream_t s);
+
+// ---- small SVD and finishing (svd.hip) ----
+// One-sided Jacobi on X = R^T (l x l, from the Cholesky factor of B B^T).
+// Outputs sigma (sorted descending, shift removed), Ut (L x L, column c =
+// left singular vector c of B, sorted), Mv (L x L: Ut * diag(1/sigma)),
+// perm unused by callers.  work: 2*L*L doubles (global path).
+hipError_t launch_jacobi(const double* R, int l, int L, const double* shift, double* sigma, double* Ut,
+                         double* Mv, DevFlags* flags, double* work, hipStream_t s);
+
+// Reduce the per-block argmax partials of the V columns, choose signs,
+// write S (r values) and sign[c].
+hipError_t launch_signs(const double* argmax_val, const int* argmax_idx, int nblocks, int r,
+                        const double* sigma, double* S_out, double* sign, hipStream_t s);
+
+// Scale the rows of a (rows x cols, ld) matrix of dtype by sign[row].
+hipError_t launch_scale_rows(int dtype, void* X, int64_t ld, int rows, int64_t cols, const double* sign,
+                             hipStream_t s);
+
+// dst (rows x dcols, ldd) = src (rows x cols, lds) padded with zero columns.
+hipError_t launch_copy2d(int dtype, const void* src, int64_t lds, int64_t rows, int cols, void* dst, int64_t ldd,
+                         int dcols, hipStream_t s);
+
+// Zero `count` ints and the flags block.
+hipError_t launch_init(int* counters, int count, DevFlags* flags, hipStream_t s);
+// Copy the flags' info word into the caller's info (OR-ed).
+hipError_t launch_export_info(const DevFlags* flags, int* info, hipStream_t s);
+
+// Omega materialised / raw Philox words (test entry points).
+hipError_t launch_omega(int dtype, uint64_t seed, uint32_t stream, int64_t n, int64_t l, void* out, int64_t ld,
+                        hipStream_t s);
+hipError_t launch_philox_words(uint64_t seed, uint32_t stream, const uint32_t* ctr, int64_t count, uint32_t* out,
+                               hipStream_t s);
+
+// ||A - Q B||_F with B^T = Bt (n x L): fused, FP64 accumulation of squares.
+hipError_t launch_residual_fro(int dtype, const void* A, int64_t lda, int64_t m, int64_t n, const void* Q,
+                               const void* Bt, int l, int L, double* partial, int* counter, double* out,
+                               hipStream_t s);
+size_t residual_partials(int64_t m, int64_t n);
+
+}  // namespace rsvd

@@ -1,0 +1,375 @@
+// Host driver of the C ABI (include/rsvd.h): argument checks, workspace
+// layout and the launch sequence of Algorithm 4 on one HIP stream.
+//
+// A solve is a fixed chain of kernels on the caller's stream; nothing in it
+// synchronises with the host.  Data-dependent choices (the Householder
+// fallback of orth, the shifted Cholesky of the small SVD) are taken on the
+// device through flags in the workspace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <new>
+
+#include "../../include/rsvd.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+using namespace rsvd;
+
+struct rsvd_handle {
+    int device;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t esize(int dtype) { return dtype == RSVD_F64 ? 8 : 4; }
+
+struct Carver {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        const size_t o = off;
+        off += (bytes + kAlign - 1) / kAlign * kAlign;
+        return o;
+    }
+};
+
+// Workspace of one solve (offsets in bytes from the workspace base).
+struct Plan {
+    int dtype = 1;
+    int64_t m = 0, n = 0, k = 0, p = 0, q = 0, l = 0, r = 0;
+    int L = 0;
+    int ncounters = 0;
+    int splits_nn = 1, splits_tn = 1;
+    size_t counters, flags, part, Y, Q, W, Q1, GP, G, R, Rinv, Ut, Mv, sigma, shift, sign, amax_val, amax_idx, H, Qw,
+        work, res_part, res;
+    size_t total;
+};
+
+bool make_plan(int dtype, int64_t m, int64_t n, int64_t k, int64_t p, int64_t q, int full, Plan& P) {
+    P.dtype = dtype;
+    P.m = m; P.n = n; P.k = k; P.p = p; P.q = q;
+    P.l = std::min<int64_t>(k + p, std::min(m, n));
+    P.r = full ? P.l : k;
+    P.L = (int)round_up(P.l, 16);
+    if (P.L > kMaxL) return false;
+    const int64_t mx = std::max(m, n);
+    const size_t es = esize(dtype);
+    const size_t pn = gemm_partials_elems(dtype, m, n, P.L, &P.splits_nn);
+    const size_t pt = gemm_partials_elems(dtype, n, m, P.L, &P.splits_tn);
+    P.ncounters = std::max({gemm_row_tiles(dtype, mx), gram_pairs(P.L), 1});
+    Carver c;
+    P.counters = c.take(sizeof(int) * (size_t)P.ncounters);
+    P.flags = c.take(sizeof(DevFlags));
+    P.part = c.take(es * std::max<size_t>({pn, pt, 1}));
+    P.Y = c.take(es * (size_t)mx * P.L);
+    P.Q = c.take(es * (size_t)m * P.L);
+    P.W = c.take(es * (size_t)n * P.L);
+    P.Q1 = c.take(es * (size_t)mx * P.L);
+    P.GP = c.take(sizeof(double) * gram_partials_elems(mx, P.L));
+    P.G = c.take(sizeof(double) * (size_t)P.L * P.L);
+    P.R = c.take(sizeof(double) * (size_t)P.L * P.L);
+    P.Rinv = c.take(sizeof(double) * (size_t)P.L * P.L);
+    P.Ut = c.take(sizeof(double) * (size_t)P.L * P.L);
+    P.Mv = c.take(sizeof(double) * (size_t)P.L * P.L);
+    P.sigma = c.take(sizeof(double) * (size_t)P.L);
+    P.shift = c.take(sizeof(double));
+    P.sign = c.take(sizeof(double) * (size_t)P.L);
+    P.amax_val = c.take(sizeof(double) * (size_t)apply_blocks(n) * P.L);
+    P.amax_idx = c.take(sizeof(int) * (size_t)apply_blocks(n) * P.L);
+    P.H = c.take(sizeof(double) * (size_t)mx * P.L);
+    P.Qw = c.take(sizeof(double) * (size_t)mx * P.L);
+    P.work = c.take(sizeof(double) * (size_t)P.L * P.L);
+    P.res_part = c.take(sizeof(double) * residual_partials(m, n));
+    P.res = c.take(sizeof(double) * 2);
+    P.total = c.off;
+    return true;
+}
+
+template <typename T>
+T* at(void* base, size_t off) {
+    return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+#define RSVD_TRY(expr)                                     \
+    do {                                                   \
+        hipError_t e_ = (expr);                            \
+        if (e_ != hipSuccess) return RSVD_ERR_DEVICE;      \
+    } while (0)
+
+// orth(Y) -> Q for an internal rows x L buffer (ld = L, zero padding).
+rsvd_status run_orth(const Plan& P, void* ws, int dtype, int64_t rows, const void* Y, void* Qout, int force_hh,
+                     hipStream_t s) {
+    const int L = P.L, l = (int)P.l;
+    DevFlags* flags = at<DevFlags>(ws, P.flags);
+    int* cnt = at<int>(ws, P.counters);
+    double* G = at<double>(ws, P.G);
+    double* R = at<double>(ws, P.R);
+    double* Rinv = at<double>(ws, P.Rinv);
+    double* GP = at<double>(ws, P.GP);
+    double* work = at<double>(ws, P.work);
+    void* Q1 = at<char>(ws, P.Q1);
+    if (!force_hh) {
+        RSVD_TRY(launch_gram(dtype, Y, L, rows, L, G, GP, cnt, nullptr, s));
+        RSVD_TRY(launch_chol(G, l, L, R, Rinv, flags, 0, nullptr, work, s));
+        RSVD_TRY(launch_apply(dtype, Y, L, rows, L, Rinv, L, L, Q1, L, 0, nullptr, flags, nullptr, nullptr, s));
+        RSVD_TRY(launch_gram(dtype, Q1, L, rows, L, G, GP, cnt, flags, s));
+        RSVD_TRY(launch_chol(G, l, L, R, Rinv, flags, 1, nullptr, work, s));
+        RSVD_TRY(launch_apply(dtype, Q1, L, rows, L, Rinv, L, L, Qout, L, 0, nullptr, flags, nullptr, nullptr, s));
+    }
+    RSVD_TRY(launch_householder(dtype, Y, L, rows, l, L, Qout, L, at<double>(ws, P.H), at<double>(ws, P.Qw), flags,
+                                force_hh, s));
+    return RSVD_OK;
+}
+
+rsvd_status run_gemm(const Plan& P, void* ws, const rsvd_matrix* A, int trans, const void* X, uint64_t seed,
+                     void* Yout, hipStream_t s) {
+    GemmArgs g{};
+    g.A = A->data;
+    g.lda = A->ld;
+    g.trans = trans;
+    g.M = trans ? A->cols : A->rows;
+    g.K = trans ? A->rows : A->cols;
+    g.X = X;
+    g.ldx = P.L;
+    g.seed = seed;
+    g.ncols = trans ? P.L : (X ? P.L : (int)P.l);
+    g.wcols = P.L;
+    g.Y = Yout;
+    g.ldy = P.L;
+    g.partials = at<char>(ws, P.part);
+    g.counters = at<int>(ws, P.counters);
+    g.splits = trans ? P.splits_tn : P.splits_nn;
+    RSVD_TRY(launch_gemm(P.dtype, g, s));
+    return RSVD_OK;
+}
+
+rsvd_status check_matrix(const rsvd_matrix* A) {
+    if (!A || !A->data) return RSVD_ERR_INVALID_ARG;
+    if (A->dtype != RSVD_F32 && A->dtype != RSVD_F64) return RSVD_ERR_INVALID_ARG;
+    if (A->rows < 1 || A->cols < 1 || A->ld < A->cols) return RSVD_ERR_INVALID_ARG;
+    if (A->rows > (int64_t)1 << 31 || A->cols > (int64_t)1 << 31) return RSVD_ERR_UNSUPPORTED;
+    return RSVD_OK;
+}
+
+rsvd_status check_params(const rsvd_matrix* A, const rsvd_params* p) {
+    if (!p) return RSVD_ERR_INVALID_ARG;
+    const int64_t mn = std::min(A->rows, A->cols);
+    if (p->k < 1 || p->k > mn || p->p < 0 || p->q < 0 || p->q > 64) return RSVD_ERR_INVALID_ARG;
+    if (p->residual != 0 && p->residual != 2) return RSVD_ERR_INVALID_ARG;
+    if (round_up(std::min<int64_t>(p->k + p->p, mn), 16) > kMaxL) return RSVD_ERR_UNSUPPORTED;
+    return RSVD_OK;
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" {
+
+const char* rsvd_status_string(rsvd_status s) {
+    switch (s) {
+        case RSVD_OK: return "ok";
+        case RSVD_ERR_INVALID_ARG: return "invalid argument";
+        case RSVD_ERR_UNSUPPORTED: return "unsupported request";
+        case RSVD_ERR_NO_MEMORY: return "out of memory";
+        case RSVD_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+        case RSVD_ERR_DEVICE: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+int64_t rsvd_l_used(int64_t m, int64_t n, int64_t k, int64_t p) { return std::min(k + p, std::min(m, n)); }
+
+rsvd_status rsvd_create(rsvd_handle** out, int device) {
+    if (!out) return RSVD_ERR_INVALID_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess) return RSVD_ERR_DEVICE;
+    if (device < 0 || device >= count) return RSVD_ERR_INVALID_ARG;
+    rsvd_handle* h = new (std::nothrow) rsvd_handle;
+    if (!h) return RSVD_ERR_NO_MEMORY;
+    h->device = device;
+    *out = h;
+    return RSVD_OK;
+}
+
+rsvd_status rsvd_destroy(rsvd_handle* h) {
+    delete h;
+    return RSVD_OK;
+}
+
+rsvd_status rsvd_workspace_size(const rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* params,
+                                size_t* bytes) {
+    (void)h;
+    if (!bytes) return RSVD_ERR_INVALID_ARG;
+    rsvd_status st = check_matrix(A);
+    if (st != RSVD_OK) return st;
+    if ((st = check_params(A, params)) != RSVD_OK) return st;
+    Plan P;
+    if (!make_plan(A->dtype, A->rows, A->cols, params->k, params->p, params->q, params->return_full_l, P))
+        return RSVD_ERR_UNSUPPORTED;
+    *bytes = P.total;
+    return RSVD_OK;
+}
+
+rsvd_status rsvd_solve(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* params, const rsvd_result* out,
+                       void* ws, size_t ws_bytes, void* stream) {
+    if (!h || !out) return RSVD_ERR_INVALID_ARG;
+    rsvd_status st = check_matrix(A);
+    if (st != RSVD_OK) return st;
+    if ((st = check_params(A, params)) != RSVD_OK) return st;
+    Plan P;
+    if (!make_plan(A->dtype, A->rows, A->cols, params->k, params->p, params->q, params->return_full_l, P))
+        return RSVD_ERR_UNSUPPORTED;
+    if (!out->U || !out->S || !out->Vt || !out->info) return RSVD_ERR_INVALID_ARG;
+    if (out->ldu < P.r || out->ldvt < P.n) return RSVD_ERR_INVALID_ARG;
+    if (out->Q && out->ldq < P.l) return RSVD_ERR_INVALID_ARG;
+    if (params->residual && !out->residual) return RSVD_ERR_INVALID_ARG;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return RSVD_ERR_INVALID_ARG;
+    if (ws_bytes < P.total) return RSVD_ERR_WORKSPACE_TOO_SMALL;
+    if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_DEVICE;
+
+    hipStream_t s = as_stream(stream);
+    const int dt = A->dtype;
+    const int L = P.L;
+    DevFlags* flags = at<DevFlags>(ws, P.flags);
+    int* cnt = at<int>(ws, P.counters);
+    void* Y = at<char>(ws, P.Y);
+    void* Q = at<char>(ws, P.Q);
+    void* W = at<char>(ws, P.W);
+    const int hh = params->force_householder;
+
+    RSVD_TRY(launch_init(cnt, P.ncounters, flags, s));
+    // Stage 1: steps 1-3, sketch with the generated test matrix, then orth.
+    if ((st = run_gemm(P, ws, A, 0, nullptr, params->seed, Y, s)) != RSVD_OK) return st;
+    if ((st = run_orth(P, ws, dt, P.m, Y, Q, hh, s)) != RSVD_OK) return st;
+    // Steps 4-5: q power iterations, each product re-orthonormalised.
+    for (int64_t t = 0; t < P.q; ++t) {
+        if ((st = run_gemm(P, ws, A, 1, Q, 0, Y, s)) != RSVD_OK) return st;
+        if ((st = run_orth(P, ws, dt, P.n, Y, W, hh, s)) != RSVD_OK) return st;
+        if ((st = run_gemm(P, ws, A, 0, W, 0, Y, s)) != RSVD_OK) return st;
+        if ((st = run_orth(P, ws, dt, P.m, Y, Q, hh, s)) != RSVD_OK) return st;
+    }
+    // Stage 2: step 6 as B^T = A^T Q (n x l), step 7 small SVD, step 8 lift.
+    if ((st = run_gemm(P, ws, A, 1, Q, 0, Y, s)) != RSVD_OK) return st;
+    const void* Bt = Y;
+    double* G = at<double>(ws, P.G);
+    double* R = at<double>(ws, P.R);
+    double* sigma = at<double>(ws, P.sigma);
+    double* sign = at<double>(ws, P.sign);
+    double* Ut = at<double>(ws, P.Ut);
+    double* Mv = at<double>(ws, P.Mv);
+    double* shift = at<double>(ws, P.shift);
+    double* av = at<double>(ws, P.amax_val);
+    int* ai = at<int>(ws, P.amax_idx);
+    const int r = (int)P.r;
+    RSVD_TRY(launch_gram(dt, Bt, L, P.n, L, G, at<double>(ws, P.GP), cnt, nullptr, s));
+    RSVD_TRY(launch_chol(G, (int)P.l, L, R, at<double>(ws, P.Rinv), flags, 2, shift, at<double>(ws, P.work), s));
+    RSVD_TRY(launch_jacobi(R, (int)P.l, L, shift, sigma, Ut, Mv, flags, at<double>(ws, P.work), s));
+    // V = B^T U~ Sigma^{-1}, written transposed into Vt, with column argmax partials.
+    RSVD_TRY(launch_apply(dt, Bt, L, P.n, L, Mv, L, r, out->Vt, out->ldvt, 1, nullptr, nullptr, av, ai, s));
+    RSVD_TRY(launch_signs(av, ai, apply_blocks(P.n), r, sigma, out->S, sign, s));
+    // U = Q U~ (top r columns), signs folded in; then the signs of Vt's rows.
+    RSVD_TRY(launch_apply(dt, Q, L, P.m, L, Ut, L, r, out->U, out->ldu, 0, sign, nullptr, nullptr, nullptr, s));
+    RSVD_TRY(launch_scale_rows(dt, out->Vt, out->ldvt, r, P.n, sign, s));
+    if (out->Q) RSVD_TRY(launch_copy2d(dt, Q, L, P.m, (int)P.l, out->Q, out->ldq, (int)P.l, s));
+    if (params->residual == 2)
+        RSVD_TRY(launch_residual_fro(dt, A->data, A->ld, P.m, P.n, Q, Bt, (int)P.l, L, at<double>(ws, P.res_part), cnt,
+                                     out->residual, s));
+    RSVD_TRY(launch_export_info(flags, out->info, s));
+    return RSVD_OK;
+}
+
+rsvd_status rsvd_omega(int32_t dtype, uint64_t seed, uint32_t stream_id, int64_t n, int64_t l, void* out, int64_t ld,
+                       void* stream) {
+    if (dtype != RSVD_F32 && dtype != RSVD_F64) return RSVD_ERR_INVALID_ARG;
+    if (n < 0 || l < 0 || (n * l > 0 && (!out || ld < l)) || n > ((int64_t)1 << 33)) return RSVD_ERR_INVALID_ARG;
+    RSVD_TRY(launch_omega(dtype, seed, stream_id, n, l, out, ld, as_stream(stream)));
+    return RSVD_OK;
+}
+
+rsvd_status rsvd_philox_words(uint64_t seed, uint32_t stream_id, const uint32_t* ctr, int64_t count, uint32_t* out,
+                              void* stream) {
+    if (count < 0 || (count > 0 && (!ctr || !out))) return RSVD_ERR_INVALID_ARG;
+    RSVD_TRY(launch_philox_words(seed, stream_id, ctr, count, out, as_stream(stream)));
+    return RSVD_OK;
+}
+
+rsvd_status rsvd_gemm_workspace_size(const rsvd_matrix* A, int32_t trans, int64_t ncols, size_t* bytes) {
+    rsvd_status st = check_matrix(A);
+    if (st != RSVD_OK) return st;
+    if (!bytes || ncols < 1 || ncols > kMaxL) return RSVD_ERR_INVALID_ARG;
+    const int64_t M = trans ? A->cols : A->rows, K = trans ? A->rows : A->cols;
+    Carver c;
+    c.take(sizeof(int) * (size_t)gemm_row_tiles(A->dtype, M));
+    c.take(sizeof(DevFlags));
+    c.take(esize(A->dtype) * std::max<size_t>(1, gemm_partials_elems(A->dtype, M, K, (int)ncols, nullptr)));
+    *bytes = c.off;
+    return RSVD_OK;
+}
+
+rsvd_status rsvd_gemm(rsvd_handle* h, const rsvd_matrix* A, int32_t trans, const void* X, int64_t ldx, uint64_t seed,
+                      int64_t ncols, void* Y, int64_t ldy, void* ws, size_t ws_bytes, void* stream) {
+    if (!h) return RSVD_ERR_INVALID_ARG;
+    size_t need = 0;
+    rsvd_status st = rsvd_gemm_workspace_size(A, trans, ncols, &need);
+    if (st != RSVD_OK) return st;
+    if (trans && !X) return RSVD_ERR_INVALID_ARG;
+    if (X && ldx < ncols) return RSVD_ERR_INVALID_ARG;
+    if (!Y || ldy < ncols) return RSVD_ERR_INVALID_ARG;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return RSVD_ERR_INVALID_ARG;
+    if (ws_bytes < need) return RSVD_ERR_WORKSPACE_TOO_SMALL;
+    if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_DEVICE;
+    hipStream_t s = as_stream(stream);
+    const int64_t M = trans ? A->cols : A->rows, K = trans ? A->rows : A->cols;
+    Carver c;
+    const size_t o_cnt = c.take(sizeof(int) * (size_t)gemm_row_tiles(A->dtype, M));
+    const size_t o_flags = c.take(sizeof(DevFlags));
+    const size_t o_part = c.take(0);
+    int splits = 1;
+    gemm_partials_elems(A->dtype, M, K, (int)ncols, &splits);
+    RSVD_TRY(launch_init(at<int>(ws, o_cnt), gemm_row_tiles(A->dtype, M), at<DevFlags>(ws, o_flags), s));
+    GemmArgs g{};
+    g.A = A->data; g.lda = A->ld; g.trans = trans; g.M = M; g.K = K;
+    g.X = X; g.ldx = ldx; g.seed = seed; g.ncols = (int)ncols; g.wcols = (int)ncols;
+    g.Y = Y; g.ldy = ldy; g.partials = at<char>(ws, o_part); g.counters = at<int>(ws, o_cnt); g.splits = splits;
+    RSVD_TRY(launch_gemm(A->dtype, g, s));
+    return RSVD_OK;
+}
+
+rsvd_status rsvd_orth_workspace_size(int32_t dtype, int64_t rows, int64_t l, size_t* bytes) {
+    if (!bytes || (dtype != RSVD_F32 && dtype != RSVD_F64) || l < 1 || rows < l) return RSVD_ERR_INVALID_ARG;
+    Plan P;
+    if (!make_plan(dtype, rows, l, l, 0, 0, 0, P)) return RSVD_ERR_UNSUPPORTED;
+    *bytes = P.total;
+    return RSVD_OK;
+}
+
+rsvd_status rsvd_orth(rsvd_handle* h, int32_t dtype, int64_t rows, int64_t l, const void* Y, int64_t ldy, void* Qo,
+                      int64_t ldq, int32_t force_householder, int32_t* info, void* ws, size_t ws_bytes, void* stream) {
+    if (!h || !Y || !Qo || !info || ldy < l || ldq < l) return RSVD_ERR_INVALID_ARG;
+    size_t need = 0;
+    rsvd_status st = rsvd_orth_workspace_size(dtype, rows, l, &need);
+    if (st != RSVD_OK) return st;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return RSVD_ERR_INVALID_ARG;
+    if (ws_bytes < need) return RSVD_ERR_WORKSPACE_TOO_SMALL;
+    if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_DEVICE;
+    Plan P;
+    make_plan(dtype, rows, l, l, 0, 0, 0, P);
+    hipStream_t s = as_stream(stream);
+    DevFlags* flags = at<DevFlags>(ws, P.flags);
+    RSVD_TRY(launch_init(at<int>(ws, P.counters), P.ncounters, flags, s));
+    void* Yi = at<char>(ws, P.Y);
+    void* Qi = at<char>(ws, P.Q);
+    RSVD_TRY(launch_copy2d(dtype, Y, ldy, rows, (int)l, Yi, P.L, P.L, s));
+    if ((st = run_orth(P, ws, dtype, rows, Yi, Qi, force_householder, s)) != RSVD_OK) return st;
+    RSVD_TRY(launch_copy2d(dtype, Qi, P.L, rows, (int)l, Qo, ldq, (int)l, s));
+    RSVD_TRY(launch_export_info(flags, info, s));
+    return RSVD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,245 @@
+"""Thin Python binding of librsvd.so (ctypes).
+
+Argument marshalling only: torch tensors provide device memory and the
+stream; every step of the computation runs in the library's HIP kernels.
+The names follow the C ABI in include/rsvd.h.  There is no fallback: if the
+library is missing or a call fails, an exception is raised.
+"""
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "librsvd.so")
+
+RSVD_F64, RSVD_F32 = 0, 1
+INFO_QR_FALLBACK = 1
+INFO_SHIFTED_CHOLESKY = 2
+INFO_JACOBI_NOT_CONVERGED = 4
+INFO_NONFINITE = 8
+
+_DTYPES = {torch.float64: RSVD_F64, torch.float32: RSVD_F32}
+
+
+class rsvd_matrix(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("rows", ctypes.c_int64), ("cols", ctypes.c_int64), ("ld", ctypes.c_int64)]
+
+
+class rsvd_params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int64), ("p", ctypes.c_int64), ("q", ctypes.c_int64), ("seed", ctypes.c_uint64),
+                ("residual", ctypes.c_int32), ("return_full_l", ctypes.c_int32),
+                ("force_householder", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
+
+
+class rsvd_result(ctypes.Structure):
+    _fields_ = [("U", ctypes.c_void_p), ("ldu", ctypes.c_int64), ("S", ctypes.c_void_p),
+                ("Vt", ctypes.c_void_p), ("ldvt", ctypes.c_int64), ("residual", ctypes.c_void_p),
+                ("info", ctypes.c_void_p), ("Q", ctypes.c_void_p), ("ldq", ctypes.c_int64)]
+
+
+EXPORTS = ["rsvd_create", "rsvd_destroy", "rsvd_l_used", "rsvd_workspace_size", "rsvd_solve",
+           "rsvd_status_string", "rsvd_omega", "rsvd_philox_words", "rsvd_gemm_workspace_size", "rsvd_gemm",
+           "rsvd_orth_workspace_size", "rsvd_orth"]
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load librsvd.so and declare the C signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2402_17794_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, I64, I32, U64, SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_size_t
+    sig = {
+        "rsvd_create": ([ctypes.POINTER(P), ctypes.c_int], I32),
+        "rsvd_destroy": ([P], I32),
+        "rsvd_l_used": ([I64, I64, I64, I64], I64),
+        "rsvd_workspace_size": ([P, ctypes.POINTER(rsvd_matrix), ctypes.POINTER(rsvd_params), ctypes.POINTER(SZ)],
+                                I32),
+        "rsvd_solve": ([P, ctypes.POINTER(rsvd_matrix), ctypes.POINTER(rsvd_params), ctypes.POINTER(rsvd_result),
+                        P, SZ, P], I32),
+        "rsvd_status_string": ([I32], ctypes.c_char_p),
+        "rsvd_omega": ([I32, U64, ctypes.c_uint32, I64, I64, P, I64, P], I32),
+        "rsvd_philox_words": ([U64, ctypes.c_uint32, P, I64, P, P], I32),
+        "rsvd_gemm_workspace_size": ([ctypes.POINTER(rsvd_matrix), I32, I64, ctypes.POINTER(SZ)], I32),
+        "rsvd_gemm": ([P, ctypes.POINTER(rsvd_matrix), I32, P, I64, U64, I64, P, I64, P, SZ, P], I32),
+        "rsvd_orth_workspace_size": ([I32, I64, I64, ctypes.POINTER(SZ)], I32),
+        "rsvd_orth": ([P, I32, I64, I64, P, I64, P, I64, I32, P, P, SZ, P], I32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    if path == LIB_PATH:
+        _lib = lib
+    return lib
+
+
+class RsvdError(RuntimeError):
+    pass
+
+
+def _check(status):
+    if status != 0:
+        msg = load_library().rsvd_status_string(status).decode()
+        raise RsvdError(f"librsvd: {msg} (status {status})")
+
+
+_handles = {}
+
+
+def _handle(device):
+    idx = torch.device(device).index
+    idx = torch.cuda.current_device() if idx is None else idx
+    if idx not in _handles:
+        h = ctypes.c_void_p()
+        _check(load_library().rsvd_create(ctypes.byref(h), idx))
+        _handles[idx] = h
+    return _handles[idx]
+
+
+def _stream_ptr(stream, device):
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _as_matrix(A):
+    if A.dim() != 2 or not A.is_cuda or A.dtype not in _DTYPES:
+        raise ValueError("A must be a 2-D float32/float64 CUDA tensor")
+    if A.stride(1) != 1:
+        raise ValueError("A must be row-major (stride(1) == 1)")
+    return rsvd_matrix(A.data_ptr(), _DTYPES[A.dtype], 0, A.shape[0], A.shape[1], max(A.stride(0), A.shape[1]))
+
+
+def _workspace(nbytes, device):
+    # 256-byte alignment: torch's caching allocator returns 512-byte aligned blocks.
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def l_used(m, n, k, p):
+    return int(load_library().rsvd_l_used(m, n, k, p))
+
+
+def workspace_size(A, k, p=10, q=0, return_full_l=False):
+    lib = load_library()
+    M = _as_matrix(A)
+    prm = rsvd_params(k, p, q, 0, 0, int(return_full_l), 0, 0)
+    nb = ctypes.c_size_t()
+    _check(lib.rsvd_workspace_size(_handle(A.device), ctypes.byref(M), ctypes.byref(prm), ctypes.byref(nb)))
+    return nb.value
+
+
+class Solver:
+    """Reusable solve for one (shape, dtype, k, p, q): owns the output tensors
+    and the workspace, so repeated calls allocate nothing."""
+
+    def __init__(self, A, k, p=10, q=0, seed=0, residual=False, return_full_l=False, force_householder=False,
+                 return_q=False, stream=None):
+        self.lib = load_library()
+        self.A = A
+        self.M = _as_matrix(A)
+        m, n = A.shape
+        self.l = l_used(m, n, k, p)
+        r = self.l if return_full_l else k
+        dev = A.device
+        self.params = rsvd_params(k, p, q, seed, 2 if residual else 0, int(return_full_l), int(force_householder), 0)
+        self.U = torch.empty((m, r), dtype=A.dtype, device=dev)
+        self.S = torch.empty((r,), dtype=torch.float64, device=dev)
+        self.Vt = torch.empty((r, n), dtype=A.dtype, device=dev)
+        self.info = torch.zeros((1,), dtype=torch.int32, device=dev)
+        self.res = torch.zeros((2,), dtype=torch.float64, device=dev) if residual else None
+        self.Q = torch.empty((m, self.l), dtype=A.dtype, device=dev) if return_q else None
+        nb = ctypes.c_size_t()
+        self.h = _handle(dev)
+        _check(self.lib.rsvd_workspace_size(self.h, ctypes.byref(self.M), ctypes.byref(self.params),
+                                            ctypes.byref(nb)))
+        self.ws = _workspace(nb.value, dev)
+        self.result = rsvd_result(self.U.data_ptr(), r, self.S.data_ptr(), self.Vt.data_ptr(), n,
+                                  self.res.data_ptr() if residual else None, self.info.data_ptr(),
+                                  self.Q.data_ptr() if return_q else None, self.l)
+        self.stream = stream
+
+    def set_seed(self, seed):
+        self.params.seed = seed
+
+    def __call__(self):
+        _check(self.lib.rsvd_solve(self.h, ctypes.byref(self.M), ctypes.byref(self.params), ctypes.byref(self.result),
+                                   ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                   _stream_ptr(self.stream, self.A.device)))
+        return self
+
+
+def solve(A, k, p=10, q=0, seed=0, residual=False, return_full_l=False, force_householder=False, return_q=False,
+          stream=None):
+    """Randomized SVD (Algorithm 4) of a CUDA tensor A.  Returns a dict with
+    U (m x r), S (r, float64), Vt (r x n), info (int), l, and optionally
+    residual (||A - QQ^T A||_F) and Q (m x l)."""
+    s = Solver(A, k, p, q, seed, residual, return_full_l, force_householder, return_q, stream)()
+    out = dict(U=s.U, S=s.S, Vt=s.Vt, l=s.l, info_tensor=s.info)
+    if residual:
+        out["residual_t"] = s.res
+    if return_q:
+        out["Q"] = s.Q
+    return out
+
+
+def omega(n, l, seed, dtype=torch.float32, stream_id=0, device="cuda"):
+    """The test matrix of Algorithm 4 step 1, materialised on the device."""
+    out = torch.empty((n, l), dtype=dtype, device=device)
+    _check(load_library().rsvd_omega(_DTYPES[dtype], seed, stream_id, n, l, ctypes.c_void_p(out.data_ptr()), l,
+                                     _stream_ptr(None, out.device)))
+    return out
+
+
+def philox_words(seed, ctr, stream_id=0):
+    """Raw Philox4x32-10 words for an (N, 2) int32 tensor of (g, j) counters."""
+    ctr = ctr.contiguous()
+    out = torch.empty((ctr.shape[0], 4), dtype=torch.int32, device=ctr.device)
+    _check(load_library().rsvd_philox_words(seed, stream_id, ctypes.c_void_p(ctr.data_ptr()), ctr.shape[0],
+                                            ctypes.c_void_p(out.data_ptr()), _stream_ptr(None, ctr.device)))
+    return out
+
+
+def gemm(A, X=None, trans=False, seed=0, ncols=None):
+    """Y = A X (trans False) or A^T X (trans True) with the solve's MFMA
+    kernels; X None (trans False) means the generated test matrix."""
+    lib = load_library()
+    M = _as_matrix(A)
+    if X is not None:
+        if X.dtype != A.dtype or X.stride(1) != 1:
+            raise ValueError("X must match A's dtype and be row-major")
+        ncols = X.shape[1]
+    rows = A.shape[1] if trans else A.shape[0]
+    nb = ctypes.c_size_t()
+    _check(lib.rsvd_gemm_workspace_size(ctypes.byref(M), int(trans), ncols, ctypes.byref(nb)))
+    ws = _workspace(nb.value, A.device)
+    Y = torch.empty((rows, ncols), dtype=A.dtype, device=A.device)
+    _check(lib.rsvd_gemm(_handle(A.device), ctypes.byref(M), int(trans),
+                         ctypes.c_void_p(X.data_ptr()) if X is not None else None,
+                         X.stride(0) if X is not None else 0, seed, ncols, ctypes.c_void_p(Y.data_ptr()), ncols,
+                         ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(None, A.device)))
+    return Y
+
+
+def orth(Y, force_householder=False):
+    """Orthonormal basis of range(Y) (CholeskyQR2 with Householder fallback).
+    Returns (Q, info)."""
+    lib = load_library()
+    if Y.dtype not in _DTYPES or Y.stride(1) != 1:
+        raise ValueError("Y must be a row-major float32/float64 CUDA tensor")
+    rows, l = Y.shape
+    nb = ctypes.c_size_t()
+    _check(lib.rsvd_orth_workspace_size(_DTYPES[Y.dtype], rows, l, ctypes.byref(nb)))
+    ws = _workspace(nb.value, Y.device)
+    Q = torch.empty_like(Y)
+    info = torch.zeros((1,), dtype=torch.int32, device=Y.device)
+    _check(lib.rsvd_orth(_handle(Y.device), _DTYPES[Y.dtype], rows, l, ctypes.c_void_p(Y.data_ptr()), Y.stride(0),
+                         ctypes.c_void_p(Q.data_ptr()), l, int(force_householder), ctypes.c_void_p(info.data_ptr()),
+                         ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(None, Y.device)))
+    return Q, info

@@ -1,0 +1,58 @@
+"""The C-ABI library loads on the CPU and exports every function that
+include/rsvd.h declares; host-only entry points (sizes, validation, status
+strings) answer without a GPU."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rsvd.h")
+LIB = os.path.join(ROOT, "paper_2402_17794_amd", "librsvd.so")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rsvd_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("librsvd.so not built: run `python -m paper_2402_17794_amd.build`")
+    from paper_2402_17794_amd import rsvd
+    return rsvd.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared_functions()
+    assert "rsvd_solve" in names and "rsvd_create" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    from paper_2402_17794_amd import rsvd
+    assert set(rsvd.EXPORTS) == set(names)
+
+
+def test_host_only_entry_points(lib):
+    from paper_2402_17794_amd import rsvd
+    assert lib.rsvd_l_used(512, 256, 20, 10) == 30
+    assert lib.rsvd_l_used(804, 1092, 800, 10) == 804
+    assert lib.rsvd_status_string(0) == b"ok"
+    assert lib.rsvd_status_string(4) == b"workspace too small"
+    A = rsvd.rsvd_matrix(0x1000, rsvd.RSVD_F32, 0, 8192, 8192, 8192)
+    nb = ctypes.c_size_t()
+    good = rsvd.rsvd_params(100, 10, 2, 0, 0, 0, 0, 0)
+    assert lib.rsvd_workspace_size(None, ctypes.byref(A), ctypes.byref(good), ctypes.byref(nb)) == 0
+    assert nb.value > 8192 * 112 * 4 * 3
+    for k, p, q in [(0, 10, 0), (8193, 0, 0), (10, -1, 0), (10, 5, -2)]:
+        bad = rsvd.rsvd_params(k, p, q, 0, 0, 0, 0, 0)
+        assert lib.rsvd_workspace_size(None, ctypes.byref(A), ctypes.byref(bad), ctypes.byref(nb)) == 1
+    wide = rsvd.rsvd_params(400, 10, 0, 0, 0, 0, 0, 0)          # l = 410 > 288
+    assert lib.rsvd_workspace_size(None, ctypes.byref(A), ctypes.byref(wide), ctypes.byref(nb)) == 2
+    badld = rsvd.rsvd_matrix(0x1000, rsvd.RSVD_F32, 0, 10, 20, 19)
+    assert lib.rsvd_workspace_size(None, ctypes.byref(badld), ctypes.byref(good), ctypes.byref(nb)) == 1
+    # solve with a NULL handle is rejected before any device work
+    assert lib.rsvd_solve(None, ctypes.byref(A), ctypes.byref(good), None, None, 0, None) == 1

@@ -1,0 +1,141 @@
+"""Parity of each GPU step with the FP64 oracle, through the C ABI.
+
+Tolerances are derived from the arithmetic:
+* Philox words: bit-exact (integer work).
+* Omega: the GPU evaluates log/sqrt/sincospi in the working precision; the
+  FP32 result is within a few ulp of the FP64 value (bound used:
+  2^-20 (|z| + 1)); the FP64 result within 1e-14 (|z| + 1).
+* Products with A: any summation order satisfies |Y - Y*| <= K u |A||X|
+  (u = 2^-24 for FP32 accumulation, 2^-53 for FP64), K the reduction length.
+* orth: for well-conditioned full-rank Y the Q factor with positive
+  diagonal is unique, so the GPU's Q matches the oracle's Householder Q to
+  O(kappa(Y) u) elementwise; Q^T Q = I to O(u) in the storage precision.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle.linalg as OL
+from oracle import philox as OP
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2402_17794_amd import rsvd
+    rsvd.load_library()
+    return rsvd
+
+
+def _cuda(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 0xDEADBEEFCAFEF00D])
+def test_philox_words_bit_exact(R, seed):
+    rng = np.random.default_rng(7)
+    ctr = np.concatenate([rng.integers(0, 2 ** 32, size=(500, 2), dtype=np.uint64),
+                          np.array([[0, 0], [0xFFFFFFFF, 0xFFFFFFFF], [1, 2]], dtype=np.uint64)])
+    for stream in (0, 2):
+        gpu = R.philox_words(seed, torch.from_numpy(ctr.astype(np.uint32).view(np.int32)).cuda(), stream)
+        got = gpu.cpu().numpy().view(np.uint32)
+        ref = OP.philox_words(seed, ctr, stream)
+        assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("n,l,seed", [(1, 1, 0), (37, 9, 7), (8192, 110, 0), (1001, 272, 5)])
+def test_omega_matches_oracle(R, n, l, seed):
+    ref = OP.omega(seed, n, l)
+    g32 = R.omega(n, l, seed, torch.float32).cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(g32 - ref) <= 2.0 ** -20 * (np.abs(ref) + 1.0))
+    g64 = R.omega(n, l, seed, torch.float64).cpu().numpy()
+    assert np.all(np.abs(g64 - ref) <= 1e-14 * (np.abs(ref) + 1.0))
+
+
+def _bound(A, X, K, dtype):
+    u = 2.0 ** -24 if dtype == torch.float32 else 2.0 ** -53
+    return K * u * (np.abs(A) @ np.abs(X)) + 1e-300
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("m,n,nc", [(1000, 777, 30), (333, 4099, 110), (130, 129, 1), (4096, 2048, 288),
+                                    (64, 64, 16), (8192, 8192, 112)])
+def test_products_with_A(R, dtype, m, n, nc):
+    rng = np.random.default_rng(m * 7 + n + nc)
+    A = rng.standard_normal((m, n))
+    if dtype == torch.float32:
+        A = A.astype(np.float32).astype(np.float64)
+    Ad = _cuda(A, dtype)
+    # Y = A X
+    X = rng.standard_normal((n, nc))
+    if dtype == torch.float32:
+        X = X.astype(np.float32).astype(np.float64)
+    Y = R.gemm(Ad, _cuda(X, dtype)).cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(Y - A @ X) <= _bound(A, X, n, dtype))
+    # Z = A^T W
+    Wm = rng.standard_normal((m, nc))
+    if dtype == torch.float32:
+        Wm = Wm.astype(np.float32).astype(np.float64)
+    Z = R.gemm(Ad, _cuda(Wm, dtype), trans=True).cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(Z - A.T @ Wm) <= _bound(A.T, Wm, m, dtype))
+    # sketch with the generated Omega (FP32 Omega differs from FP64 by <= 2^-20 (|z|+1))
+    Om = OP.omega(3, n, nc)
+    S = R.gemm(Ad, None, seed=3, ncols=nc).cpu().numpy().astype(np.float64)
+    eps_om = 2.0 ** -20 if dtype == torch.float32 else 1e-14
+    tol = _bound(A, np.abs(Om) + 1.0, n, dtype) + eps_om * (np.abs(A) @ (np.abs(Om) + 1.0))
+    assert np.all(np.abs(S - A @ Om) <= tol)
+
+
+def test_products_strided_and_unaligned(R):
+    rng = np.random.default_rng(3)
+    big = torch.from_numpy(rng.standard_normal((300, 203)).astype(np.float32)).cuda()
+    A = big[:, 1:200]                                   # ld 203, misaligned start
+    X = rng.standard_normal((199, 17)).astype(np.float32)
+    Y = R.gemm(A, _cuda(X, torch.float32)).cpu().numpy().astype(np.float64)
+    An = A.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(Y - An @ X) <= _bound(An, X.astype(np.float64), 199, torch.float32))
+
+
+def _orth_err(Q):
+    return np.max(np.abs(Q.T @ Q - np.eye(Q.shape[1])))
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("rows,l", [(1000, 30), (8192, 110), (300, 288), (17, 17), (5000, 1)])
+@pytest.mark.parametrize("force_hh", [False, True])
+def test_orth_matches_householder_oracle(R, dtype, rows, l, force_hh):
+    if force_hh and rows * l > 300 * 288:
+        pytest.skip("single-workgroup fallback: exercised at the smaller shapes")
+    rng = np.random.default_rng(rows + l)
+    Y = rng.standard_normal((rows, l)) * np.logspace(0, -2, l)[None, :]     # kappa ~ 1e2
+    if dtype == torch.float32:
+        Y = Y.astype(np.float32).astype(np.float64)
+    Q, info = R.orth(_cuda(Y, dtype), force_householder=force_hh)
+    Qg = Q.cpu().numpy().astype(np.float64)
+    Qo = OL.householder_qr(Y)[0]
+    tol_e, tol_o = (2e-5, 2e-6) if dtype == torch.float32 else (1e-11, 1e-13)
+    assert _orth_err(Qg) <= tol_o
+    assert np.max(np.abs(Qg - Qo)) <= tol_e
+    fell_back = bool(info.item() & R.INFO_QR_FALLBACK)
+    assert fell_back == force_hh
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_orth_rank_deficient_falls_back(R, dtype):
+    rng = np.random.default_rng(11)
+    Y = rng.standard_normal((600, 5)) @ rng.standard_normal((5, 20))          # rank 5, 20 columns
+    Yd = _cuda(Y, dtype)
+    Q, info = R.orth(Yd)
+    Qg = Q.cpu().numpy().astype(np.float64)
+    tol_o = 2e-6 if dtype == torch.float32 else 1e-13
+    assert _orth_err(Qg) <= tol_o
+    Yr = Yd.cpu().numpy().astype(np.float64)
+    # range(Y) is inside range(Q)
+    assert np.linalg.norm(Yr - Qg @ (Qg.T @ Yr)) <= (1e-5 if dtype == torch.float32 else 1e-12) * np.linalg.norm(Yr)
+    if dtype == torch.float64:
+        assert info.item() & R.INFO_QR_FALLBACK
+    Z, zinfo = R.orth(torch.zeros((100, 8), dtype=dtype, device="cuda"))
+    assert zinfo.item() & R.INFO_QR_FALLBACK
+    assert _orth_err(Z.cpu().numpy().astype(np.float64)) <= tol_o

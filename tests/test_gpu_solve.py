@@ -1,0 +1,149 @@
+"""End-to-end parity of the GPU solve (Algorithm 4) with the FP64 oracle,
+through the C ABI, on the same seeded inputs and the same seeded test matrix.
+
+Tolerances:
+* FP64 solve: singular values within 1e-12 sigma_1 (normwise), vectors of
+  well-separated singular values within 1e-9, residual within 1e-9 relative.
+* FP32 solve: top-k singular values within 1e-5 sigma_1 (normwise; FP32
+  rounding perturbs every singular value by about u ||A||), the Frobenius
+  residual within 1% of the oracle's (plus the FP32 floor 16 u ||A||_F, which
+  matters only when the exact residual vanishes), and the subspaces of well-separated
+  leading singular vectors within 1e-3 (sin of the largest canonical angle).
+* Vectors are compared up to the sign of each column; the GPU's own output
+  is separately checked to satisfy the sign convention.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.rsvd import residual_norms, rsvd_alg4
+from paper_2402_17794_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2402_17794_amd import rsvd
+    rsvd.load_library()
+    return rsvd
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _align(X, Xref):
+    """Flip columns of X to the sign of Xref's."""
+    s = np.sign(np.sum(X * Xref, axis=0))
+    s[s == 0] = 1.0
+    return X * s[None, :]
+
+
+def _check_sign_convention(Vt):
+    for i in range(Vt.shape[0]):
+        idx = int(np.argmax(np.abs(Vt[i])))
+        assert Vt[i, idx] >= 0.0
+
+
+def _separated(S, rel=1e-3):
+    """Indices i whose sigma_i is separated from its neighbours by rel * sigma_1."""
+    gaps = np.full(S.size, np.inf)
+    gaps[:-1] = np.minimum(gaps[:-1], S[:-1] - S[1:])
+    gaps[1:] = np.minimum(gaps[1:], S[:-1] - S[1:])
+    return np.nonzero(gaps > rel * S[0])[0]
+
+
+def test_c1_fp64_512x256(R):
+    """The FP64 configuration: 512 x 256, sigma_i = 0.8^i, k=20, p=10, q=0, seed 0."""
+    sig = W.spectrum_geometric(256, 0.8)
+    A = W.known_spectrum(512, 256, sig, 1, 2)
+    out = R.solve(torch.from_numpy(A).cuda(), k=20, p=10, q=0, seed=0, residual=True, return_q=True)
+    torch.cuda.synchronize()
+    ref = rsvd_alg4(A, 20, 10, 0, seed=0)
+    S = _np(out["S"])
+    assert out["l"] == 30
+    assert out["info_tensor"].item() == 0
+    assert np.max(np.abs(S - ref["S"])) <= 1e-12 * ref["S"][0]
+    U, Vt = _np(out["U"]), _np(out["Vt"])
+    assert np.max(np.abs(U - ref["U"])) <= 1e-9
+    assert np.max(np.abs(Vt - ref["Vt"])) <= 1e-9
+    _check_sign_convention(Vt)
+    spec, fro = residual_norms(A, ref["Q"])
+    assert abs(_np(out["residual_t"])[1] - fro) <= 1e-9 * fro
+    Qg = _np(out["Q"])
+    assert np.max(np.abs(Qg - ref["Q"])) <= 1e-9
+
+
+@pytest.mark.parametrize("m,n,k,p,q,seed", [(1000, 600, 20, 10, 0, 0), (600, 1000, 25, 5, 1, 3),
+                                            (777, 333, 50, 10, 2, 9), (2048, 2048, 50, 10, 1, 0),
+                                            (300, 3000, 100, 10, 2, 1), (129, 65, 60, 10, 1, 2)])
+def test_fp32_solve_matches_oracle(R, m, n, k, p, q, seed):
+    d = min(m, n)
+    sig = W.spectrum_geometric(d, 0.95, 1e-6)
+    A = W.known_spectrum(m, n, sig, 1, 2)
+    A32 = A.astype(np.float32)
+    Ad = A32.astype(np.float64)                      # the oracle sees the same (rounded) matrix
+    out = R.solve(torch.from_numpy(A32).cuda(), k=k, p=p, q=q, seed=seed, residual=True)
+    torch.cuda.synchronize()
+    ref = rsvd_alg4(Ad, k, p, q, seed=seed)
+    S = _np(out["S"])
+    assert np.max(np.abs(S - ref["S"])) <= 1e-5 * ref["S"][0]
+    _, fro = residual_norms(Ad, ref["Q"])
+    # 1% of the oracle's residual, above the FP32 rounding floor u ||A||_F
+    # (when l = min(m, n) the exact residual is zero).
+    floor = 16 * 2.0 ** -24 * np.linalg.norm(Ad)
+    assert abs(_np(out["residual_t"])[1] - fro) <= 1e-2 * fro + floor
+    U, Vt = _np(out["U"]), _np(out["Vt"])
+    assert np.max(np.abs(U.T @ U - np.eye(k))) <= 1e-5
+    assert np.max(np.abs(Vt @ Vt.T - np.eye(k))) <= 1e-5
+    _check_sign_convention(Vt)
+    idx = _separated(ref["S"], 1e-2)[:10]
+    Ua = _align(U[:, idx], ref["U"][:, idx])
+    assert np.max(np.abs(Ua - ref["U"][:, idx])) <= 1e-3
+    Va = _align(Vt[idx].T, ref["Vt"][idx].T)
+    assert np.max(np.abs(Va - ref["Vt"][idx].T)) <= 1e-3
+
+
+def test_exact_rank_fp64(R):
+    A, sig = W.exact_rank(700, 300, 12, 5, 6)
+    out = R.solve(torch.from_numpy(A).cuda(), k=12, p=8, q=1, seed=4, residual=True)
+    torch.cuda.synchronize()
+    S = _np(out["S"])
+    assert np.max(np.abs(S - sig[:12])) <= 1e-12 * sig[0]
+    assert _np(out["residual_t"])[1] <= 1e-12 * sig[0]
+
+
+def test_zero_matrix_and_full_width(R):
+    out = R.solve(torch.zeros((200, 50), dtype=torch.float64, device="cuda"), k=5, p=5, q=1)
+    torch.cuda.synchronize()
+    assert np.all(_np(out["S"]) == 0.0)
+    assert out["info_tensor"].item() & R.INFO_QR_FALLBACK
+    # l = min(m, n): an exact SVD
+    sig = W.spectrum_geometric(40, 0.7)
+    A = W.known_spectrum(90, 40, sig, 3, 4)
+    out = R.solve(torch.from_numpy(A).cuda(), k=40, p=10, q=0)
+    torch.cuda.synchronize()
+    assert out["l"] == 40
+    assert np.max(np.abs(_np(out["S"]) - sig)) <= 1e-12 * sig[0]
+
+
+def test_return_full_l_and_determinism(R):
+    A = W.eq41_matrix(2.0, 5, 6).astype(np.float32)
+    Ad = torch.from_numpy(A).cuda()
+    a = R.solve(Ad, k=25, p=5, q=1, seed=1, return_full_l=True)
+    b = R.solve(Ad, k=25, p=5, q=1, seed=1, return_full_l=True)
+    torch.cuda.synchronize()
+    assert a["U"].shape == (3000, 30) and a["Vt"].shape == (30, 300)
+    for key in ("U", "S", "Vt"):
+        assert torch.equal(a[key], b[key])
+    ref = rsvd_alg4(A.astype(np.float64), 25, 5, 1, seed=1, return_full_l=True)
+    assert np.max(np.abs(_np(a["S"]) - ref["S"])) <= 1e-5 * ref["S"][0]
+
+
+def test_invalid_arguments_raise(R):
+    A = torch.zeros((10, 8), dtype=torch.float32, device="cuda")
+    for k, p, q in [(0, 1, 0), (9, 0, 0), (2, -1, 0)]:
+        with pytest.raises(R.RsvdError):
+            R.solve(A, k=k, p=p, q=q)
