@@ -69,9 +69,10 @@ typedef enum {
 
 typedef struct rsvd_handle rsvd_handle;
 
-/* Input matrix A: rows x cols, row-major, leading dimension ld (elements).
- * For RSVD_F32, ld must be a multiple of 4 and data 16-byte aligned; for
- * RSVD_F64 a multiple of 2 and 16-byte aligned. */
+/* Input matrix A: rows x cols, row-major, leading dimension ld (elements),
+ * 1 <= rows, cols < 2^31.  A is streamed with 16-byte loads when data is
+ * 16-byte aligned and ld is a multiple of 4 (RSVD_F32) or 2 (RSVD_F64);
+ * otherwise element loads are used (correct, slower). */
 typedef struct {
     const void* data;
     int32_t dtype;                 /* rsvd_dtype */
@@ -103,8 +104,9 @@ typedef struct {
     void* Q;  int64_t ldq;         /* nullable; m x l, row-major, ldq >= l */
 } rsvd_result;
 
-/* Create a handle bound to HIP device `device`.  Allocates a small amount of
- * device memory (counters) and queries the device.  *out is NULL on error. */
+/* Create a handle bound to HIP device `device` (host memory only; device
+ * scratch always comes from the caller's workspace).  *out is NULL on error.
+ * Calls made with the handle make `device` current (hipSetDevice). */
 rsvd_status rsvd_create(rsvd_handle** out, int device);
 rsvd_status rsvd_destroy(rsvd_handle* h);
 
@@ -124,6 +126,16 @@ rsvd_status rsvd_solve(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* 
                        void* stream);
 
 const char* rsvd_status_string(rsvd_status s);
+
+/* Kernel timing for performance reports.  While enabled, every product with
+ * A enqueued by rsvd_solve on handle h is bracketed by a pair of HIP events
+ * recorded on the solve's stream (events owned by the handle).
+ * rsvd_profile_read waits for the recorded events of one kind (0: the
+ * sketch A * Omega with the generated test matrix, 1: A * X, 2: A^T * X,
+ * 3: all kinds), returns the summed kernel time in milliseconds and the
+ * number of launches, and forgets those records. */
+rsvd_status rsvd_profile_enable(rsvd_handle* h, int32_t enable);
+rsvd_status rsvd_profile_read(rsvd_handle* h, int32_t kind, double* total_ms, int64_t* launches);
 
 /* ---- Single steps of the path, for testing each kernel on its own. ---- */
 

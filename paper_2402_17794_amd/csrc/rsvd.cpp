@@ -11,6 +11,7 @@
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "../../include/rsvd.h"
 #include "common.hpp"
@@ -20,6 +21,18 @@ using namespace rsvd;
 
 struct rsvd_handle {
     int device;
+    // Optional timing of the products with A (rsvd_profile_*): one event pair
+    // per launch, recorded on the solve's stream around the kernel.
+    bool profiling = false;
+    struct Rec { int kind; hipEvent_t start, stop; };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get_event() {
+        if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
 };
 
 namespace {
@@ -125,8 +138,8 @@ rsvd_status run_orth(const Plan& P, void* ws, int dtype, int64_t rows, const voi
     return RSVD_OK;
 }
 
-rsvd_status run_gemm(const Plan& P, void* ws, const rsvd_matrix* A, int trans, const void* X, uint64_t seed,
-                     void* Yout, hipStream_t s) {
+rsvd_status run_gemm(rsvd_handle* h, const Plan& P, void* ws, const rsvd_matrix* A, int trans, const void* X,
+                     uint64_t seed, void* Yout, hipStream_t s) {
     GemmArgs g{};
     g.A = A->data;
     g.lda = A->ld;
@@ -143,7 +156,18 @@ rsvd_status run_gemm(const Plan& P, void* ws, const rsvd_matrix* A, int trans, c
     g.partials = at<char>(ws, P.part);
     g.counters = at<int>(ws, P.counters);
     g.splits = trans ? P.splits_tn : P.splits_nn;
+    rsvd_handle::Rec rec{trans ? 2 : (X ? 1 : 0), nullptr, nullptr};
+    if (h->profiling) {
+        rec.start = h->get_event();
+        rec.stop = h->get_event();
+        if (!rec.start || !rec.stop) return RSVD_ERR_DEVICE;
+        RSVD_TRY(hipEventRecord(rec.start, s));
+    }
     RSVD_TRY(launch_gemm(P.dtype, g, s));
+    if (h->profiling) {
+        RSVD_TRY(hipEventRecord(rec.stop, s));
+        h->recs.push_back(rec);
+    }
     return RSVD_OK;
 }
 
@@ -198,7 +222,37 @@ rsvd_status rsvd_create(rsvd_handle** out, int device) {
 }
 
 rsvd_status rsvd_destroy(rsvd_handle* h) {
+    if (!h) return RSVD_OK;
+    for (auto& r : h->recs) { h->pool.push_back(r.start); h->pool.push_back(r.stop); }
+    for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
     delete h;
+    return RSVD_OK;
+}
+
+rsvd_status rsvd_profile_enable(rsvd_handle* h, int32_t enable) {
+    if (!h) return RSVD_ERR_INVALID_ARG;
+    h->profiling = enable != 0;
+    return RSVD_OK;
+}
+
+rsvd_status rsvd_profile_read(rsvd_handle* h, int32_t kind, double* total_ms, int64_t* launches) {
+    if (!h || !total_ms || !launches || kind < 0 || kind > 3) return RSVD_ERR_INVALID_ARG;
+    double tot = 0.0;
+    int64_t cnt = 0;
+    std::vector<rsvd_handle::Rec> keep;
+    for (auto& r : h->recs) {
+        if (kind != 3 && r.kind != kind) { keep.push_back(r); continue; }
+        if (hipEventSynchronize(r.stop) != hipSuccess) return RSVD_ERR_DEVICE;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess) return RSVD_ERR_DEVICE;
+        tot += ms;
+        ++cnt;
+        h->pool.push_back(r.start);
+        h->pool.push_back(r.stop);
+    }
+    h->recs.swap(keep);
+    *total_ms = tot;
+    *launches = cnt;
     return RSVD_OK;
 }
 
@@ -245,17 +299,17 @@ rsvd_status rsvd_solve(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* 
 
     RSVD_TRY(launch_init(cnt, P.ncounters, flags, s));
     // Stage 1: steps 1-3, sketch with the generated test matrix, then orth.
-    if ((st = run_gemm(P, ws, A, 0, nullptr, params->seed, Y, s)) != RSVD_OK) return st;
+    if ((st = run_gemm(h, P, ws, A, 0, nullptr, params->seed, Y, s)) != RSVD_OK) return st;
     if ((st = run_orth(P, ws, dt, P.m, Y, Q, hh, s)) != RSVD_OK) return st;
     // Steps 4-5: q power iterations, each product re-orthonormalised.
     for (int64_t t = 0; t < P.q; ++t) {
-        if ((st = run_gemm(P, ws, A, 1, Q, 0, Y, s)) != RSVD_OK) return st;
+        if ((st = run_gemm(h, P, ws, A, 1, Q, 0, Y, s)) != RSVD_OK) return st;
         if ((st = run_orth(P, ws, dt, P.n, Y, W, hh, s)) != RSVD_OK) return st;
-        if ((st = run_gemm(P, ws, A, 0, W, 0, Y, s)) != RSVD_OK) return st;
+        if ((st = run_gemm(h, P, ws, A, 0, W, 0, Y, s)) != RSVD_OK) return st;
         if ((st = run_orth(P, ws, dt, P.m, Y, Q, hh, s)) != RSVD_OK) return st;
     }
     // Stage 2: step 6 as B^T = A^T Q (n x l), step 7 small SVD, step 8 lift.
-    if ((st = run_gemm(P, ws, A, 1, Q, 0, Y, s)) != RSVD_OK) return st;
+    if ((st = run_gemm(h, P, ws, A, 1, Q, 0, Y, s)) != RSVD_OK) return st;
     const void* Bt = Y;
     double* G = at<double>(ws, P.G);
     double* R = at<double>(ws, P.R);

@@ -41,8 +41,8 @@ class rsvd_result(ctypes.Structure):
 
 
 EXPORTS = ["rsvd_create", "rsvd_destroy", "rsvd_l_used", "rsvd_workspace_size", "rsvd_solve",
-           "rsvd_status_string", "rsvd_omega", "rsvd_philox_words", "rsvd_gemm_workspace_size", "rsvd_gemm",
-           "rsvd_orth_workspace_size", "rsvd_orth"]
+           "rsvd_status_string", "rsvd_profile_enable", "rsvd_profile_read", "rsvd_omega", "rsvd_philox_words",
+           "rsvd_gemm_workspace_size", "rsvd_gemm", "rsvd_orth_workspace_size", "rsvd_orth"]
 
 _lib = None
 
@@ -65,6 +65,8 @@ def load_library(path=LIB_PATH):
         "rsvd_solve": ([P, ctypes.POINTER(rsvd_matrix), ctypes.POINTER(rsvd_params), ctypes.POINTER(rsvd_result),
                         P, SZ, P], I32),
         "rsvd_status_string": ([I32], ctypes.c_char_p),
+        "rsvd_profile_enable": ([P, I32], I32),
+        "rsvd_profile_read": ([P, I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)], I32),
         "rsvd_omega": ([I32, U64, ctypes.c_uint32, I64, I64, P, I64, P], I32),
         "rsvd_philox_words": ([U64, ctypes.c_uint32, P, I64, P, P], I32),
         "rsvd_gemm_workspace_size": ([ctypes.POINTER(rsvd_matrix), I32, I64, ctypes.POINTER(SZ)], I32),
@@ -187,6 +189,22 @@ def solve(A, k, p=10, q=0, seed=0, residual=False, return_full_l=False, force_ho
     if return_q:
         out["Q"] = s.Q
     return out
+
+
+PROFILE_SKETCH, PROFILE_NN, PROFILE_TN, PROFILE_ALL = 0, 1, 2, 3
+
+
+def profile_enable(device, enable=True):
+    """Time every product with A of later solves on `device` with HIP events."""
+    _check(load_library().rsvd_profile_enable(_handle(device), int(enable)))
+
+
+def profile_read(device, kind=PROFILE_ALL):
+    """(total kernel milliseconds, launches) of the recorded products of `kind`."""
+    tot = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    _check(load_library().rsvd_profile_read(_handle(device), kind, ctypes.byref(tot), ctypes.byref(cnt)))
+    return tot.value, cnt.value
 
 
 def omega(n, l, seed, dtype=torch.float32, stream_id=0, device="cuda"):
