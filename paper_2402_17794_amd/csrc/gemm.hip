@@ -16,12 +16,14 @@
 // device memory or, for the sketch, from the counter-based generator
 // evaluated straight into LDS (Omega never touches HBM).
 //
-// Split-K reduction is deterministic: every slice writes its partial tile,
-// the last slice to finish (device-scope counter) sums all slices in slice
-// order and writes Y, then resets the counter.  Block ids map slice-fastest,
-// so with 8 slices each XCD (ids are dealt round-robin over the 8 XCDs)
-// holds one K slice of every row tile and reads one slice of the thin
-// operand into its own L2.
+// Split-K reduction is deterministic: every slice writes its partial tile
+// and a separate kernel sums the slices in slice order.  (Reducing inside
+// the product kernel needs a device-scope release/acquire per workgroup; on
+// this chip that writes back and invalidates the XCD's L2 and costs more
+// than the whole reduction kernel.)  Block ids map slice-fastest, so with 8
+// slices each XCD (ids are dealt round-robin over the 8 XCDs) holds one K
+// slice of every row tile and reads one slice of the thin operand into its
+// own L2.
 #include <algorithm>
 
 #include "common.hpp"
@@ -30,9 +32,15 @@
 
 namespace rsvd {
 
-template <typename T> struct GemmTile;
-template <> struct GemmTile<float> { static constexpr int RT = 2, BK = 32; };
-template <> struct GemmTile<double> { static constexpr int RT = 1, BK = 16; };
+// Rows per wavefront (16 * RT) and K tile.  Wide thin operands (LT > 9, i.e.
+// more than 144 columns) use one row tile per wavefront and a shorter K tile
+// to keep the accumulators and the prefetch registers within the register
+// file.
+template <typename T, int LT> struct GemmTile;
+template <int LT> struct GemmTile<float, LT> {
+    static constexpr int RT = LT > 9 ? 1 : 2, BK = LT > 9 ? 32 : 64;
+};
+template <int LT> struct GemmTile<double, LT> { static constexpr int RT = 1, BK = 16; };
 
 template <typename T> struct Vec16;
 template <> struct Vec16<float> { using type = float4; static constexpr int n = 4; };
@@ -60,8 +68,8 @@ template <> __device__ __forceinline__ void vset<double>(double2& v, int i, doub
 // LDS strides chosen so that the 4 lane groups of an MFMA fragment read hit
 // disjoint banks.
 template <typename T, int L> struct Strides {
-    static constexpr int BK = GemmTile<T>::BK;
-    static constexpr int BM = 64 * GemmTile<T>::RT;
+    static constexpr int BK = GemmTile<T, L / 16>::BK;
+    static constexpr int BM = 64 * GemmTile<T, L / 16>::RT;
     static constexpr int SA_NN = BK + 16 / (int)sizeof(T);
     static constexpr int SA_TN = BM + 64 / (int)sizeof(T);
     static constexpr int SB = (sizeof(T) == 4) ? ((L % 32 == 16) ? L : L + 16)
@@ -70,8 +78,8 @@ template <typename T, int L> struct Strides {
 
 template <typename T, bool TRANS, bool OMEGA, int LT>
 __global__ __launch_bounds__(256) void skinny_gemm_kernel(GemmArgs g) {
-    constexpr int RT = GemmTile<T>::RT;
-    constexpr int BK = GemmTile<T>::BK;
+    constexpr int RT = GemmTile<T, LT>::RT;
+    constexpr int BK = GemmTile<T, LT>::BK;
     constexpr int BM = 64 * RT;
     constexpr int L = 16 * LT;
     constexpr int VEC = Vec16<T>::n;
@@ -111,7 +119,20 @@ __global__ __launch_bounds__(256) void skinny_gemm_kernel(GemmArgs g) {
     V rb[OMEGA ? 1 : NVB];
     T ro[OMEGA ? NOB : 1][4];
 
+    // Tiles wholly inside A (and the slice) take unguarded 16-byte loads.
+    const bool rows_full = avec && (row0 + BM <= g.M);
     auto load_a = [&](int64_t k0) {
+        if (rows_full && k0 + BK <= kend) {
+#pragma unroll
+            for (int it = 0; it < NVA; ++it) {
+                const int idx = tid + 256 * it;
+                int64_t row, col;
+                if (!TRANS) { row = row0 + idx / (BK / VEC); col = k0 + (idx % (BK / VEC)) * VEC; }
+                else        { row = k0 + idx / (BM / VEC);   col = row0 + (idx % (BM / VEC)) * VEC; }
+                ra[it] = *reinterpret_cast<const V*>(A + row * g.lda + col);
+            }
+            return;
+        }
 #pragma unroll
         for (int it = 0; it < NVA; ++it) {
             const int idx = tid + 256 * it;
@@ -157,6 +178,17 @@ __global__ __launch_bounds__(256) void skinny_gemm_kernel(GemmArgs g) {
                 }
             }
         } else {
+            if (xvec && g.ncols == L && k0 + BK <= kend) {
+#pragma unroll
+                for (int it = 0; it < NVB; ++it) {
+                    const int idx = tid + 256 * it;
+                    if (idx < BK * L / VEC) {
+                        const int rr = idx / (L / VEC), c = (idx % (L / VEC)) * VEC;
+                        rb[it] = *reinterpret_cast<const V*>(X + (k0 + rr) * g.ldx + c);
+                    }
+                }
+                return;
+            }
 #pragma unroll
             for (int it = 0; it < NVB; ++it) {
                 const int idx = tid + 256 * it;
@@ -208,18 +240,28 @@ __global__ __launch_bounds__(256) void skinny_gemm_kernel(GemmArgs g) {
                 load_a(k0 + BK);
                 load_b(k0 + BK);
             }
-#pragma unroll
-            for (int kk = 0; kk < BK; kk += 4) {
-                T a[RT];
+            // Fragments of k-step s + 1 are read from LDS while the MFMAs of
+            // step s issue (two register sets).
+            T fa[2][RT], fb[2][LT];
+            auto read_frags = [&](int kk, T (&a)[RT], T (&b)[LT]) {
 #pragma unroll
                 for (int r = 0; r < RT; ++r)
                     a[r] = TRANS ? As[(kk + lk) * SA + wm + 16 * r + li] : As[(wm + 16 * r + li) * SA + kk + lk];
 #pragma unroll
-                for (int t = 0; t < LT; ++t) {
-                    const T b = Bs[(kk + lk) * SB + 16 * t + li];
+                for (int t = 0; t < LT; ++t) b[t] = Bs[(kk + lk) * SB + 16 * t + li];
+            };
+            read_frags(0, fa[0], fb[0]);
 #pragma unroll
-                    for (int r = 0; r < RT; ++r) acc[r][t] = mfma16x16x4(a[r], b, acc[r][t]);
-                }
+            for (int st = 0; st < BK / 4; ++st) {
+                const int cur = st & 1;
+                if (st + 1 < BK / 4) read_frags(4 * (st + 1), fa[cur ^ 1], fb[cur ^ 1]);
+#pragma unroll
+                for (int t = 0; t < LT; ++t)
+#pragma unroll
+                    for (int r = 0; r < RT; ++r) acc[r][t] = mfma16x16x4(fa[cur][r], fb[cur][t], acc[r][t]);
+                // Keep that order in the schedule: next step's LDS reads, then this step's MFMAs.
+                if (st + 1 < BK / 4) __builtin_amdgcn_sched_group_barrier(0x100, RT + LT, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, RT * LT, 0);
             }
         }
     }
@@ -250,28 +292,33 @@ __global__ __launch_bounds__(256) void skinny_gemm_kernel(GemmArgs g) {
                 const int64_t row = row0 + wm + 16 * r + acc_row<T>(lk, v);
                 if (row < g.M) P[split * pstride + row * L + 16 * t + li] = acc[r][t][v];
             }
-    __threadfence();
-    __syncthreads();
-    __shared__ int last;
-    if (tid == 0) last = (atomicAdd(&g.counters[tile], 1) == splits - 1);
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    const int rows_here = (int)min<int64_t>(BM, g.M - row0);
-    for (int idx = tid; idx < rows_here * (L / VEC); idx += 256) {
-        const int rr = idx / (L / VEC), c = (idx % (L / VEC)) * VEC;
-        const int64_t off = (row0 + rr) * L + c;
-        V sum = *reinterpret_cast<const V*>(P + off);
-        for (int s = 1; s < splits; ++s) {
-            const V x = *reinterpret_cast<const V*>(P + s * pstride + off);
+}
+
+// Y = sum of the split-K slices, added in slice order (slice 0 first).
+template <typename T, int SMAX>
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(const T* __restrict__ P, int64_t M, int L, int splits,
+                                                            T* __restrict__ Y, int64_t ldy, int wcols) {
+    using V = typename Vec16<T>::type;
+    constexpr int VEC = Vec16<T>::n;
+    const int64_t nvec = M * (L / VEC);
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= nvec) return;
+    const int64_t pstride = M * L;
+    V x[SMAX];
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) vset<T>(sum, e, vget<T>(sum, e) + vget<T>(x, e));
-        }
+    for (int sl = 0; sl < SMAX; ++sl)
+        if (sl < splits) x[sl] = *reinterpret_cast<const V*>(P + sl * pstride + idx * VEC);
+    V sum = x[0];
 #pragma unroll
-        for (int e = 0; e < VEC; ++e)
-            if (c + e < g.wcols) Y[(row0 + rr) * g.ldy + c + e] = vget<T>(sum, e);
-    }
-    if (tid == 0) g.counters[tile] = 0;
+    for (int sl = 1; sl < SMAX; ++sl)
+        if (sl < splits)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) vset<T>(sum, e, vget<T>(sum, e) + vget<T>(x[sl], e));
+    const int64_t row = idx / (L / VEC);
+    const int c = (int)(idx % (L / VEC)) * VEC;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e)
+        if (c + e < wcols) Y[row * ldy + c + e] = vget<T>(sum, e);
 }
 
 template <typename T, bool TRANS, bool OMEGA>
@@ -288,25 +335,31 @@ static hipError_t dispatch_lt(const GemmArgs& a, int LT, dim3 grid, hipStream_t 
     return hipGetLastError();
 }
 
-static int bm_of(int dtype) { return dtype == 0 ? 64 * GemmTile<double>::RT : 64 * GemmTile<float>::RT; }
-static int bk_of(int dtype) { return dtype == 0 ? GemmTile<double>::BK : GemmTile<float>::BK; }
+static int bm_of(int dtype, int LT) {
+    return dtype == 0 ? 64 * GemmTile<double, 1>::RT : (LT > 9 ? 64 * GemmTile<float, 10>::RT : 64 * GemmTile<float, 1>::RT);
+}
+static int bk_of(int dtype, int LT) {
+    return dtype == 0 ? GemmTile<double, 1>::BK : (LT > 9 ? GemmTile<float, 10>::BK : GemmTile<float, 1>::BK);
+}
 
-int gemm_row_tiles(int dtype, int64_t M) { return (int)ceil_div(M, bm_of(dtype)); }
+int gemm_row_tiles(int dtype, int64_t M, int ncols) {
+    return (int)ceil_div(M, bm_of(dtype, (int)ceil_div(ncols, 16)));
+}
 
 // Split count: aim for about two workgroups per CU (256 CUs) with at least
 // eight K tiles per slice; at most 16 slices.
-static int choose_splits(int dtype, int64_t M, int64_t K) {
-    const int tiles = gemm_row_tiles(dtype, M);
-    const int64_t ktiles = ceil_div(K, bk_of(dtype));
+static int choose_splits(int dtype, int64_t M, int64_t K, int ncols) {
+    const int tiles = gemm_row_tiles(dtype, M, ncols);
+    const int64_t ktiles = ceil_div(K, bk_of(dtype, (int)ceil_div(ncols, 16)));
     int s = (int)ceil_div(512, tiles);
     s = (int)std::min<int64_t>(s, std::max<int64_t>(1, ktiles / 8));
-    s = std::max(1, std::min(s, 16));
+    s = std::max(1, std::min(s, kMaxSplits));
     if (s > 1 && s < 8 && 8 <= ktiles / 8) s = 8;      // one slice per XCD when it fits
     return s;
 }
 
 size_t gemm_partials_elems(int dtype, int64_t M, int64_t K, int ncols, int* splits_out) {
-    const int s = choose_splits(dtype, M, K);
+    const int s = choose_splits(dtype, M, K, ncols);
     if (splits_out) *splits_out = s;
     const int L = (int)round_up(ncols, 16);
     return s > 1 ? (size_t)s * (size_t)M * (size_t)L : 0;
@@ -318,13 +371,27 @@ hipError_t launch_gemm(int dtype, GemmArgs a, hipStream_t s) {
     const int LT = (int)ceil_div(a.ncols, 16);
     const bool omega = (a.X == nullptr);
     if (omega && a.trans) return hipErrorInvalidValue;
-    dim3 grid(gemm_row_tiles(dtype, a.M) * a.splits);
+    if (a.splits < 1 || a.splits > kMaxSplits) return hipErrorInvalidValue;
+    dim3 grid(gemm_row_tiles(dtype, a.M, a.ncols) * a.splits);
+    hipError_t e;
     if (dtype == 0) {
-        if (a.trans) return dispatch_lt<double, true, false>(a, LT, grid, s);
-        return omega ? dispatch_lt<double, false, true>(a, LT, grid, s) : dispatch_lt<double, false, false>(a, LT, grid, s);
+        if (a.trans) e = dispatch_lt<double, true, false>(a, LT, grid, s);
+        else e = omega ? dispatch_lt<double, false, true>(a, LT, grid, s) : dispatch_lt<double, false, false>(a, LT, grid, s);
+    } else {
+        if (a.trans) e = dispatch_lt<float, true, false>(a, LT, grid, s);
+        else e = omega ? dispatch_lt<float, false, true>(a, LT, grid, s) : dispatch_lt<float, false, false>(a, LT, grid, s);
     }
-    if (a.trans) return dispatch_lt<float, true, false>(a, LT, grid, s);
-    return omega ? dispatch_lt<float, false, true>(a, LT, grid, s) : dispatch_lt<float, false, false>(a, LT, grid, s);
+    if (e != hipSuccess || a.splits == 1) return e;
+    const int L = 16 * LT;
+    const int64_t nvec = a.M * (L / (dtype == 0 ? 2 : 4));
+    dim3 rgrid((unsigned)ceil_div(nvec, 256));
+    if (dtype == 0)
+        hipLaunchKernelGGL((splitk_reduce_kernel<double, kMaxSplits>), rgrid, dim3(256), 0, s,
+                           (const double*)a.partials, a.M, L, a.splits, (double*)a.Y, a.ldy, a.wcols);
+    else
+        hipLaunchKernelGGL((splitk_reduce_kernel<float, kMaxSplits>), rgrid, dim3(256), 0, s,
+                           (const float*)a.partials, a.M, L, a.splits, (float*)a.Y, a.ldy, a.wcols);
+    return hipGetLastError();
 }
 
 // ---- test entry points: Omega materialised, raw Philox words ----

@@ -9,6 +9,7 @@ namespace rsvd {
 // Largest padded width L = 16 * LT supported by the product kernels.
 constexpr int kMaxLT = 18;
 constexpr int kMaxL = 16 * kMaxLT;
+constexpr int kMaxSplits = 16;     // split-K slices of a product with A
 
 // Status flags kept in device memory for one orthonormalisation / solve.
 struct DevFlags {
@@ -28,38 +29,42 @@ struct GemmArgs {
     int wcols;                 // columns of Y to write (ncols or L)
     void* Y; int64_t ldy;
     void* partials;            // splits * M * L elements (splits > 1)
-    int* counters;             // ceil(M / BM) ints, zero on entry, zero on exit
     int splits;
 };
 size_t gemm_partials_elems(int dtype, int64_t M, int64_t K, int ncols, int* splits_out);
-int gemm_row_tiles(int dtype, int64_t M);
+int gemm_row_tiles(int dtype, int64_t M, int ncols);
 hipError_t launch_gemm(int dtype, GemmArgs a, hipStream_t s);
 
 // ---- Gram, Cholesky, apply, Householder (orth.hip) ----
-// G (L x L, double, full symmetric) = Y^T Y for Y rows x L (dtype), ld = ldy.
-// partials: gram_partials_elems doubles; counters: gram_pairs ints.
+// Chunk partials of G = Y^T Y (FP64) for Y rows x L (dtype, zero padding):
+// gram_partials_elems doubles, consumed by launch_chol with the same rows.
+int gram_chunks(int64_t rows);
 size_t gram_partials_elems(int64_t rows, int L);
 int gram_pairs(int L);
-hipError_t launch_gram(int dtype, const void* Y, int64_t ldy, int64_t rows, int L, double* G,
-                       double* partials, int* counters, const DevFlags* skip_if_fail, hipStream_t s);
+hipError_t launch_gram(int dtype, const void* Y, int64_t ldy, int64_t rows, int L, double* partials,
+                       const DevFlags* skip_if_fail, hipStream_t s);
 
-// Cholesky G = R^T R and R^{-1} for the leading l x l block (single workgroup).
+// Sum the Gram partials and factor G = R^T R, forming R^{-1} too (single
+// workgroup); R, Rinv: L x L, zero outside the leading l x l block.
 // mode 0 (orth pass 1): on breakdown set flags->orth_fail = 1 (else 0).
-// mode 1 (orth pass 2): skip if orth_fail; on breakdown set orth_fail = 1.
+// mode 1 (orth pass 2): skip if orth_fail; first-order factor when
+//                       max |G - I| <= tau; on breakdown set orth_fail = 1.
 // mode 2 (small SVD): on breakdown retry with a diagonal shift, report it in
 //                     info and store the shift in *shift_out.
-// work: L*L doubles of device scratch (used when L is too large for LDS).
-hipError_t launch_chol(const double* G, int l, int L, double* R, double* Rinv, DevFlags* flags, int mode,
-                       double* shift_out, double* work, hipStream_t s);
+// work: L*L doubles of device scratch (used when l is too large for LDS).
+hipError_t launch_chol(const double* partials, int64_t rows, int l, int L, double* R, double* Rinv,
+                       DevFlags* flags, int mode, double* shift_out, double* work, double tau, hipStream_t s);
 
 // out[rows x ncols_out] = in[rows x L] * M[L x ncols_out] with FP64 accumulation.
 // transpose_out: write out^T (ncols_out x rows, ld = ldo).  colscale (nullable):
 // multiply output column c by colscale[c].  skip_if_fail: return at once if
 // flags->orth_fail is set.  argmax (nullable, with transpose_out): per-block
 // index/value of the largest |entry| of each output column.
+// upper: M is upper triangular (its zero blocks are skipped).
 hipError_t launch_apply(int dtype, const void* in, int64_t ldi, int64_t rows, int L, const double* M, int ldm,
                         int ncols_out, void* out, int64_t ldo, int transpose_out, const double* colscale,
-                        const DevFlags* skip_if_fail, double* argmax_val, int* argmax_idx, hipStream_t s);
+                        const DevFlags* skip_if_fail, double* argmax_val, int* argmax_idx, int upper,
+                        hipStream_t s);
 int apply_blocks(int64_t rows);
 
 // Householder QR fallback (single workgroup); runs only if flags->orth_fail
@@ -71,7 +76,7 @@ hipError_t launch_householder(int dtype, const void* Y, int64_t ldy, int64_t row
 // One-sided Jacobi on X = R^T (l x l, from the Cholesky factor of B B^T).
 // Outputs sigma (sorted descending, shift removed), Ut (L x L, column c =
 // left singular vector c of B, sorted), Mv (L x L: Ut * diag(1/sigma)),
-// perm unused by callers.  work: 2*L*L doubles (global path).
+// work: kMaxL * kMaxL doubles (used when l is too large for LDS).
 hipError_t launch_jacobi(const double* R, int l, int L, const double* shift, double* sigma, double* Ut,
                          double* Mv, DevFlags* flags, double* work, hipStream_t s);
 
@@ -99,10 +104,10 @@ hipError_t launch_omega(int dtype, uint64_t seed, uint32_t stream, int64_t n, in
 hipError_t launch_philox_words(uint64_t seed, uint32_t stream, const uint32_t* ctr, int64_t count, uint32_t* out,
                                hipStream_t s);
 
-// ||A - Q B||_F with B^T = Bt (n x L): fused, FP64 accumulation of squares.
+// ||A - Q B||_F with B^T = Bt (n x L): tile partials (FP64 accumulation of
+// squares) and a fixed-order final sum; out[0] = 0, out[1] = the norm.
 hipError_t launch_residual_fro(int dtype, const void* A, int64_t lda, int64_t m, int64_t n, const void* Q,
-                               const void* Bt, int l, int L, double* partial, int* counter, double* out,
-                               hipStream_t s);
+                               const void* Bt, int l, int L, double* partial, double* out, hipStream_t s);
 size_t residual_partials(int64_t m, int64_t n);
 
 }  // namespace rsvd

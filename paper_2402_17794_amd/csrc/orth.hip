@@ -26,92 +26,73 @@
 namespace rsvd {
 
 // ---------------------------------------------------------------- Gram --
-// G = Y^T Y in FP64.  Output tiles of 32 x 32 on and above the diagonal;
-// rows split into chunks of kGramRows.  Each workgroup computes one tile
-// over one chunk; the last chunk to finish a tile (device-scope counter)
-// sums the chunk partials in chunk order, writes the tile and its mirror.
-constexpr int kGramRows = 256;
-constexpr int kGT = 32;
-
+// Partial Gram matrices Y_c^T Y_c (FP64, on FP64 MFMA 16x16x4) for nchunks
+// row chunks Y_c of Y.  Output tiles of 16 x 16 on and above the diagonal.
+// A workgroup of 4 wavefronts computes one tile over one chunk: wavefront w
+// takes the 4-row steps w, w + 4, ... with two accumulators, and the eight
+// accumulators are summed in a fixed order.  The chunk partials are summed
+// (in chunk order) by the Cholesky kernel that consumes them, so no
+// workgroup ever waits for another.
 int gram_pairs(int L) {
-    const int nt = (int)ceil_div(L, kGT);
+    const int nt = (int)ceil_div(L, 16);
     return nt * (nt + 1) / 2;
 }
-size_t gram_partials_elems(int64_t rows, int L) {
-    return (size_t)ceil_div(std::max<int64_t>(rows, 1), kGramRows) * gram_pairs(L) * kGT * kGT;
-}
+int gram_chunks(int64_t rows) { return (int)std::min<int64_t>(8, std::max<int64_t>(1, ceil_div(rows, 1024))); }
+size_t gram_partials_elems(int64_t rows, int L) { return (size_t)gram_chunks(rows) * gram_pairs(L) * 256; }
 
 template <typename T>
 __global__ __launch_bounds__(256) void gram_kernel(const T* __restrict__ Y, int64_t ldy, int64_t rows, int L,
-                                                   double* __restrict__ G, double* __restrict__ part,
-                                                   int* __restrict__ cnt, const DevFlags* skip) {
+                                                   int nchunks, double* __restrict__ part, const DevFlags* skip) {
     if (skip && skip->orth_fail) return;
-    const int nt = (int)ceil_div(L, kGT);
+    const int nt = L / 16;
     const int npairs = nt * (nt + 1) / 2;
     const int pair = blockIdx.x % npairs;
     const int chunk = blockIdx.x / npairs;
-    const int nchunks = (int)ceil_div(max<int64_t>(rows, 1), kGramRows);
     int a = 0, p = pair;
     while (p >= nt - a) { p -= nt - a; ++a; }
     const int b = a + p;
-
-    __shared__ double Ya[kGT][kGT + 1];
-    __shared__ double Yb[kGT][kGT + 1];
-    const int tid = threadIdx.x;
-    const int ti = (tid >> 4) * 2, tj = (tid & 15) * 2;
-    double s00 = 0, s01 = 0, s10 = 0, s11 = 0;
-    const int64_t r0 = (int64_t)chunk * kGramRows;
-    const int64_t r1 = min<int64_t>(rows, r0 + kGramRows);
-    for (int64_t rb = r0; rb < r1; rb += kGT) {
-        __syncthreads();
-        for (int idx = tid; idx < kGT * kGT; idx += 256) {
-            const int rr = idx / kGT, cc = idx % kGT;
-            const int64_t row = rb + rr;
-            const int ca = a * kGT + cc, cb = b * kGT + cc;
-            Ya[rr][cc] = (row < r1 && ca < L) ? (double)Y[row * ldy + ca] : 0.0;
-            Yb[rr][cc] = (row < r1 && cb < L) ? (double)Y[row * ldy + cb] : 0.0;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t per = round_up(ceil_div(rows, nchunks), 16);
+    const int64_t r0 = (int64_t)chunk * per;
+    const int64_t r1 = min<int64_t>(rows, r0 + per);
+    const T* __restrict__ ya = Y + a * 16 + li;
+    const T* __restrict__ yb = Y + b * 16 + li;
+    doublex4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+    constexpr int UNR = 8;          // 8 MFMA steps (32 rows per wavefront) per batch of loads
+    for (int64_t k0 = r0 + 4 * wave; k0 < r1; k0 += 16 * UNR) {
+        double va[UNR], vb[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int64_t row = k0 + 16 * u + lk;
+            const bool ok = row < r1;
+            va[u] = ok ? (double)ya[row * ldy] : 0.0;
+            vb[u] = ok ? (double)yb[row * ldy] : 0.0;
         }
-        __syncthreads();
-#pragma unroll 8
-        for (int rr = 0; rr < kGT; ++rr) {
-            const double x0 = Ya[rr][ti], x1 = Ya[rr][ti + 1];
-            const double y0 = Yb[rr][tj], y1 = Yb[rr][tj + 1];
-            s00 = fma(x0, y0, s00); s01 = fma(x0, y1, s01);
-            s10 = fma(x1, y0, s10); s11 = fma(x1, y1, s11);
+#pragma unroll
+        for (int u = 0; u < UNR; u += 2) {
+            acc0 = mfma16x16x4(va[u], vb[u], acc0);
+            acc1 = mfma16x16x4(va[u + 1], vb[u + 1], acc1);
         }
     }
-    double* mine = part + ((size_t)chunk * npairs + pair) * (kGT * kGT);
-    mine[ti * kGT + tj] = s00;       mine[ti * kGT + tj + 1] = s01;
-    mine[(ti + 1) * kGT + tj] = s10; mine[(ti + 1) * kGT + tj + 1] = s11;
-    __threadfence();
+    // acc[v] = G[a*16 + acc_row(lk, v)][b*16 + li] restricted to this chunk.
+    __shared__ double red[4][256];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[wave][acc_row<double>(lk, v) * 16 + li] = acc0[v] + acc1[v];
     __syncthreads();
-    __shared__ int last;
-    if (tid == 0) last = (atomicAdd(&cnt[pair], 1) == nchunks - 1);
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    for (int idx = tid; idx < kGT * kGT; idx += 256) {
-        double s = 0.0;
-        for (int c = 0; c < nchunks; ++c) s += part[((size_t)c * npairs + pair) * (kGT * kGT) + idx];
-        const int i = a * kGT + idx / kGT, j = b * kGT + idx % kGT;
-        if (i < L && j < L) {
-            G[(int64_t)i * L + j] = s;
-            G[(int64_t)j * L + i] = s;
-        }
-    }
-    if (tid == 0) cnt[pair] = 0;
+    part[((size_t)chunk * npairs + pair) * 256 + tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
 }
 
-hipError_t launch_gram(int dtype, const void* Y, int64_t ldy, int64_t rows, int L, double* G, double* partials,
-                       int* counters, const DevFlags* skip, hipStream_t s) {
-    const int nchunks = (int)ceil_div(std::max<int64_t>(rows, 1), kGramRows);
+hipError_t launch_gram(int dtype, const void* Y, int64_t ldy, int64_t rows, int L, double* partials,
+                       const DevFlags* skip, hipStream_t s) {
+    const int nchunks = gram_chunks(rows);
     dim3 grid(nchunks * gram_pairs(L));
     if (dtype == 0)
-        hipLaunchKernelGGL(gram_kernel<double>, grid, dim3(256), 0, s, (const double*)Y, ldy, rows, L, G, partials,
-                           counters, skip);
+        hipLaunchKernelGGL(gram_kernel<double>, grid, dim3(256), 0, s, (const double*)Y, ldy, rows, L, nchunks,
+                           partials, skip);
     else
-        hipLaunchKernelGGL(gram_kernel<float>, grid, dim3(256), 0, s, (const float*)Y, ldy, rows, L, G, partials,
-                           counters, skip);
+        hipLaunchKernelGGL(gram_kernel<float>, grid, dim3(256), 0, s, (const float*)Y, ldy, rows, L, nchunks,
+                           partials, skip);
     return hipGetLastError();
 }
 
@@ -120,61 +101,174 @@ hipError_t launch_gram(int dtype, const void* Y, int64_t ldy, int64_t rows, int 
 // R^{-1} in the same sweep: row operations of the elimination are applied to
 // an identity carried in the (otherwise unused) strict lower triangle, which
 // turns into R^{-T} (the Gauss-Jordan view of Cholesky).  One barrier per
-// column.  Row j of R and column j of R^{-1} are written as soon as pivot j
-// is known.
+// column.  Thread (rg, cl) owns rows j+1+rg+32u and columns cl+32v of the
+// trailing update; all its loads are issued before its updates.  Row j of R
+// and column j of R^{-1} are written as soon as pivot j is known.
+//
+// Second pass of CholeskyQR2 (mode 1): G = Q1^T Q1 = I + E with E tiny.  If
+// max |E| <= tau (FP32 data: 2^-13, FP64: 2^-26) the factor is taken to first
+// order, R = I + U with U = triu(E) - diag(E) / 2 and R^{-1} = I - U; the
+// neglected terms are O(|E|^2), below the storage precision, and Q1 R^{-1}
+// is orthonormal to O(|E|^2).  Otherwise the exact factorisation runs.
 constexpr int kCholLdsMax = 128;
 
 template <bool IN_LDS>
-__global__ __launch_bounds__(1024) void chol_kernel(const double* __restrict__ G, int l, int L,
+__global__ __launch_bounds__(1024) void chol_kernel(const double* __restrict__ part, int nchunks, int l, int L,
                                                     double* __restrict__ R, double* __restrict__ Rinv,
                                                     DevFlags* flags, int mode, double* shift_out,
-                                                    double* __restrict__ work) {
+                                                    double* __restrict__ work, double tau) {
+    constexpr int LP = IN_LDS ? kCholLdsMax : 1;
     __shared__ double lds[IN_LDS ? kCholLdsMax * kCholLdsMax : 1];
+    __shared__ double dg[kMaxL];
+    __shared__ double inv_r[kMaxL];
+    __shared__ unsigned long long s_emax;
     if (mode == 1 && flags->orth_fail) return;
     double* M = IN_LDS ? lds : work;
-    const int tid = threadIdx.x, nth = blockDim.x;
+    const int ldm = IN_LDS ? LP : l;
+    const int tid = threadIdx.x, rg = tid >> 5, cl = tid & 31;
+    const int nt = L / 16, npairs = nt * (nt + 1) / 2;
+
+    // Sum the chunk partials (chunk order) into the upper triangle of M;
+    // the strict lower triangle starts at zero.
+    if (tid == 0) s_emax = 0ull;
+    for (int a = rg; a < l; a += 32)
+        for (int c = cl; c < a; c += 32) M[a * ldm + c] = 0.0;
+    double emax = 0.0;
+    for (int idx = tid; idx < npairs * 256; idx += 1024) {
+        const int pr = idx >> 8, e = idx & 255;
+        int ta = 0, pp = pr;
+        while (pp >= nt - ta) { pp -= nt - ta; ++ta; }
+        const int row = ta * 16 + (e >> 4), col = (ta + pp) * 16 + (e & 15);
+        if (row > col || row >= l || col >= l) continue;
+        double sum = 0.0;
+        int c = 0;
+        for (; c + 4 <= nchunks; c += 4) {
+            const double x0 = part[((size_t)(c + 0) * npairs + pr) * 256 + e];
+            const double x1 = part[((size_t)(c + 1) * npairs + pr) * 256 + e];
+            const double x2 = part[((size_t)(c + 2) * npairs + pr) * 256 + e];
+            const double x3 = part[((size_t)(c + 3) * npairs + pr) * 256 + e];
+            sum = (((sum + x0) + x1) + x2) + x3;
+        }
+        for (; c < nchunks; ++c) sum += part[((size_t)c * npairs + pr) * 256 + e];
+        M[row * ldm + col] = sum;
+        if (row == col) dg[row] = sum;
+        double ee = fabs(sum - (row == col ? 1.0 : 0.0));
+        if (!(ee < 1e300)) ee = 1e300;
+        emax = fmax(emax, ee);
+    }
+    if (mode == 1) atomicMax(&s_emax, (unsigned long long)__double_as_longlong(emax));
+    __syncthreads();
+
+    if (mode == 1 && __longlong_as_double((long long)s_emax) <= tau) {
+        // Second pass: first-order factor (see above).
+#pragma unroll 4
+        for (int idx = tid; idx < L * L; idx += 1024) {
+            const int a = idx / L, c = idx - a * L;
+            double r = 0.0, ri = 0.0;
+            if (a <= c && c < l) {
+                const double e = M[a * ldm + c] - (a == c ? 1.0 : 0.0);
+                const double u = a < c ? e : 0.5 * e;
+                r = (a == c ? 1.0 : 0.0) + u;
+                ri = (a == c ? 1.0 : 0.0) - u;
+            }
+            R[idx] = r;
+            Rinv[idx] = ri;
+        }
+        if (tid == 0) flags->orth_fail = 0;
+        return;
+    }
 
     double gmax = 0.0;
     bool nonfinite = false;
     for (int j = 0; j < l; ++j) {
-        const double d = G[(int64_t)j * L + j];
+        const double d = dg[j];
         if (!isfinite(d)) nonfinite = true;
         else gmax = fmax(gmax, d);
     }
     const double rel = (mode == 0) ? 1e-12 : (mode == 1 ? 1e-2 : 0.0);
-    double shift = 0.0;
+    double shift = 0.0, applied = 0.0;
     bool broke = false;
     for (int attempt = 0; attempt < (mode == 2 ? 5 : 1); ++attempt) {
-        __syncthreads();
-        for (int idx = tid; idx < L * L; idx += nth) { R[idx] = 0.0; Rinv[idx] = 0.0; }
-        for (int idx = tid; idx < l * l; idx += nth) {
-            const int a = idx / l, c = idx % l;
-            M[idx] = (c >= a) ? G[(int64_t)a * L + c] + (a == c ? shift : 0.0) : 0.0;
+        if (shift != applied) {        // retry: the factorisation overwrote M; restore with the new shift
+            __syncthreads();
+            for (int idx = tid; idx < npairs * 256; idx += 1024) {
+                const int pr = idx >> 8, e = idx & 255;
+                int ta = 0, pp = pr;
+                while (pp >= nt - ta) { pp -= nt - ta; ++ta; }
+                const int row = ta * 16 + (e >> 4), col = (ta + pp) * 16 + (e & 15);
+                if (row > col || row >= l || col >= l) continue;
+                double sum = 0.0;
+                for (int c = 0; c < nchunks; ++c) sum += part[((size_t)c * npairs + pr) * 256 + e];
+                M[row * ldm + col] = sum + (row == col ? shift : 0.0);
+            }
+            for (int a = rg; a < l; a += 32)
+                for (int c = cl; c < a; c += 32) M[a * ldm + c] = 0.0;
+            applied = shift;
+            __syncthreads();
         }
-        __syncthreads();
         broke = nonfinite;
         for (int j = 0; j < l && !broke; ++j) {
-            const double d = M[j * l + j];
-            const double dj0 = G[(int64_t)j * L + j] + shift;
-            if (!(d > rel * dj0) || !(d > 0.0) || !isfinite(d)) { broke = true; break; }
-            const double rj = sqrt(d), inv_rj = 1.0 / rj, inv_d = 1.0 / d;
-            for (int c = tid; c < l; c += nth) {
-                if (c >= j) R[(int64_t)j * L + c] = M[j * l + c] * inv_rj;
-                if (c < j) Rinv[(int64_t)c * L + j] = M[j * l + c] * inv_rj;
-                if (c == j) Rinv[(int64_t)j * L + j] = inv_rj;
-            }
-            const int nrows = l - 1 - j;
-            for (int idx = tid; idx < nrows * l; idx += nth) {
-                const int a = j + 1 + idx / l, c = idx % l;
-                const double f = M[j * l + a] * inv_d;
-                if (c >= a || c < j) M[a * l + c] -= f * M[j * l + c];
-                else if (c == j) M[a * l + j] = -f;
+            const double d = M[j * ldm + j];
+            if (!(d > rel * (dg[j] + shift)) || !(d > 0.0) || !isfinite(d)) { broke = true; break; }
+            const double inv_rj = 1.0 / sqrt(d), inv_d = inv_rj * inv_rj;
+            if (tid == 0) inv_r[j] = inv_rj;
+            if (IN_LDS) {
+                // Rows a = j+1+rg+32u (u < 4), columns c = cl+32v (v < 4); l <= 128.
+                double rowj[4], f[4], x[4][4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int c = cl + 32 * v;
+                    rowj[v] = c < l ? M[j * ldm + c] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int a = min(j + 1 + rg + 32 * u, LP - 1);
+                    f[u] = M[j * ldm + a] * inv_d;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) x[u][v] = M[a * ldm + cl + 32 * v];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int a = j + 1 + rg + 32 * u;
+                    if (a >= l) continue;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int c = cl + 32 * v;
+                        if (c >= l) continue;
+                        if (c >= a || c < j) M[a * ldm + c] = x[u][v] - f[u] * rowj[v];
+                        else if (c == j) M[a * ldm + j] = -f[u];
+                    }
+                }
+            } else {
+                for (int a = j + 1 + rg; a < l; a += 32) {
+                    const double fa = M[j * ldm + a] * inv_d;
+                    for (int c = cl; c < l; c += 32) {
+                        if (c >= a || c < j) M[a * ldm + c] -= fa * M[j * ldm + c];
+                        else if (c == j) M[a * ldm + j] = -fa;
+                    }
+                }
             }
             __syncthreads();
         }
         if (!broke || mode != 2 || nonfinite) break;
         shift = (shift == 0.0) ? gmax * 0x1.0p-40 : shift * 1024.0;
         if (!(shift > 0.0)) shift = 0x1.0p-1000;
+    }
+    __syncthreads();
+    // Row a of M holds row a of R (times r_aa) in its upper part and row a of
+    // R^{-T} (times r_aa) in its strict lower part; neither changes after step a.
+    if (!broke) {
+#pragma unroll 4
+        for (int idx = tid; idx < L * L; idx += 1024) {
+            const int x = idx / L, y = idx - x * L;
+            double r = 0.0, ri = 0.0;
+            if (x < l && y < l) {
+                if (y >= x) r = M[x * ldm + y] * inv_r[x];
+                if (x <= y) ri = (x == y) ? inv_r[y] : M[y * ldm + x] * inv_r[y];
+            }
+            R[idx] = r;
+            Rinv[idx] = ri;
+        }
     }
     if (tid == 0) {
         if (mode == 2) {
@@ -188,22 +282,26 @@ __global__ __launch_bounds__(1024) void chol_kernel(const double* __restrict__ G
     }
 }
 
-hipError_t launch_chol(const double* G, int l, int L, double* R, double* Rinv, DevFlags* flags, int mode,
-                       double* shift_out, double* work, hipStream_t s) {
+hipError_t launch_chol(const double* partials, int64_t rows, int l, int L, double* R, double* Rinv, DevFlags* flags,
+                       int mode, double* shift_out, double* work, double tau, hipStream_t s) {
+    const int nchunks = gram_chunks(rows);
     if (l <= kCholLdsMax)
-        hipLaunchKernelGGL(chol_kernel<true>, dim3(1), dim3(1024), 0, s, G, l, L, R, Rinv, flags, mode, shift_out,
-                           work);
+        hipLaunchKernelGGL(chol_kernel<true>, dim3(1), dim3(1024), 0, s, partials, nchunks, l, L, R, Rinv, flags, mode,
+                           shift_out, work, tau);
     else
-        hipLaunchKernelGGL(chol_kernel<false>, dim3(1), dim3(1024), 0, s, G, l, L, R, Rinv, flags, mode, shift_out,
-                           work);
+        hipLaunchKernelGGL(chol_kernel<false>, dim3(1), dim3(1024), 0, s, partials, nchunks, l, L, R, Rinv, flags,
+                           mode, shift_out, work, tau);
     return hipGetLastError();
 }
 
 // --------------------------------------------------------------- apply --
-// out = in * M with FP64 accumulation: the CholeskyQR products Y R^{-1}, and
-// the lifts U = Q U~ and V = B^T U~ Sigma^{-1}.  A workgroup owns 32 rows;
-// thread (rg, cg) owns rows 2rg, 2rg+1 and output columns cg + 16c.  Inner
-// dimension staged through LDS 16 at a time.
+// out = in * M with FP64 arithmetic on FP64 MFMA (16x16x4): the CholeskyQR
+// products Y R^{-1}, and the lifts U = Q U~ and V = B^T U~ Sigma^{-1}.  A
+// workgroup owns 32 rows; wavefront w owns row block w & 1 and the column
+// tiles t = (w >> 1), (w >> 1) + 2, ...  The inner dimension is staged
+// through LDS 16 at a time with a one-slice register prefetch.  With `upper`
+// set, M is upper triangular and the zero blocks below its diagonal are
+// skipped.
 constexpr int kApplyRows = 32;
 int apply_blocks(int64_t rows) { return (int)ceil_div(rows, kApplyRows); }
 
@@ -212,57 +310,81 @@ __global__ __launch_bounds__(256) void apply_kernel(const T* __restrict__ in, in
                                                     const double* __restrict__ M, int ldm, int ncols_out,
                                                     T* __restrict__ out, int64_t ldo, int transpose_out,
                                                     const double* __restrict__ colscale, const DevFlags* skip,
-                                                    double* __restrict__ amax_val, int* __restrict__ amax_idx) {
+                                                    double* __restrict__ amax_val, int* __restrict__ amax_idx,
+                                                    int upper) {
     if (skip && skip->orth_fail) return;
+    constexpr int W = CT * 16;
+    constexpr int NTW = (CT + 1) / 2;                  // column tiles per wavefront
+    constexpr int NM = (16 * W + 255) / 256;           // M elements per thread per slice
     __shared__ double inS[kApplyRows][17];
-    __shared__ double MS[16][CT * 16 + 1];
-    const int tid = threadIdx.x, rg = tid >> 4, cg = tid & 15;
+    __shared__ double MS[16][W + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int rb = 16 * (wave & 1), tw = wave >> 1;
     const int64_t row0 = (int64_t)blockIdx.x * kApplyRows;
-    double acc0[CT], acc1[CT];
+    doublex4 acc[NTW];
 #pragma unroll
-    for (int c = 0; c < CT; ++c) { acc0[c] = 0.0; acc1[c] = 0.0; }
+    for (int j = 0; j < NTW; ++j) acc[j] = doublex4{0, 0, 0, 0};
+    double pin[2], pm[NM];
+    auto fetch = [&](int a0) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int idx = tid + 256 * u, rr = idx >> 4, aa = idx & 15;
+            const int64_t row = row0 + rr;
+            pin[u] = (row < rows && a0 + aa < L) ? (double)in[row * ldi + a0 + aa] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < NM; ++u) {
+            const int idx = tid + 256 * u, aa = idx / W, cc = idx % W;
+            pm[u] = (idx < 16 * W && a0 + aa < L && cc < ncols_out) ? M[(int64_t)(a0 + aa) * ldm + cc] : 0.0;
+        }
+    };
+    fetch(0);
     for (int a0 = 0; a0 < L; a0 += 16) {
         __syncthreads();
-        for (int idx = tid; idx < kApplyRows * 16; idx += 256) {
-            const int rr = idx >> 4, aa = idx & 15;
-            const int64_t row = row0 + rr;
-            inS[rr][aa] = (row < rows && a0 + aa < L) ? (double)in[row * ldi + a0 + aa] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int idx = tid + 256 * u;
+            inS[idx >> 4][idx & 15] = pin[u];
         }
-        for (int idx = tid; idx < 16 * CT * 16; idx += 256) {
-            const int aa = idx / (CT * 16), cc = idx % (CT * 16);
-            MS[aa][cc] = (a0 + aa < L && cc < ncols_out) ? M[(int64_t)(a0 + aa) * ldm + cc] : 0.0;
+#pragma unroll
+        for (int u = 0; u < NM; ++u) {
+            const int idx = tid + 256 * u;
+            if (idx < 16 * W) MS[idx / W][idx % W] = pm[u];
         }
         __syncthreads();
+        if (a0 + 16 < L) fetch(a0 + 16);
 #pragma unroll
-        for (int aa = 0; aa < 16; ++aa) {
-            const double x0 = inS[2 * rg][aa], x1 = inS[2 * rg + 1][aa];
+        for (int kk = 0; kk < 16; kk += 4) {
+            const double av_ = inS[rb + li][kk + lk];
 #pragma unroll
-            for (int c = 0; c < CT; ++c) {
-                const double mv = MS[aa][cg + 16 * c];
-                acc0[c] = fma(x0, mv, acc0[c]);
-                acc1[c] = fma(x1, mv, acc1[c]);
+            for (int j = 0; j < NTW; ++j) {
+                const int t = tw + 2 * j;
+                if (t >= CT) continue;
+                if (upper && a0 >= 16 * (t + 1)) continue;
+                acc[j] = mfma16x16x4(av_, MS[kk + lk][16 * t + li], acc[j]);
             }
         }
     }
-    extern __shared__ double av_dyn[];          // kApplyRows x (CT * 16 + 1), argmax only
-    auto av = [&](int rr, int col) -> double& { return av_dyn[rr * (CT * 16 + 1) + col]; };
-    const int64_t ra = row0 + 2 * rg, rb = ra + 1;
+    extern __shared__ double av_dyn[];          // kApplyRows x (W + 1), argmax only
+    auto avs = [&](int rr, int col) -> double& { return av_dyn[rr * (W + 1) + col]; };
 #pragma unroll
-    for (int c = 0; c < CT; ++c) {
-        const int col = cg + 16 * c;
+    for (int j = 0; j < NTW; ++j) {
+        const int t = tw + 2 * j;
+        if (t >= CT) continue;
+        const int col = 16 * t + li;
         if (col >= ncols_out) continue;
         const double sc = colscale ? colscale[col] : 1.0;
-        const T v0 = (T)(acc0[c] * sc), v1 = (T)(acc1[c] * sc);
-        if (!transpose_out) {
-            if (ra < rows) out[ra * ldo + col] = v0;
-            if (rb < rows) out[rb * ldo + col] = v1;
-        } else {
-            if (ra < rows) out[(int64_t)col * ldo + ra] = v0;
-            if (rb < rows) out[(int64_t)col * ldo + rb] = v1;
-        }
-        if (amax_val) {
-            av(2 * rg, col) = (ra < rows) ? (double)v0 : 0.0;
-            av(2 * rg + 1, col) = (rb < rows) ? (double)v1 : 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int rr = rb + acc_row<double>(lk, v);
+            const int64_t row = row0 + rr;
+            const T val = (T)(acc[j][v] * sc);
+            if (row < rows) {
+                if (!transpose_out) out[row * ldo + col] = val;
+                else out[(int64_t)col * ldo + row] = val;
+            }
+            if (amax_val) avs(rr, col) = (row < rows) ? (double)val : 0.0;
         }
     }
     if (!amax_val) return;
@@ -271,7 +393,7 @@ __global__ __launch_bounds__(256) void apply_kernel(const T* __restrict__ in, in
         double best = -1.0, val = 0.0;
         int bi = 0;
         for (int rr = 0; rr < kApplyRows; ++rr)      // lowest row wins ties
-            if (fabs(av(rr, col)) > best) { best = fabs(av(rr, col)); val = av(rr, col); bi = rr; }
+            if (fabs(avs(rr, col)) > best) { best = fabs(avs(rr, col)); val = avs(rr, col); bi = rr; }
         amax_val[(int64_t)blockIdx.x * ncols_out + col] = val;
         amax_idx[(int64_t)blockIdx.x * ncols_out + col] = (int)(row0 + bi);
     }
@@ -280,12 +402,12 @@ __global__ __launch_bounds__(256) void apply_kernel(const T* __restrict__ in, in
 template <typename T>
 static hipError_t apply_dispatch(int CT, dim3 grid, hipStream_t s, const T* in, int64_t ldi, int64_t rows, int L,
                                  const double* M, int ldm, int ncols_out, T* out, int64_t ldo, int tr,
-                                 const double* colscale, const DevFlags* skip, double* av, int* ai) {
+                                 const double* colscale, const DevFlags* skip, double* av, int* ai, int upper) {
 #define RSVD_CT_CASE(N)                                                                                         \
     case N:                                                                                                     \
         hipLaunchKernelGGL((apply_kernel<T, N>), grid, dim3(256),                                               \
                            av ? (size_t)kApplyRows * (N * 16 + 1) * sizeof(double) : 0, s, in, ldi, rows, L, M,  \
-                           ldm, ncols_out, out, ldo, tr, colscale, skip, av, ai);                               \
+                           ldm, ncols_out, out, ldo, tr, colscale, skip, av, ai, upper);                        \
         break;
     switch (CT) {
         RSVD_CT_CASE(1) RSVD_CT_CASE(2) RSVD_CT_CASE(3) RSVD_CT_CASE(4) RSVD_CT_CASE(5) RSVD_CT_CASE(6)
@@ -299,15 +421,15 @@ static hipError_t apply_dispatch(int CT, dim3 grid, hipStream_t s, const T* in, 
 
 hipError_t launch_apply(int dtype, const void* in, int64_t ldi, int64_t rows, int L, const double* M, int ldm,
                         int ncols_out, void* out, int64_t ldo, int transpose_out, const double* colscale,
-                        const DevFlags* skip, double* av, int* ai, hipStream_t s) {
+                        const DevFlags* skip, double* av, int* ai, int upper, hipStream_t s) {
     if (rows == 0 || ncols_out == 0) return hipSuccess;
     const int CT = (int)ceil_div(ncols_out, 16);
     dim3 grid(apply_blocks(rows));
     if (dtype == 0)
         return apply_dispatch<double>(CT, grid, s, (const double*)in, ldi, rows, L, M, ldm, ncols_out, (double*)out,
-                                      ldo, transpose_out, colscale, skip, av, ai);
+                                      ldo, transpose_out, colscale, skip, av, ai, upper);
     return apply_dispatch<float>(CT, grid, s, (const float*)in, ldi, rows, L, M, ldm, ncols_out, (float*)out, ldo,
-                                 transpose_out, colscale, skip, av, ai);
+                                 transpose_out, colscale, skip, av, ai, upper);
 }
 
 // ---------------------------------------------------------- Householder --

@@ -57,7 +57,7 @@ struct Plan {
     int L = 0;
     int ncounters = 0;
     int splits_nn = 1, splits_tn = 1;
-    size_t counters, flags, part, Y, Q, W, Q1, GP, G, R, Rinv, Ut, Mv, sigma, shift, sign, amax_val, amax_idx, H, Qw,
+    size_t counters, flags, part, Y, Q, W, Q1, GP, R, Rinv, Ut, Mv, sigma, shift, sign, amax_val, amax_idx, H, Qw,
         work, res_part, res;
     size_t total;
 };
@@ -73,7 +73,7 @@ bool make_plan(int dtype, int64_t m, int64_t n, int64_t k, int64_t p, int64_t q,
     const size_t es = esize(dtype);
     const size_t pn = gemm_partials_elems(dtype, m, n, P.L, &P.splits_nn);
     const size_t pt = gemm_partials_elems(dtype, n, m, P.L, &P.splits_tn);
-    P.ncounters = std::max({gemm_row_tiles(dtype, mx), gram_pairs(P.L), 1});
+    P.ncounters = 1;
     Carver c;
     P.counters = c.take(sizeof(int) * (size_t)P.ncounters);
     P.flags = c.take(sizeof(DevFlags));
@@ -83,7 +83,6 @@ bool make_plan(int dtype, int64_t m, int64_t n, int64_t k, int64_t p, int64_t q,
     P.W = c.take(es * (size_t)n * P.L);
     P.Q1 = c.take(es * (size_t)mx * P.L);
     P.GP = c.take(sizeof(double) * gram_partials_elems(mx, P.L));
-    P.G = c.take(sizeof(double) * (size_t)P.L * P.L);
     P.R = c.take(sizeof(double) * (size_t)P.L * P.L);
     P.Rinv = c.take(sizeof(double) * (size_t)P.L * P.L);
     P.Ut = c.take(sizeof(double) * (size_t)P.L * P.L);
@@ -95,7 +94,7 @@ bool make_plan(int dtype, int64_t m, int64_t n, int64_t k, int64_t p, int64_t q,
     P.amax_idx = c.take(sizeof(int) * (size_t)apply_blocks(n) * P.L);
     P.H = c.take(sizeof(double) * (size_t)mx * P.L);
     P.Qw = c.take(sizeof(double) * (size_t)mx * P.L);
-    P.work = c.take(sizeof(double) * (size_t)P.L * P.L);
+    P.work = c.take(sizeof(double) * (size_t)kMaxL * kMaxL);
     P.res_part = c.take(sizeof(double) * residual_partials(m, n));
     P.res = c.take(sizeof(double) * 2);
     P.total = c.off;
@@ -118,20 +117,19 @@ rsvd_status run_orth(const Plan& P, void* ws, int dtype, int64_t rows, const voi
                      hipStream_t s) {
     const int L = P.L, l = (int)P.l;
     DevFlags* flags = at<DevFlags>(ws, P.flags);
-    int* cnt = at<int>(ws, P.counters);
-    double* G = at<double>(ws, P.G);
     double* R = at<double>(ws, P.R);
     double* Rinv = at<double>(ws, P.Rinv);
     double* GP = at<double>(ws, P.GP);
     double* work = at<double>(ws, P.work);
     void* Q1 = at<char>(ws, P.Q1);
     if (!force_hh) {
-        RSVD_TRY(launch_gram(dtype, Y, L, rows, L, G, GP, cnt, nullptr, s));
-        RSVD_TRY(launch_chol(G, l, L, R, Rinv, flags, 0, nullptr, work, s));
-        RSVD_TRY(launch_apply(dtype, Y, L, rows, L, Rinv, L, L, Q1, L, 0, nullptr, flags, nullptr, nullptr, s));
-        RSVD_TRY(launch_gram(dtype, Q1, L, rows, L, G, GP, cnt, flags, s));
-        RSVD_TRY(launch_chol(G, l, L, R, Rinv, flags, 1, nullptr, work, s));
-        RSVD_TRY(launch_apply(dtype, Q1, L, rows, L, Rinv, L, L, Qout, L, 0, nullptr, flags, nullptr, nullptr, s));
+        RSVD_TRY(launch_gram(dtype, Y, L, rows, L, GP, nullptr, s));
+        RSVD_TRY(launch_chol(GP, rows, l, L, R, Rinv, flags, 0, nullptr, work, 0.0, s));
+        RSVD_TRY(launch_apply(dtype, Y, L, rows, L, Rinv, L, L, Q1, L, 0, nullptr, flags, nullptr, nullptr, 1, s));
+        RSVD_TRY(launch_gram(dtype, Q1, L, rows, L, GP, flags, s));
+        RSVD_TRY(launch_chol(GP, rows, l, L, R, Rinv, flags, 1, nullptr, work,
+                             dtype == RSVD_F64 ? 0x1.0p-26 : 0x1.0p-13, s));
+        RSVD_TRY(launch_apply(dtype, Q1, L, rows, L, Rinv, L, L, Qout, L, 0, nullptr, flags, nullptr, nullptr, 1, s));
     }
     RSVD_TRY(launch_householder(dtype, Y, L, rows, l, L, Qout, L, at<double>(ws, P.H), at<double>(ws, P.Qw), flags,
                                 force_hh, s));
@@ -154,7 +152,6 @@ rsvd_status run_gemm(rsvd_handle* h, const Plan& P, void* ws, const rsvd_matrix*
     g.Y = Yout;
     g.ldy = P.L;
     g.partials = at<char>(ws, P.part);
-    g.counters = at<int>(ws, P.counters);
     g.splits = trans ? P.splits_tn : P.splits_nn;
     rsvd_handle::Rec rec{trans ? 2 : (X ? 1 : 0), nullptr, nullptr};
     if (h->profiling) {
@@ -311,7 +308,6 @@ rsvd_status rsvd_solve(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* 
     // Stage 2: step 6 as B^T = A^T Q (n x l), step 7 small SVD, step 8 lift.
     if ((st = run_gemm(h, P, ws, A, 1, Q, 0, Y, s)) != RSVD_OK) return st;
     const void* Bt = Y;
-    double* G = at<double>(ws, P.G);
     double* R = at<double>(ws, P.R);
     double* sigma = at<double>(ws, P.sigma);
     double* sign = at<double>(ws, P.sign);
@@ -321,18 +317,19 @@ rsvd_status rsvd_solve(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* 
     double* av = at<double>(ws, P.amax_val);
     int* ai = at<int>(ws, P.amax_idx);
     const int r = (int)P.r;
-    RSVD_TRY(launch_gram(dt, Bt, L, P.n, L, G, at<double>(ws, P.GP), cnt, nullptr, s));
-    RSVD_TRY(launch_chol(G, (int)P.l, L, R, at<double>(ws, P.Rinv), flags, 2, shift, at<double>(ws, P.work), s));
+    RSVD_TRY(launch_gram(dt, Bt, L, P.n, L, at<double>(ws, P.GP), nullptr, s));
+    RSVD_TRY(launch_chol(at<double>(ws, P.GP), P.n, (int)P.l, L, R, at<double>(ws, P.Rinv), flags, 2, shift,
+                         at<double>(ws, P.work), 0.0, s));
     RSVD_TRY(launch_jacobi(R, (int)P.l, L, shift, sigma, Ut, Mv, flags, at<double>(ws, P.work), s));
     // V = B^T U~ Sigma^{-1}, written transposed into Vt, with column argmax partials.
-    RSVD_TRY(launch_apply(dt, Bt, L, P.n, L, Mv, L, r, out->Vt, out->ldvt, 1, nullptr, nullptr, av, ai, s));
+    RSVD_TRY(launch_apply(dt, Bt, L, P.n, L, Mv, L, r, out->Vt, out->ldvt, 1, nullptr, nullptr, av, ai, 0, s));
     RSVD_TRY(launch_signs(av, ai, apply_blocks(P.n), r, sigma, out->S, sign, s));
     // U = Q U~ (top r columns), signs folded in; then the signs of Vt's rows.
-    RSVD_TRY(launch_apply(dt, Q, L, P.m, L, Ut, L, r, out->U, out->ldu, 0, sign, nullptr, nullptr, nullptr, s));
+    RSVD_TRY(launch_apply(dt, Q, L, P.m, L, Ut, L, r, out->U, out->ldu, 0, sign, nullptr, nullptr, nullptr, 0, s));
     RSVD_TRY(launch_scale_rows(dt, out->Vt, out->ldvt, r, P.n, sign, s));
     if (out->Q) RSVD_TRY(launch_copy2d(dt, Q, L, P.m, (int)P.l, out->Q, out->ldq, (int)P.l, s));
     if (params->residual == 2)
-        RSVD_TRY(launch_residual_fro(dt, A->data, A->ld, P.m, P.n, Q, Bt, (int)P.l, L, at<double>(ws, P.res_part), cnt,
+        RSVD_TRY(launch_residual_fro(dt, A->data, A->ld, P.m, P.n, Q, Bt, (int)P.l, L, at<double>(ws, P.res_part),
                                      out->residual, s));
     RSVD_TRY(launch_export_info(flags, out->info, s));
     return RSVD_OK;
@@ -359,7 +356,7 @@ rsvd_status rsvd_gemm_workspace_size(const rsvd_matrix* A, int32_t trans, int64_
     if (!bytes || ncols < 1 || ncols > kMaxL) return RSVD_ERR_INVALID_ARG;
     const int64_t M = trans ? A->cols : A->rows, K = trans ? A->rows : A->cols;
     Carver c;
-    c.take(sizeof(int) * (size_t)gemm_row_tiles(A->dtype, M));
+    c.take(sizeof(int) * (size_t)gemm_row_tiles(A->dtype, M, (int)ncols));
     c.take(sizeof(DevFlags));
     c.take(esize(A->dtype) * std::max<size_t>(1, gemm_partials_elems(A->dtype, M, K, (int)ncols, nullptr)));
     *bytes = c.off;
@@ -381,16 +378,16 @@ rsvd_status rsvd_gemm(rsvd_handle* h, const rsvd_matrix* A, int32_t trans, const
     hipStream_t s = as_stream(stream);
     const int64_t M = trans ? A->cols : A->rows, K = trans ? A->rows : A->cols;
     Carver c;
-    const size_t o_cnt = c.take(sizeof(int) * (size_t)gemm_row_tiles(A->dtype, M));
+    const size_t o_cnt = c.take(sizeof(int) * (size_t)gemm_row_tiles(A->dtype, M, (int)ncols));
     const size_t o_flags = c.take(sizeof(DevFlags));
     const size_t o_part = c.take(0);
     int splits = 1;
     gemm_partials_elems(A->dtype, M, K, (int)ncols, &splits);
-    RSVD_TRY(launch_init(at<int>(ws, o_cnt), gemm_row_tiles(A->dtype, M), at<DevFlags>(ws, o_flags), s));
+    RSVD_TRY(launch_init(at<int>(ws, o_cnt), gemm_row_tiles(A->dtype, M, (int)ncols), at<DevFlags>(ws, o_flags), s));
     GemmArgs g{};
     g.A = A->data; g.lda = A->ld; g.trans = trans; g.M = M; g.K = K;
     g.X = X; g.ldx = ldx; g.seed = seed; g.ncols = (int)ncols; g.wcols = (int)ncols;
-    g.Y = Y; g.ldy = ldy; g.partials = at<char>(ws, o_part); g.counters = at<int>(ws, o_cnt); g.splits = splits;
+    g.Y = Y; g.ldy = ldy; g.partials = at<char>(ws, o_part); g.splits = splits;
     RSVD_TRY(launch_gemm(A->dtype, g, s));
     return RSVD_OK;
 }

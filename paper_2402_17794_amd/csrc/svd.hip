@@ -29,29 +29,44 @@ constexpr int kJacobiLdsMax = 128;
 constexpr double kJacobiTol = 1e-15;
 constexpr int kJacobiMaxSweeps = 60;
 
+// Sum over the 8 lanes of each eighth of a wavefront (xor 1, xor 2, then
+// lane i <-> 7 - i within each 8-lane half-row), result in all 8 lanes.
+__device__ __forceinline__ double octet_sum(double x) {
+    x += dpp_f64<dpp_quad_xor1>(x);
+    x += dpp_f64<dpp_quad_xor2>(x);
+    x += dpp_f64<dpp_half_mirror>(x);
+    return x;
+}
+
 // Round-robin (circle method) schedule: with n2 (even) columns, round r pairs
 // slot 0 with (n2 - 1, r) and slot s > 0 with ((r + s), (r - s)) mod (n2 - 1).
 __device__ __forceinline__ void rr_pair(int r, int s, int n2, int& p1, int& p2) {
     const int m = n2 - 1;
-    if (s == 0) { p1 = m; p2 = r; }
-    else { p1 = (r + s) % m; p2 = (r - s + m) % m; }
+    if (s == 0) { p1 = m; p2 = r; return; }
+    p1 = r + s; if (p1 >= m) p1 -= m;
+    p2 = r - s + m; if (p2 >= m) p2 -= m;
 }
 
-template <int RPL, bool IN_LDS>
+// One-sided Jacobi on X = R^T; 8 lanes per column pair.  Columns are stored
+// with a padded stride (zero rows past l stay zero under rotations), so
+// every lane loads and stores its rows 2e, 2e+1, 2e+16, 2e+17, ... as 16-byte
+// pairs without bounds checks.  NP = row pairs per lane.
+template <int NP, bool IN_LDS>
 __global__ __launch_bounds__(1024) void jacobi_kernel(const double* __restrict__ R, int l, int L,
                                                       const double* __restrict__ shift_p, double* __restrict__ sigma,
                                                       double* __restrict__ Ut, double* __restrict__ Mv,
                                                       DevFlags* flags, double* __restrict__ work) {
-    __shared__ double lds[IN_LDS ? kJacobiLdsMax * kJacobiLdsMax : 1];
+    __shared__ __attribute__((aligned(16))) double lds[IN_LDS ? kJacobiLdsMax * kJacobiLdsMax : 2];
     __shared__ int rotated;
     __shared__ double nrm2[kMaxL];
     __shared__ int rank_of[kMaxL];
-    double* X = IN_LDS ? lds : work;           // column-major, X[c * l + r] = R[c][r]
-    const int tid = threadIdx.x, q = tid >> 4, e = tid & 15;
+    const int ld = IN_LDS ? kJacobiLdsMax : kMaxL;  // column stride (>= 16 * NP rows)
+    double* X = IN_LDS ? lds : work;                // X[c * ld + r] = R[c][r], zero for r >= l
+    const int tid = threadIdx.x, grp = tid >> 3, e = tid & 7;
 
-    for (int idx = tid; idx < l * l; idx += 1024) {
-        const int c = idx / l, r = idx % l;
-        X[idx] = R[(int64_t)c * L + r];
+    for (int idx = tid; idx < l * ld; idx += 1024) {
+        const int c = idx / ld, r = idx - c * ld;
+        X[idx] = r < l ? R[(int64_t)c * L + r] : 0.0;
     }
     const int n2 = l + (l & 1);
     bool converged = (l < 2);
@@ -60,36 +75,44 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const double* __restrict__
         if (tid == 0) rotated = 0;
         __syncthreads();
         for (int r = 0; r < n2 - 1; ++r) {
-            for (int s = q; s < n2 / 2; s += 64) {
+            for (int s = grp; s < n2 / 2; s += 128) {
                 int p1, p2;
                 rr_pair(r, s, n2, p1, p2);
                 if (p1 >= l || p2 >= l) continue;
                 const int i = min(p1, p2), j = max(p1, p2);
-                double xi[RPL], xj[RPL];
+                double2* xi_p = reinterpret_cast<double2*>(X + i * ld) + e;
+                double2* xj_p = reinterpret_cast<double2*>(X + j * ld) + e;
+                double2 xi[NP], xj[NP];
                 double a = 0.0, b = 0.0, g = 0.0;
 #pragma unroll
-                for (int t = 0; t < RPL; ++t) {
-                    const int row = e + 16 * t;
-                    xi[t] = row < l ? X[i * l + row] : 0.0;
-                    xj[t] = row < l ? X[j * l + row] : 0.0;
-                    a = fma(xi[t], xi[t], a);
-                    b = fma(xj[t], xj[t], b);
-                    g = fma(xi[t], xj[t], g);
+                for (int t = 0; t < NP; ++t) {
+                    xi[t] = xi_p[8 * t];
+                    xj[t] = xj_p[8 * t];
                 }
-                a = quarter_sum(a);
-                b = quarter_sum(b);
-                g = quarter_sum(g);
+#pragma unroll
+                for (int t = 0; t < NP; ++t) {
+                    a = fma(xi[t].x, xi[t].x, a); a = fma(xi[t].y, xi[t].y, a);
+                    b = fma(xj[t].x, xj[t].x, b); b = fma(xj[t].y, xj[t].y, b);
+                    g = fma(xi[t].x, xj[t].x, g); g = fma(xi[t].y, xj[t].y, g);
+                }
+                a = octet_sum(a);
+                b = octet_sum(b);
+                g = octet_sum(g);
                 if (fabs(g) > kJacobiTol * sqrt(a * b)) {
                     const double zeta = (b - a) / (2.0 * g);
-                    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+                    const double az = fabs(zeta);
+                    double t = az > 1e150 ? 0.5 / az : 1.0 / (az + sqrt(1.0 + az * az));
+                    t = zeta >= 0.0 ? t : -t;
                     const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
 #pragma unroll
-                    for (int u = 0; u < RPL; ++u) {
-                        const int row = e + 16 * u;
-                        if (row < l) {
-                            X[i * l + row] = c * xi[u] - sn * xj[u];
-                            X[j * l + row] = sn * xi[u] + c * xj[u];
-                        }
+                    for (int u = 0; u < NP; ++u) {
+                        double2 ni, nj;
+                        ni.x = c * xi[u].x - sn * xj[u].x;
+                        ni.y = c * xi[u].y - sn * xj[u].y;
+                        nj.x = sn * xi[u].x + c * xj[u].x;
+                        nj.y = sn * xi[u].y + c * xj[u].y;
+                        xi_p[8 * u] = ni;
+                        xj_p[8 * u] = nj;
                     }
                     if (e == 0) rotated = 1;
                 }
@@ -102,10 +125,10 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const double* __restrict__
     }
     if (!converged && tid == 0) atomicOr(&flags->info, RSVD_INFO_JACOBI_NOT_CONVERGED);
 
-    for (int c = q; c < l; c += 64) {
+    for (int c = grp; c < l; c += 128) {
         double s2 = 0.0;
-        for (int row = e; row < l; row += 16) s2 = fma(X[c * l + row], X[c * l + row], s2);
-        s2 = quarter_sum(s2);
+        for (int row = e; row < l; row += 8) s2 = fma(X[c * ld + row], X[c * ld + row], s2);
+        s2 = octet_sum(s2);
         if (e == 0) nrm2[c] = s2;
     }
     __syncthreads();
@@ -128,10 +151,10 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const double* __restrict__
     }
     __syncthreads();
     for (int idx = tid; idx < l * l; idx += 1024) {
-        const int c = idx / l, row = idx % l;
+        const int c = idx / l, row = idx - c * l;
         const double nc = sqrt(nrm2[c]);
         const double sc = sqrt(fmax(nrm2[c] - shift, 0.0));
-        const double u = nc > 0.0 ? X[c * l + row] / nc : (row == c ? 1.0 : 0.0);
+        const double u = nc > 0.0 ? X[c * ld + row] / nc : (row == c ? 1.0 : 0.0);
         const int col = rank_of[c];
         Ut[(int64_t)row * L + col] = u;
         Mv[(int64_t)row * L + col] = sc > 0.0 ? u / sc : 0.0;
@@ -141,8 +164,8 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const double* __restrict__
 hipError_t launch_jacobi(const double* R, int l, int L, const double* shift, double* sigma, double* Ut, double* Mv,
                          DevFlags* flags, double* work, hipStream_t s) {
     if (l <= kJacobiLdsMax)
-        hipLaunchKernelGGL((jacobi_kernel<kJacobiLdsMax / 16, true>), dim3(1), dim3(1024), 0, s, R, l, L, shift, sigma,
-                           Ut, Mv, flags, work);
+        hipLaunchKernelGGL((jacobi_kernel<kJacobiLdsMax / 16, true>), dim3(1), dim3(1024), 0, s, R, l, L, shift,
+                           sigma, Ut, Mv, flags, work);
     else
         hipLaunchKernelGGL((jacobi_kernel<kMaxL / 16, false>), dim3(1), dim3(1024), 0, s, R, l, L, shift, sigma, Ut,
                            Mv, flags, work);
@@ -150,25 +173,41 @@ hipError_t launch_jacobi(const double* R, int l, int L, const double* shift, dou
 }
 
 // Signs: for each returned column c of V, the entry of largest magnitude
-// (lowest row on ties) is made positive.  Block partials arrive in row order.
-__global__ void signs_kernel(const double* __restrict__ av, const int* __restrict__ ai, int nblocks, int r,
-                             const double* __restrict__ sigma, double* __restrict__ S_out, double* __restrict__ sign) {
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < r; c += gridDim.x * blockDim.x) {
-        double best = -1.0, val = 0.0;
-        for (int b = 0; b < nblocks; ++b) {
-            const double v = av[(int64_t)b * r + c];
-            if (fabs(v) > best) { best = fabs(v); val = v; }
+// (lowest row on ties) is made positive.  One workgroup per column reduces
+// the per-block partials, which are in row order.
+__global__ __launch_bounds__(256) void signs_kernel(const double* __restrict__ av, const int* __restrict__ ai,
+                                                   int nblocks, int r, const double* __restrict__ sigma,
+                                                   double* __restrict__ S_out, double* __restrict__ sign) {
+    (void)ai;
+    const int c = blockIdx.x, tid = threadIdx.x;
+    __shared__ double bm[256], bv[256];
+    __shared__ int bb[256];
+    double best = -1.0, val = 0.0;
+    int bestb = 0x7fffffff;
+    for (int b = tid; b < nblocks; b += 256) {      // increasing b: strict > keeps the lowest block
+        const double v = av[(int64_t)b * r + c];
+        if (fabs(v) > best) { best = fabs(v); val = v; bestb = b; }
+    }
+    bm[tid] = best; bv[tid] = val; bb[tid] = bestb;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (tid < off) {
+            const double m2 = bm[tid + off];
+            const int b2 = bb[tid + off];
+            if (m2 > bm[tid] || (m2 == bm[tid] && b2 < bb[tid])) { bm[tid] = m2; bv[tid] = bv[tid + off]; bb[tid] = b2; }
         }
-        (void)ai;
-        sign[c] = val < 0.0 ? -1.0 : 1.0;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        sign[c] = bv[0] < 0.0 ? -1.0 : 1.0;
         S_out[c] = sigma[c];
     }
 }
 
 hipError_t launch_signs(const double* av, const int* ai, int nblocks, int r, const double* sigma, double* S_out,
                         double* sign, hipStream_t s) {
-    hipLaunchKernelGGL(signs_kernel, dim3((unsigned)ceil_div(r, 256)), dim3(256), 0, s, av, ai, nblocks, r, sigma,
-                       S_out, sign);
+    if (r == 0) return hipSuccess;
+    hipLaunchKernelGGL(signs_kernel, dim3(r), dim3(256), 0, s, av, ai, nblocks, r, sigma, S_out, sign);
     return hipGetLastError();
 }
 
@@ -238,8 +277,8 @@ namespace rsvd {
 
 // ||A - Q B||_F for the error measure of Theorems 2, 3, 6 (Frobenius form):
 // each workgroup forms a 64 x 64 tile of E = A - Q (B^T)^T in FP64 from the
-// stored Q and B^T, sums its squares, and the last workgroup (device-scope
-// counter) adds the tile sums in tile order.
+// stored Q and B^T and writes the sum of its squares; a second kernel adds
+// the tile sums in a fixed order.
 constexpr int kResTile = 64;
 
 size_t residual_partials(int64_t m, int64_t n) {
@@ -249,8 +288,7 @@ size_t residual_partials(int64_t m, int64_t n) {
 template <typename T>
 __global__ __launch_bounds__(256) void residual_fro_kernel(const T* __restrict__ A, int64_t lda, int64_t m, int64_t n,
                                                            const T* __restrict__ Q, const T* __restrict__ Bt, int L,
-                                                           double* __restrict__ part, int* __restrict__ cnt,
-                                                           double* __restrict__ out) {
+                                                           double* __restrict__ part) {
     __shared__ double Qs[16][kResTile + 1];
     __shared__ double Bs[16][kResTile + 1];
     __shared__ double red[4];
@@ -287,33 +325,36 @@ __global__ __launch_bounds__(256) void residual_fro_kernel(const T* __restrict__
         }
     s = block_sum(s, red);
     if (tid == 0) part[blockIdx.x] = s;
-    __threadfence();
-    __syncthreads();
-    __shared__ int last;
-    if (tid == 0) last = (atomicAdd(cnt, 1) == (int)gridDim.x - 1);
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    if (tid == 0) {
-        double t = 0.0;
-        for (unsigned b = 0; b < gridDim.x; ++b) t += part[b];
+}
+
+// Sum of the tile partials in a fixed order (thread-strided, then the block
+// sum in wave order), and the square root.
+__global__ __launch_bounds__(256) void residual_final_kernel(const double* __restrict__ part, int64_t n,
+                                                             double* __restrict__ out) {
+    __shared__ double red[4];
+    double t = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) t += part[i];
+    t = block_sum(t, red);
+    if (threadIdx.x == 0) {
         out[0] = 0.0;
         out[1] = sqrt(t);
-        *cnt = 0;
     }
 }
 
 hipError_t launch_residual_fro(int dtype, const void* A, int64_t lda, int64_t m, int64_t n, const void* Q,
-                               const void* Bt, int l, int L, double* partial, int* counter, double* out,
-                               hipStream_t s) {
+                               const void* Bt, int l, int L, double* partial, double* out, hipStream_t s) {
     (void)l;
-    dim3 grid((unsigned)residual_partials(m, n));
+    const int64_t ntiles = (int64_t)residual_partials(m, n);
+    dim3 grid((unsigned)ntiles);
     if (dtype == 0)
         hipLaunchKernelGGL(residual_fro_kernel<double>, grid, dim3(256), 0, s, (const double*)A, lda, m, n,
-                           (const double*)Q, (const double*)Bt, L, partial, counter, out);
+                           (const double*)Q, (const double*)Bt, L, partial);
     else
         hipLaunchKernelGGL(residual_fro_kernel<float>, grid, dim3(256), 0, s, (const float*)A, lda, m, n,
-                           (const float*)Q, (const float*)Bt, L, partial, counter, out);
+                           (const float*)Q, (const float*)Bt, L, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(residual_final_kernel, dim3(1), dim3(256), 0, s, partial, ntiles, out);
     return hipGetLastError();
 }
 

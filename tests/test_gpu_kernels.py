@@ -122,6 +122,20 @@ def test_orth_matches_householder_oracle(R, dtype, rows, l, force_hh):
     assert fell_back == force_hh
 
 
+def test_orth_ill_conditioned_fp64(R):
+    """kappa(Y) = 1e6: the second CholeskyQR pass is far from the identity
+    and takes the exact factorisation."""
+    rng = np.random.default_rng(5)
+    U, _ = np.linalg.qr(rng.standard_normal((2000, 40)))
+    V, _ = np.linalg.qr(rng.standard_normal((40, 40)))
+    Y = (U * np.logspace(0, -6, 40)) @ V.T
+    Q, info = R.orth(_cuda(Y, torch.float64))
+    Qg = Q.cpu().numpy()
+    assert info.item() == 0
+    assert _orth_err(Qg) <= 1e-13
+    assert np.max(np.abs(Qg - OL.householder_qr(Y)[0])) <= 1e-8
+
+
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_orth_rank_deficient_falls_back(R, dtype):
     rng = np.random.default_rng(11)

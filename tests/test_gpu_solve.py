@@ -78,7 +78,8 @@ def test_c1_fp64_512x256(R):
 
 @pytest.mark.parametrize("m,n,k,p,q,seed", [(1000, 600, 20, 10, 0, 0), (600, 1000, 25, 5, 1, 3),
                                             (777, 333, 50, 10, 2, 9), (2048, 2048, 50, 10, 1, 0),
-                                            (300, 3000, 100, 10, 2, 1), (129, 65, 60, 10, 1, 2)])
+                                            (300, 3000, 100, 10, 2, 1), (129, 65, 60, 10, 1, 2),
+                                            (1200, 400, 150, 10, 1, 5)])
 def test_fp32_solve_matches_oracle(R, m, n, k, p, q, seed):
     d = min(m, n)
     sig = W.spectrum_geometric(d, 0.95, 1e-6)
@@ -104,6 +105,20 @@ def test_fp32_solve_matches_oracle(R, m, n, k, p, q, seed):
     assert np.max(np.abs(Ua - ref["U"][:, idx])) <= 1e-3
     Va = _align(Vt[idx].T, ref["Vt"][idx].T)
     assert np.max(np.abs(Va - ref["Vt"][idx].T)) <= 1e-3
+
+
+def test_fp64_wide_l(R):
+    """l = 200 > 128: the Cholesky and Jacobi kernels run on their device-memory path."""
+    sig = W.spectrum_geometric(500, 0.97)
+    A = W.known_spectrum(900, 500, sig, 7, 8)
+    out = R.solve(torch.from_numpy(A).cuda(), k=190, p=10, q=0, seed=3)
+    torch.cuda.synchronize()
+    ref = rsvd_alg4(A, 190, 10, 0, seed=3)
+    assert np.max(np.abs(_np(out["S"]) - ref["S"])) <= 1e-12 * ref["S"][0]
+    U, Vt = _np(out["U"]), _np(out["Vt"])
+    idx = _separated(ref["S"], 1e-3)[:20]
+    assert np.max(np.abs(_align(U[:, idx], ref["U"][:, idx]) - ref["U"][:, idx])) <= 1e-8
+    assert np.max(np.abs(U.T @ U - np.eye(190))) <= 1e-12
 
 
 def test_exact_rank_fp64(R):
