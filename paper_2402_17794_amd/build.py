@@ -8,6 +8,7 @@ runtime; it has no dependency on torch.
 """
 
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -41,11 +42,26 @@ def _hipcc():
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     lang = ["-x", "hip"]
-    cmd = [_hipcc(), *lang, *COMMON_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    remarks = ["-Rpass-analysis=kernel-resource-usage"] if src.endswith(".hip") else []
+    cmd = [_hipcc(), *lang, *COMMON_FLAGS, *remarks, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {src}\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     return obj, r.stderr
+
+
+def _spills(remarks):
+    """Kernels whose registers spill to scratch memory, from the compiler's
+    kernel-resource-usage remarks: {kernel: scratch bytes per lane}."""
+    out, name = {}, None
+    for line in remarks.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+        m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
+        if m and name and int(m.group(1)) > 0:
+            out[name] = int(m.group(1))
+    return out
 
 
 def build(verbose=False):
@@ -53,10 +69,21 @@ def build(verbose=False):
     jobs = min(len(SOURCES), max(1, (os.cpu_count() or 4)))
     with ThreadPoolExecutor(jobs) as ex:
         results = list(ex.map(_compile, SOURCES))
-    if verbose:
-        for _, err in results:
-            if err.strip():
-                print(err, file=sys.stderr)
+    spills = {}
+    for _, err in results:
+        spills.update(_spills(err))
+        if verbose:
+            msgs = "\n".join(x for x in err.splitlines()
+                             if x.strip() and "remark:" not in x and not re.match(r"\s*\d*\s*\|", x))
+            if msgs:
+                print(msgs, file=sys.stderr)
+    with open(os.path.join(BUILD, "spills.txt"), "w") as f:
+        for k, v in sorted(spills.items()):
+            f.write(f"{k} {v}\n")
+    if spills:
+        # Register spills turn the single-workgroup kernels into scratch-bound code.
+        print("warning: kernels spill registers to scratch: " + ", ".join(f"{k} ({v} B/lane)" for k, v in spills.items()),
+              file=sys.stderr)
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *[o for o, _ in results]]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -282,222 +282,209 @@ __global__ __launch_bounds__(1024) void chol_kernel(const double* __restrict__ p
     }
 }
 
-// Blocked form for l <= 128 (the matrix lives in LDS).  Blocks of 16:
-// step J factors the diagonal block by one wavefront (Gauss-Jordan on
-// [D | I] in registers, one LDS row broadcast per column, no workgroup
-// barrier), then the whole workgroup forms the panel R_J,K = R_JJ^{-T} G_J,K,
-// the block column J of R^{-1} (X_IJ = -(sum_{I <= K < J} X_IK R_KJ) R_JJ^{-1})
-// and the trailing update G_KK' -= R_JK^T R_JK'.  Three barriers per block
-// instead of one per column.  Storage in M (LDS): upper triangle = R, strict
-// lower triangle = R^{-1} transposed (X[a][c] at M[c][a]), inv_r = 1 / r_aa;
-// rows and columns past l are padded with the identity.
-__global__ __launch_bounds__(1024) void chol_blocked_kernel(const double* __restrict__ part, int nchunks, int l,
-                                                            int L, double* __restrict__ R, double* __restrict__ Rinv,
-                                                            DevFlags* flags, int mode, double* shift_out, double tau) {
-    constexpr int LP = kCholLdsMax;
-    __shared__ double M[LP * LP];
-    __shared__ double T[7 * 256];               // T_IJ = sum_K X_IK R_KJ, I < J
-    __shared__ double inv_r[LP];
-    __shared__ double dg[LP];
-    __shared__ double rowp[32];
-    __shared__ int s_broke;
-    __shared__ unsigned long long s_emax;
-    if (mode == 1 && flags->orth_fail) return;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int nt = L / 16, npairs = nt * (nt + 1) / 2;
-    const int nb = (l + 15) / 16, lp = 16 * nb;
+// Form for l <= 128: right-looking LDL^T elimination of the augmented
+// matrix [G | I], one workgroup barrier per pivot, with the working matrix in
+// registers.  With G = L D L^T the elimination turns [G | I] into
+// [D L^T | L^{-1}], and row j is final once pivot j is reached, so
+//   R = D^{1/2} L^T (upper, from the left half),
+//   R^{-1} = L^{-T} D^{-1/2} (from the lower triangle of the right half).
+// The left half is held as 8 x 8 tiles on and above the block diagonal, the
+// right half as 8 x 8 tiles on and below it, one tile per thread.  Pivot row j
+// updates row r > j as  row_r -= (G'_jr / d_j) row_j  over whole tiles with
+// no per-element test: entries below the diagonal of the left half are
+// never read into a result, and the right half of pivot row j is exactly
+// zero past column j.  After step j the owners of row j + 1 publish it to
+// LDS, where it is the pivot row of the next step and, at the end, the output.
+// Packed LDS row r: slot s = right column s (s <= r) or left column s - 1
+// (s > r); a tile publishes its whole row with unconditional stores, so the
+// right half of each diagonal block goes to a separate array RD (the left
+// diagonal tile's unused entries land in the packed slots it shadows).
+constexpr int kCholThreads = 512;
+constexpr int kCholT = 6;                         // tile edge: 2 * nb (nb + 1) / 2 <= 512 threads for l <= 128
 
+__global__ __launch_bounds__(kCholThreads) void chol_rl_kernel(const double* __restrict__ part, int nchunks, int l,
+                                                               int L, double* __restrict__ R,
+                                                               double* __restrict__ Rinv, DevFlags* flags, int mode,
+                                                               double* shift_out, double tau) {
+    constexpr int T = kCholT, NBM = (kCholLdsMax + kCholT - 1) / kCholT;
+    // Row stride: slots up to NBM * T (the padded tile columns), odd for bank spread.
+    constexpr int LP = NBM * T + 1;
+    static_assert(LP > kCholLdsMax && (LP & 1), "LDS row stride");
+    __shared__ double P[kCholLdsMax * LP];        // G (upper triangle) on entry, then the packed pivot rows
+    __shared__ double RD[NBM * T * T];            // right half of the diagonal blocks: RD[blk][a][b]
+    __shared__ double dg[kCholLdsMax];
+    __shared__ double isd[kCholLdsMax];           // D_j^{-1/2}
+    __shared__ unsigned long long s_emax;
+    __shared__ int s_nonfinite;
+    if (mode == 1 && flags->orth_fail) return;
+    const int tid = threadIdx.x;
+    const int nt = L / 16, npairs = nt * (nt + 1) / 2, stride = npairs * 256;
+    // Tile of this thread: tid < ntri -> left tile (bi, bj), bj >= bi; then right tile (bi, bj), bj <= bi.
+    const int nb = (l + T - 1) / T, ntri = nb * (nb + 1) / 2;
+    const bool owner = tid < 2 * ntri;
+    const bool left = tid < ntri;
+    int bi = 0, bj = 0;
+    {
+        int q = left ? tid : tid - ntri;
+        if (!owner) q = 0;
+        while (q >= nb - bi) { q -= nb - bi; ++bi; }      // row-major enumeration of the upper block triangle
+        bj = bi + q;
+        if (!left) { const int t = bi; bi = bj; bj = t; }
+    }
+    const int r0 = bi * T, c0 = bj * T;
+
+    // Sum the chunk partials in chunk order into the upper triangle of G.
+    // Addresses are clamped so that every load is unconditional and the 32
+    // loads of a batch are in flight together.
     auto load = [&](double shift) {
-        for (int idx = tid; idx < lp * lp; idx += 1024) {
-            const int a = idx / lp, c = idx - a * lp;
-            M[a * LP + c] = (a >= l && a == c) ? 1.0 : 0.0;
-        }
-        __syncthreads();
         double emax = 0.0;
-        for (int idx = tid; idx < npairs * 256; idx += 1024) {
-            const int pr = idx >> 8, e = idx & 255;
-            int ta = 0, pp = pr;
-            while (pp >= nt - ta) { pp -= nt - ta; ++ta; }
-            const int row = ta * 16 + (e >> 4), col = (ta + pp) * 16 + (e & 15);
-            if (row > col || row >= l || col >= l) continue;
-            double sum = 0.0;
-            int c = 0;
-            for (; c + 4 <= nchunks; c += 4) {
-                const double x0 = part[((size_t)(c + 0) * npairs + pr) * 256 + e];
-                const double x1 = part[((size_t)(c + 1) * npairs + pr) * 256 + e];
-                const double x2 = part[((size_t)(c + 2) * npairs + pr) * 256 + e];
-                const double x3 = part[((size_t)(c + 3) * npairs + pr) * 256 + e];
-                sum = (((sum + x0) + x1) + x2) + x3;
+        bool nf = false;
+        for (int i0 = tid; i0 < stride; i0 += 4 * kCholThreads) {
+            double x[4][8];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const int idx = min(i0 + u * kCholThreads, stride - 1), cc = min(c, nchunks - 1);
+                    x[u][c] = part[(size_t)cc * stride + idx];
+                }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int idx = i0 + u * kCholThreads;
+                if (idx >= stride) break;        // pr < npairs below keeps the pair decode finite
+                double sum = 0.0;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) sum += c < nchunks ? x[u][c] : 0.0;
+                const int pr = idx >> 8, e = idx & 255;
+                int ta = 0, pp = pr;
+                while (pp >= nt - ta) { pp -= nt - ta; ++ta; }
+                const int row = ta * 16 + (e >> 4), col = (ta + pp) * 16 + (e & 15);
+                if (row > col || col >= l) continue;
+                if (row == col) {
+                    dg[row] = sum;
+                    if (!isfinite(sum)) nf = true;
+                }
+                P[row * LP + col] = sum + (row == col ? shift : 0.0);
+                double ee = fabs(sum - (row == col ? 1.0 : 0.0));
+                if (!(ee < 1e300)) ee = 1e300;
+                emax = fmax(emax, ee);
             }
-            for (; c < nchunks; ++c) sum += part[((size_t)c * npairs + pr) * 256 + e];
-            if (row == col) dg[row] = sum;
-            M[row * LP + col] = sum + (row == col ? shift : 0.0);
-            double ee = fabs(sum - (row == col ? 1.0 : 0.0));
-            if (!(ee < 1e300)) ee = 1e300;
-            emax = fmax(emax, ee);
         }
-        for (int a = l + tid; a < lp; a += 1024) dg[a] = 1.0;
+        if (nf) s_nonfinite = 1;
         return emax;
     };
 
-    if (tid == 0) { s_emax = 0ull; s_broke = 0; }
+    if (tid == 0) { s_emax = 0ull; s_nonfinite = 0; }
     __syncthreads();
     const double emax_t = load(0.0);
     if (mode == 1) atomicMax(&s_emax, (unsigned long long)__double_as_longlong(emax_t));
     __syncthreads();
+    const int q4 = tid >> 7, y = tid & 127;          // output: 4 row groups of 128 columns
     if (mode == 1 && __longlong_as_double((long long)s_emax) <= tau) {
-#pragma unroll 4
-        for (int idx = tid; idx < L * L; idx += 1024) {
-            const int a = idx / L, c = idx - a * L;
-            double r = 0.0, ri = 0.0;
-            if (a <= c && c < l) {
-                const double e = M[a * LP + c] - (a == c ? 1.0 : 0.0);
-                const double u = a < c ? e : 0.5 * e;
-                r = (a == c ? 1.0 : 0.0) + u;
-                ri = (a == c ? 1.0 : 0.0) - u;
+        for (int x = q4; x < L; x += 4) {
+            if (y >= L) continue;
+            double ri = 0.0;
+            if (x <= y && y < l) {
+                const double e = P[x * LP + y] - (x == y ? 1.0 : 0.0);
+                ri = (x == y ? 1.0 : 0.0) - (x < y ? e : 0.5 * e);
             }
-            R[idx] = r;
-            Rinv[idx] = ri;
+            Rinv[x * L + y] = ri;
         }
         if (tid == 0) flags->orth_fail = 0;
         return;
     }
-    bool nonfinite = false;
+    const bool nonfinite = s_nonfinite != 0;
     double gmax = 0.0;
-    for (int j = 0; j < l; ++j) {
-        const double d = dg[j];
-        if (!isfinite(d)) nonfinite = true;
-        else gmax = fmax(gmax, d);
-    }
+    for (int j = 0; j < l; ++j) gmax = fmax(gmax, dg[j]);
     const double rel = (mode == 0) ? 1e-12 : (mode == 1 ? 1e-2 : 0.0);
+    // Where this tile publishes its rows: base + a * pst + b.
+    const bool rdiag = !left && bi == bj;
+    double* const pub = rdiag ? RD + bi * T * T : P + r0 * LP + c0 + (left ? 1 : 0);
+    const int pst = rdiag ? T : LP;
     double shift = 0.0;
     bool broke = nonfinite;
     for (int attempt = 0; attempt < (mode == 2 ? 5 : 1) && !nonfinite; ++attempt) {
-        if (attempt > 0) {
+        if (attempt > 0) {                // the elimination overwrote G: reload it with the new shift
+            __syncthreads();
             load(shift);
-            if (tid == 0) s_broke = 0;
             __syncthreads();
         }
-        for (int J = 0; J < nb; ++J) {
-            const int j0 = 16 * J;
-            // (a) diagonal block by wavefront 0.
-            if (wave == 0) {
-                const int i = lane;
-                double u[16], e[16];
+        double v[T][T];
 #pragma unroll
-                for (int c = 0; c < 16; ++c) {
-                    u[c] = (i < 16 && c >= i) ? M[(j0 + i) * LP + j0 + c] : 0.0;
-                    e[c] = (c == i) ? 1.0 : 0.0;
-                }
-                bool bad = false;
+        for (int a = 0; a < T; ++a)
 #pragma unroll
-                for (int p = 0; p < 16; ++p) {
-                    if (i == p) {
-#pragma unroll
-                        for (int c = 0; c < 16; ++c) { rowp[c] = u[c]; rowp[16 + c] = e[c]; }
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    const double d = rowp[p];
-                    if (!(d > rel * (dg[j0 + p] + shift)) || !(d > 0.0) || !isfinite(d)) bad = true;
-                    if (i > p && i < 16) {
-                        const double f = rowp[i] / d;
-#pragma unroll
-                        for (int c = 0; c < 16; ++c) {
-                            if (c >= i) u[c] -= f * rowp[c];
-                            if (c <= p) e[c] -= f * rowp[16 + c];
-                        }
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                }
-                if (i < 16) {
-                    const double inv = 1.0 / sqrt(u[i]);
-#pragma unroll
-                    for (int c = 0; c < 16; ++c) {
-                        if (c >= i) M[(j0 + i) * LP + j0 + c] = u[c] * inv;
-                        else M[(j0 + i) * LP + j0 + c] = e[c] * inv;
-                    }
-                    inv_r[j0 + i] = inv;
-                }
-                if (bad && lane == 0) s_broke = 1;
+            for (int b = 0; b < T; ++b) {
+                // Rows and columns past l hold whatever the LDS holds there;
+                // they never reach a pivot row or an output.
+                const int r = r0 + a, c = c0 + b;
+                v[a][b] = left ? P[min(min(r, c), kCholLdsMax - 1) * LP + min(max(r, c), LP - 1)] : (r == c ? 1.0 : 0.0);
             }
-            __syncthreads();
-            if (s_broke) break;
-            // (b) panel R_J,K (one thread per column) and T_IJ = sum_{I<=K<J} X_IK R_KJ.
-            {
-                const int ncols = lp - j0 - 16;
-                if (tid < ncols) {
-                    const int c = j0 + 16 + tid;
-                    double g[16];
+        __syncthreads();                  // every read of G precedes the first pivot row written over it
+        auto publish = [&](int a) {
+            double* const dst = pub + a * pst;
 #pragma unroll
-                    for (int k = 0; k < 16; ++k) g[k] = M[(j0 + k) * LP + c];
-#pragma unroll
-                    for (int i = 0; i < 16; ++i) {
-                        double acc = g[i] * inv_r[j0 + i];
-#pragma unroll
-                        for (int k = 0; k < 16; ++k)
-                            if (k < i) acc = fma(M[(j0 + i) * LP + j0 + k], g[k], acc);
-                        M[(j0 + i) * LP + c] = acc;
-                    }
-                }
-                for (int idx = tid - 128; idx >= 0 && idx < J * 256; idx += 1024 - 128) {
-                    const int I = idx >> 8, i = (idx >> 4) & 15, c = idx & 15;
-                    double acc = 0.0;
-                    for (int K = I; K < J; ++K) {
-#pragma unroll
-                        for (int k = 0; k < 16; ++k) {
-                            const int a = 16 * I + i, b = 16 * K + k;   // X[a][b], b >= a
-                            const double x = (b == a) ? inv_r[a] : (b > a ? M[b * LP + a] : 0.0);
-                            acc = fma(x, M[b * LP + j0 + c], acc);
-                        }
-                    }
-                    T[(I * 16 + i) * 16 + c] = acc;
-                }
-            }
-            __syncthreads();
-            // (c) trailing update and X_IJ = -T_IJ R_JJ^{-1}.
-            {
-                const int t0 = j0 + 16, nt2 = lp - t0;
-                for (int idx = tid; idx < nt2 * nt2; idx += 1024) {
-                    const int r = t0 + idx / nt2, c = t0 + idx % nt2;
-                    if (c < r) continue;
-                    double acc = M[r * LP + c];
-#pragma unroll
-                    for (int k = 0; k < 16; ++k) acc = fma(-M[(j0 + k) * LP + r], M[(j0 + k) * LP + c], acc);
-                    M[r * LP + c] = acc;
-                }
-                for (int idx = tid; idx < J * 256; idx += 1024) {
-                    const int I = idx >> 8, i = (idx >> 4) & 15, c = idx & 15;
-                    double acc = 0.0;
-#pragma unroll
-                    for (int k = 0; k < 16; ++k) {
-                        if (k > c) continue;
-                        const double y = (k == c) ? inv_r[j0 + c] : M[(j0 + c) * LP + j0 + k];   // R_JJ^{-1}[k][c]
-                        acc = fma(T[(I * 16 + i) * 16 + k], y, acc);
-                    }
-                    M[(j0 + c) * LP + 16 * I + i] = -acc;
-                }
-            }
-            __syncthreads();
-        }
-        broke = s_broke != 0;
+            for (int b = 0; b < T; ++b) dst[b] = v[a][b];
+        };
+        if (owner && r0 == 0) publish(0);
         __syncthreads();
+        // Pivots in blocks of T with the inner loop unrolled, so the tile row
+        // published after step j (row j + 1) is a compile-time index.
+        broke = false;
+        for (int jb = 0; jb < nb && !broke; ++jb) {
+#pragma unroll
+            for (int jj = 0; jj < T; ++jj) {
+                const int j = jb * T + jj;
+                if (j >= l) break;
+                const double d = P[j * LP + j + 1];
+                if (!(d > rel * (dg[j] + shift)) || !(d > 0.0) || !isfinite(d)) {    // same value in every thread
+                    broke = true;
+                    break;
+                }
+                // Rows of this tile below the pivot; a right tile also needs a column <= j.
+                if (owner && r0 + T - 1 > j && (left || c0 <= j)) {
+                    const double* const prow = P + j * LP;
+                    const double* const psrc = left ? prow + c0 + 1 : (bj == jb ? RD + jb * T * T + jj * T : prow + c0);
+                    double f[T], pv[T];
+#pragma unroll
+                    for (int a = 0; a < T; ++a) f[a] = prow[r0 + 1 + a];
+#pragma unroll
+                    for (int b = 0; b < T; ++b) pv[b] = psrc[b];
+                    const double rd = 1.0 / d;
+#pragma unroll
+                    for (int a = 0; a < T; ++a) f[a] = (r0 + a > j) ? f[a] * rd : 0.0;
+#pragma unroll
+                    for (int a = 0; a < T; ++a)
+#pragma unroll
+                        for (int b = 0; b < T; ++b) v[a][b] = fma(-f[a], pv[b], v[a][b]);
+                }
+                // Publish row j + 1 (also from a tile that had nothing to update).
+                if (owner && j + 1 < l) {
+                    if (jj < T - 1) {
+                        if (jb == bi) publish(jj + 1);
+                    } else if (jb + 1 == bi) {
+                        publish(0);
+                    }
+                }
+                __syncthreads();
+            }
+        }
         if (!broke || mode != 2) break;
         shift = (shift == 0.0) ? gmax * 0x1.0p-40 : shift * 1024.0;
         if (!(shift > 0.0)) shift = 0x1.0p-1000;
     }
     if (!broke) {
-#pragma unroll 4
-        for (int idx = tid; idx < L * L; idx += 1024) {
-            const int x = idx / L, y = idx - x * L;
-            double r = 0.0, ri = 0.0;
-            if (x < l && y < l) {
-                if (y >= x) r = M[x * LP + y];
-                if (x <= y) ri = (x == y) ? inv_r[x] : M[y * LP + x];
+        for (int j = tid; j < l; j += kCholThreads) isd[j] = 1.0 / sqrt(P[j * LP + j + 1]);
+        __syncthreads();
+        // mode 2 consumes R (the small SVD), modes 0 and 1 consume R^{-1}.
+        double* out = mode == 2 ? R : Rinv;
+        for (int x = q4; x < L; x += 4) {
+            if (y >= L) continue;
+            double val = 0.0;
+            if (x <= y && y < l) {
+                if (mode == 2) val = P[x * LP + y + 1] * isd[x];
+                else val = ((x / T == y / T) ? RD[(y / T) * T * T + (y % T) * T + x % T] : P[y * LP + x]) * isd[y];
             }
-            R[idx] = r;
-            Rinv[idx] = ri;
+            out[x * L + y] = val;
         }
     }
     if (tid == 0) {
@@ -516,7 +503,7 @@ hipError_t launch_chol(const double* partials, int64_t rows, int l, int L, doubl
                        int mode, double* shift_out, double* work, double tau, hipStream_t s) {
     const int nchunks = gram_chunks(rows);
     if (l <= kCholLdsMax)
-        hipLaunchKernelGGL(chol_blocked_kernel, dim3(1), dim3(1024), 0, s, partials, nchunks, l, L, R, Rinv, flags,
+        hipLaunchKernelGGL(chol_rl_kernel, dim3(1), dim3(kCholThreads), 0, s, partials, nchunks, l, L, R, Rinv, flags,
                            mode, shift_out, tau);
     else
         hipLaunchKernelGGL(chol_kernel<false>, dim3(1), dim3(1024), 0, s, partials, nchunks, l, L, R, Rinv, flags,

@@ -51,8 +51,8 @@ __device__ __forceinline__ void rr_pair(int r, int s, int n2, int& p1, int& p2) 
 // with a padded stride (zero rows past l stay zero under rotations), so
 // every lane loads and stores its rows 2e, 2e+1, 2e+16, 2e+17, ... as 16-byte
 // pairs without bounds checks.  NP = row pairs per lane.
-template <int NP, bool IN_LDS>
-__global__ __launch_bounds__(1024) void jacobi_kernel(const double* __restrict__ R, int l, int L,
+template <int NP, bool IN_LDS, int NT>
+__global__ __launch_bounds__(NT) void jacobi_kernel(const double* __restrict__ R, int l, int L,
                                                       const double* __restrict__ shift_p, double* __restrict__ sigma,
                                                       double* __restrict__ Ut, double* __restrict__ Mv,
                                                       DevFlags* flags, double* __restrict__ work) {
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const double* __restrict__
     double* X = IN_LDS ? lds : work;                // X[c * ld + r] = R[c][r], zero for r >= l
     const int tid = threadIdx.x, grp = tid >> 3, e = tid & 7;
 
-    for (int idx = tid; idx < l * ld; idx += 1024) {
+    for (int idx = tid; idx < l * ld; idx += NT) {
         const int c = idx / ld, r = idx - c * ld;
         X[idx] = r < l ? R[(int64_t)c * L + r] : 0.0;
     }
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const double* __restrict__
         if (tid == 0) rotated = 0;
         __syncthreads();
         for (int r = 0; r < n2 - 1; ++r) {
-            for (int s = grp; s < n2 / 2; s += 128) {
+            for (int s = grp; s < n2 / 2; s += NT / 8) {
                 int p1, p2;
                 rr_pair(r, s, n2, p1, p2);
                 if (p1 >= l || p2 >= l) continue;
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const double* __restrict__
     }
     if (!converged && tid == 0) atomicOr(&flags->info, RSVD_INFO_JACOBI_NOT_CONVERGED);
 
-    for (int c = grp; c < l; c += 128) {
+    for (int c = grp; c < l; c += NT / 8) {
         double s2 = 0.0;
         for (int row = e; row < l; row += 8) s2 = fma(X[c * ld + row], X[c * ld + row], s2);
         s2 = octet_sum(s2);
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const double* __restrict__
     __syncthreads();
     const double shift = *shift_p;
     // Stable descending order of the singular values sqrt(max(nrm2 - shift, 0)).
-    for (int c = tid; c < l; c += 1024) {
+    for (int c = tid; c < l; c += NT) {
         const double sc = sqrt(fmax(nrm2[c] - shift, 0.0));
         int rank = 0;
         for (int d = 0; d < l; ++d) {
@@ -145,12 +145,12 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const double* __restrict__
         sigma[rank] = sc;
     }
     __syncthreads();
-    for (int idx = tid; idx < L * L; idx += 1024) {
+    for (int idx = tid; idx < L * L; idx += NT) {
         Ut[idx] = 0.0;
         Mv[idx] = 0.0;
     }
     __syncthreads();
-    for (int idx = tid; idx < l * l; idx += 1024) {
+    for (int idx = tid; idx < l * l; idx += NT) {
         const int c = idx / l, row = idx - c * l;
         const double nc = sqrt(nrm2[c]);
         const double sc = sqrt(fmax(nrm2[c] - shift, 0.0));
@@ -164,11 +164,12 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const double* __restrict__
 hipError_t launch_jacobi(const double* R, int l, int L, const double* shift, double* sigma, double* Ut, double* Mv,
                          DevFlags* flags, double* work, hipStream_t s) {
     if (l <= kJacobiLdsMax)
-        hipLaunchKernelGGL((jacobi_kernel<kJacobiLdsMax / 16, true>), dim3(1), dim3(1024), 0, s, R, l, L, shift,
-                           sigma, Ut, Mv, flags, work);
+        hipLaunchKernelGGL((jacobi_kernel<kJacobiLdsMax / 16, true, 1024>), dim3(1), dim3(1024), 0, s, R, l, L,
+                           shift, sigma, Ut, Mv, flags, work);
     else
-        hipLaunchKernelGGL((jacobi_kernel<kMaxL / 16, false>), dim3(1), dim3(1024), 0, s, R, l, L, shift, sigma, Ut,
-                           Mv, flags, work);
+        // 36 register pairs per lane: 512 threads leave 256 VGPRs per lane.
+        hipLaunchKernelGGL((jacobi_kernel<kMaxL / 16, false, 512>), dim3(1), dim3(512), 0, s, R, l, L, shift, sigma,
+                           Ut, Mv, flags, work);
     return hipGetLastError();
 }
 
