@@ -51,6 +51,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="c2_fp32_8192")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--input", choices=("workload", "gaussian"), default="workload",
+                    help="gaussian: i.i.d. N(0,1)/sqrt(n) matrix of the same shape, drawn on the device without a "
+                         "QR; for hardware-counter runs, where the products' traffic does not depend on the values")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -59,7 +62,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2402_17794_amd import rsvd, workloads
+    from paper_2402_17794_amd import prof_summary, rsvd, workloads
 
     cfg = workloads.CONFIGS[args.config]
     m, n, k, p, q = cfg["m"], cfg["n"], cfg["k"], cfg["p"], cfg["q"]
@@ -67,11 +70,26 @@ def main():
     dev = torch.device("cuda:0")
     print(f"bench: generating {args.config} ...", file=sys.stderr, flush=True)
     tg = time.perf_counter()
-    A64 = workloads.config_matrix(args.config, device=dev)
-    A = A64.to(dtype).contiguous()
-    del A64
+    if args.input == "gaussian":
+        g = torch.Generator(device=dev)
+        g.manual_seed(1)
+        A = (torch.randn(m, n, device=dev, dtype=torch.float32, generator=g) / float(n) ** 0.5).to(dtype)
+    else:
+        A64 = workloads.config_matrix(args.config, device=dev)
+        A = A64.to(dtype).contiguous()
+        del A64
     torch.cuda.synchronize()
     print(f"bench: input ready in {time.perf_counter() - tg:.1f} s", file=sys.stderr, flush=True)
+
+    # A plain copy of known size (a same-type tensor copy: the runtime's blit
+    # kernel), outside the timed region: the reference that scales the
+    # FETCH_SIZE / WRITE_SIZE counters of a profiled run.
+    calib_src = torch.ones(prof_summary.CALIB_BYTES // 4, dtype=torch.int32, device=dev)
+    calib_dst = torch.empty_like(calib_src)
+    for _ in range(2):
+        calib_dst.copy_(calib_src)
+    torch.cuda.synchronize()
+    del calib_src, calib_dst
 
     solver = rsvd.Solver(A, k, p, q, seed=0)
     l = solver.l
@@ -114,6 +132,13 @@ def main():
     gemm_ms = sum(v[0] for v in kinds.values()) / args.steps
     flops_solve = (2 * q + 2) * 2.0 * m * n * l
 
+    # HBM bytes per launch of the dominant kernel from the committed counter
+    # summary, only while the GEMM sources are the ones the counters measured.
+    traffic = None
+    tr = prof_summary.read_traffic(os.path.join(ROOT, "profiles", f"gemm_tn_{args.config}_traffic.txt"))
+    if tr is not None and dom == 2 and tr[1] == prof_summary.gemm_source_hash():
+        traffic = tr[0]
+
     S_gpu = solver.S.cpu().numpy()
     out = {
         "metric": METRIC,
@@ -128,7 +153,9 @@ def main():
         "vs_baseline": None,
         "dtype": cfg["dtype"],
         "data": "synthetic",
-        "config": {"workload": _describe(args.config, cfg), "m": m, "n": n, "k": k, "p": p, "q": q, "l": l},
+        "config": {"workload": _describe(args.config, cfg) if args.input == "workload" else
+                   f"{args.config} shape with a Gaussian N(0,1/n) matrix (counter runs)",
+                   "m": m, "n": n, "k": k, "p": p, "q": q, "l": l},
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
         "tflops_algorithmic": flops_solve / (dt / args.steps) / 1e12,
@@ -141,14 +168,15 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": None,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": float(m * n * A.element_size()),
             "avg_launch_ms": dom_ms,
             "flops_per_launch": flops_launch,
             "launches_per_solve": kinds[dom][1] / args.steps,
         },
     }
 
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.input == "workload":
         from oracle.rsvd import rsvd_alg4
         try:
             from threadpoolctl import threadpool_info
@@ -175,7 +203,7 @@ def main():
             "sigma_relative_max": float(np.max(np.abs(S_gpu - S_ref) / S_ref)),
         }
     sig = workloads.config_sigma(args.config)
-    if sig is not None:
+    if sig is not None and args.input == "workload":
         out["err_vs_true_spectrum_normwise"] = float(np.max(np.abs(S_gpu - sig[:k])) / sig[0])
     print(json.dumps(out), flush=True)
 

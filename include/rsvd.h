@@ -127,9 +127,10 @@ rsvd_status rsvd_solve(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* 
 
 const char* rsvd_status_string(rsvd_status s);
 
-/* Kernel timing for performance reports.  While enabled, every product with
- * A enqueued by rsvd_solve on handle h is bracketed by a pair of HIP events
- * recorded on the solve's stream (events owned by the handle).
+/* Kernel timing for performance reports.  While enabled, the product kernel
+ * of every product with A enqueued by rsvd_solve on handle h is bracketed by
+ * a pair of HIP events recorded on the solve's stream (events owned by the
+ * handle; the split-K reduction that follows the product is outside them).
  * rsvd_profile_read waits for the recorded events of one kind (0: the
  * sketch A * Omega with the generated test matrix, 1: A * X, 2: A^T * X,
  * 3: all kinds), returns the summed kernel time in milliseconds and the

@@ -32,6 +32,7 @@
 
 namespace rsvd {
 
+// ---- product kernel (begin) ----
 // Rows per wavefront (16 * RT) and K tile.  Wide thin operands (LT > 9, i.e.
 // more than 144 columns) use one row tile per wavefront and a shorter K tile
 // to keep the accumulators and the prefetch registers within the register
@@ -293,6 +294,7 @@ __global__ __launch_bounds__(256) void skinny_gemm_kernel(GemmArgs g) {
                 if (row < g.M) P[split * pstride + row * L + 16 * t + li] = acc[r][t][v];
             }
 }
+// ---- product kernel (end) ----
 
 // Y = sum of the split-K slices, added in slice order (slice 0 first).
 template <typename T, int SMAX>
@@ -365,9 +367,9 @@ size_t gemm_partials_elems(int dtype, int64_t M, int64_t K, int ncols, int* spli
     return s > 1 ? (size_t)s * (size_t)M * (size_t)L : 0;
 }
 
-hipError_t launch_gemm(int dtype, GemmArgs a, hipStream_t s) {
+hipError_t launch_gemm(int dtype, GemmArgs a, hipStream_t s, hipEvent_t product_done) {
     if (a.ncols < 1 || a.ncols > kMaxL || a.M < 0 || a.K < 0) return hipErrorInvalidValue;
-    if (a.M == 0) return hipSuccess;
+    if (a.M == 0) return product_done ? hipEventRecord(product_done, s) : hipSuccess;
     const int LT = (int)ceil_div(a.ncols, 16);
     const bool omega = (a.X == nullptr);
     if (omega && a.trans) return hipErrorInvalidValue;
@@ -381,6 +383,7 @@ hipError_t launch_gemm(int dtype, GemmArgs a, hipStream_t s) {
         if (a.trans) e = dispatch_lt<float, true, false>(a, LT, grid, s);
         else e = omega ? dispatch_lt<float, false, true>(a, LT, grid, s) : dispatch_lt<float, false, false>(a, LT, grid, s);
     }
+    if (e == hipSuccess && product_done) e = hipEventRecord(product_done, s);
     if (e != hipSuccess || a.splits == 1) return e;
     const int L = 16 * LT;
     const int64_t nvec = a.M * (L / (dtype == 0 ? 2 : 4));

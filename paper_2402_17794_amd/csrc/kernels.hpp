@@ -33,7 +33,9 @@ struct GemmArgs {
 };
 size_t gemm_partials_elems(int dtype, int64_t M, int64_t K, int ncols, int* splits_out);
 int gemm_row_tiles(int dtype, int64_t M, int ncols);
-hipError_t launch_gemm(int dtype, GemmArgs a, hipStream_t s);
+// product_done (optional) is recorded on s right after the product kernel,
+// before the split-K reduction, so that it times the product alone.
+hipError_t launch_gemm(int dtype, GemmArgs a, hipStream_t s, hipEvent_t product_done = nullptr);
 
 // ---- Gram, Cholesky, apply, Householder (orth.hip) ----
 // Chunk partials of G = Y^T Y (FP64) for Y rows x L (dtype, zero padding):

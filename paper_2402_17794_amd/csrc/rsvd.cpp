@@ -160,11 +160,8 @@ rsvd_status run_gemm(rsvd_handle* h, const Plan& P, void* ws, const rsvd_matrix*
         if (!rec.start || !rec.stop) return RSVD_ERR_DEVICE;
         RSVD_TRY(hipEventRecord(rec.start, s));
     }
-    RSVD_TRY(launch_gemm(P.dtype, g, s));
-    if (h->profiling) {
-        RSVD_TRY(hipEventRecord(rec.stop, s));
-        h->recs.push_back(rec);
-    }
+    RSVD_TRY(launch_gemm(P.dtype, g, s, h->profiling ? rec.stop : nullptr));
+    if (h->profiling) h->recs.push_back(rec);
     return RSVD_OK;
 }
 
