@@ -86,10 +86,17 @@ typedef struct {
     int64_t p;                     /* oversampling, p >= 0; l = min(k + p, min(m, n)) */
     int64_t q;                     /* power iterations, q >= 0 (q = 0: Algorithm 2) */
     uint64_t seed;                 /* key of the Philox test matrix */
-    int32_t residual;              /* 0: none; 2: Frobenius norm of A - Q Q^T A */
+    int32_t residual;              /* error measure ||A - Q Q^T A|| of Theorems 2, 3, 6 (full l-column Q):
+                                      bit 0 (1): spectral norm, estimated (see residual_iters);
+                                      bit 1 (2): Frobenius norm, exact (FP64 accumulation); 3: both */
     int32_t return_full_l;         /* 0: return the top k triplets; 1: all l */
     int32_t force_householder;     /* 1: always orthonormalise by Householder QR */
-    int32_t reserved0;
+    int32_t residual_iters;        /* spectral estimate: block power iterations t on E = A - Q Q^T A,
+                                      0 = default (4).  Start block: min(16, m, n) columns of the test-matrix
+                                      generator on stream 2 (same seed), orthonormalised; each iteration
+                                      Y = orth(E Z), Z = orth(E^T Y); the estimate is the largest singular value
+                                      of E Z (a lower bound of ||E||_2 up to rounding, converging as t grows).
+                                      0 <= residual_iters <= 1000. */
 } rsvd_params;
 
 /* Outputs.  r = k, or l when return_full_l is set.  U and Vt have the
@@ -99,7 +106,8 @@ typedef struct {
     void* U;  int64_t ldu;         /* m x r, row-major, ldu >= r */
     double* S;                     /* r singular values, descending */
     void* Vt; int64_t ldvt;        /* r x n, row-major, ldvt >= n */
-    double* residual;              /* nullable; [0] = reserved (0), [1] = ||A - QQ^T A||_F */
+    double* residual;              /* required when params->residual != 0: [0] = spectral estimate,
+                                      [1] = Frobenius norm (an entry not requested is 0) */
     int32_t* info;                 /* required; RSVD_INFO_* bit flags */
     void* Q;  int64_t ldq;         /* nullable; m x l, row-major, ldq >= l */
 } rsvd_result;

@@ -112,4 +112,10 @@ hipError_t launch_residual_fro(int dtype, const void* A, int64_t lda, int64_t m,
                                const void* Bt, int l, int L, double* partial, double* out, hipStream_t s);
 size_t residual_partials(int64_t m, int64_t n);
 
+// Spectral-norm estimator of A - Q Q^T A: M = [-Q^T W; I_b] ((L + 16) x 16,
+// FP64) from the Gram partials of [Q | W] (rows x (L + 16)).
+hipError_t launch_proj_coef(const double* partials, int64_t rows, int L, int b, double* M, hipStream_t s);
+// out[0] = sigma[0]; out[1] = 0 unless the Frobenius norm was requested.
+hipError_t launch_residual_spec_final(const double* sigma, double* out, int fro_requested, hipStream_t s);
+
 }  // namespace rsvd

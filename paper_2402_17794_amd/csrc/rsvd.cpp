@@ -59,10 +59,19 @@ struct Plan {
     int splits_nn = 1, splits_tn = 1;
     size_t counters, flags, part, Y, Q, W, Q1, GP, R, Rinv, Ut, Mv, sigma, shift, sign, amax_val, amax_idx, H, Qw,
         work, res_part, res;
+    // Spectral-norm estimator of the residual (allocated when requested):
+    // block of sb <= 16 columns padded to 16.
+    int spectral = 0, sb = 0;
+    int splits16_nn = 1, splits16_tn = 1;
+    size_t flags2 = 0, QW = 0, Za = 0, Zb = 0, Ws = 0, Ys = 0, Mc = 0, sigma2 = 0, shift2 = 0;
     size_t total;
 };
 
-bool make_plan(int dtype, int64_t m, int64_t n, int64_t k, int64_t p, int64_t q, int full, Plan& P) {
+constexpr int kSpecBlock = 16;      // block size of the spectral-norm estimator
+constexpr int kSpecItersDefault = 4;
+
+bool make_plan(int dtype, int64_t m, int64_t n, int64_t k, int64_t p, int64_t q, int full, Plan& P,
+               int spectral = 0) {
     P.dtype = dtype;
     P.m = m; P.n = n; P.k = k; P.p = p; P.q = q;
     P.l = std::min<int64_t>(k + p, std::min(m, n));
@@ -73,16 +82,21 @@ bool make_plan(int dtype, int64_t m, int64_t n, int64_t k, int64_t p, int64_t q,
     const size_t es = esize(dtype);
     const size_t pn = gemm_partials_elems(dtype, m, n, P.L, &P.splits_nn);
     const size_t pt = gemm_partials_elems(dtype, n, m, P.L, &P.splits_tn);
+    P.spectral = spectral;
+    P.sb = (int)std::min<int64_t>(kSpecBlock, std::min(m, n));
+    const size_t pn16 = spectral ? gemm_partials_elems(dtype, m, n, kSpecBlock, &P.splits16_nn) : 0;
+    const size_t pt16 = spectral ? gemm_partials_elems(dtype, n, m, kSpecBlock, &P.splits16_tn) : 0;
     P.ncounters = 1;
     Carver c;
     P.counters = c.take(sizeof(int) * (size_t)P.ncounters);
     P.flags = c.take(sizeof(DevFlags));
-    P.part = c.take(es * std::max<size_t>({pn, pt, 1}));
+    P.part = c.take(es * std::max<size_t>({pn, pt, pn16, pt16, 1}));
     P.Y = c.take(es * (size_t)mx * P.L);
     P.Q = c.take(es * (size_t)m * P.L);
     P.W = c.take(es * (size_t)n * P.L);
     P.Q1 = c.take(es * (size_t)mx * P.L);
-    P.GP = c.take(sizeof(double) * gram_partials_elems(mx, P.L));
+    P.GP = c.take(sizeof(double) * std::max(gram_partials_elems(mx, P.L),
+                                            spectral ? gram_partials_elems(m, P.L + kSpecBlock) : 0));
     P.R = c.take(sizeof(double) * (size_t)P.L * P.L);
     P.Rinv = c.take(sizeof(double) * (size_t)P.L * P.L);
     P.Ut = c.take(sizeof(double) * (size_t)P.L * P.L);
@@ -97,6 +111,17 @@ bool make_plan(int dtype, int64_t m, int64_t n, int64_t k, int64_t p, int64_t q,
     P.work = c.take(sizeof(double) * (size_t)kMaxL * kMaxL);
     P.res_part = c.take(sizeof(double) * residual_partials(m, n));
     P.res = c.take(sizeof(double) * 2);
+    if (spectral) {
+        P.flags2 = c.take(sizeof(DevFlags));
+        P.QW = c.take(es * (size_t)m * (P.L + kSpecBlock));
+        P.Za = c.take(es * (size_t)n * kSpecBlock);
+        P.Zb = c.take(es * (size_t)n * kSpecBlock);
+        P.Ws = c.take(es * (size_t)m * kSpecBlock);
+        P.Ys = c.take(es * (size_t)m * kSpecBlock);
+        P.Mc = c.take(sizeof(double) * (size_t)(P.L + kSpecBlock) * kSpecBlock);
+        P.sigma2 = c.take(sizeof(double) * kSpecBlock);
+        P.shift2 = c.take(sizeof(double));
+    }
     P.total = c.off;
     return true;
 }
@@ -112,11 +137,10 @@ T* at(void* base, size_t off) {
         if (e_ != hipSuccess) return RSVD_ERR_DEVICE;      \
     } while (0)
 
-// orth(Y) -> Q for an internal rows x L buffer (ld = L, zero padding).
-rsvd_status run_orth(const Plan& P, void* ws, int dtype, int64_t rows, const void* Y, void* Qout, int force_hh,
-                     hipStream_t s) {
-    const int L = P.L, l = (int)P.l;
-    DevFlags* flags = at<DevFlags>(ws, P.flags);
+// orth(Y) -> Q for an internal rows x L buffer (ld = L, l valid columns,
+// zero padding), with the outcome in `flags`.  Qout must not alias Y.
+rsvd_status run_orth_cols(const Plan& P, void* ws, DevFlags* flags, int dtype, int64_t rows, int l, int L,
+                          const void* Y, void* Qout, int force_hh, hipStream_t s) {
     double* R = at<double>(ws, P.R);
     double* Rinv = at<double>(ws, P.Rinv);
     double* GP = at<double>(ws, P.GP);
@@ -136,8 +160,17 @@ rsvd_status run_orth(const Plan& P, void* ws, int dtype, int64_t rows, const voi
     return RSVD_OK;
 }
 
-rsvd_status run_gemm(rsvd_handle* h, const Plan& P, void* ws, const rsvd_matrix* A, int trans, const void* X,
-                     uint64_t seed, void* Yout, hipStream_t s) {
+rsvd_status run_orth(const Plan& P, void* ws, int dtype, int64_t rows, const void* Y, void* Qout, int force_hh,
+                     hipStream_t s) {
+    return run_orth_cols(P, ws, at<DevFlags>(ws, P.flags), dtype, rows, (int)P.l, P.L, Y, Qout, force_hh, s);
+}
+
+// Product of A with a skinny block: Yout (ldy) = A X or A^T X, X with ldx
+// and `cols` columns (zero padded to `wcols`), or X = Omega(seed) when NULL.
+// Timed (rsvd_profile_*) when h is not NULL and profiling is on.
+rsvd_status run_product(rsvd_handle* h, const Plan& P, void* ws, const rsvd_matrix* A, int trans, const void* X,
+                        int64_t ldx, uint64_t seed, int cols, int wcols, int splits, void* Yout, int64_t ldy,
+                        hipStream_t s) {
     GemmArgs g{};
     g.A = A->data;
     g.lda = A->ld;
@@ -145,23 +178,86 @@ rsvd_status run_gemm(rsvd_handle* h, const Plan& P, void* ws, const rsvd_matrix*
     g.M = trans ? A->cols : A->rows;
     g.K = trans ? A->rows : A->cols;
     g.X = X;
-    g.ldx = P.L;
+    g.ldx = ldx;
     g.seed = seed;
-    g.ncols = trans ? P.L : (X ? P.L : (int)P.l);
-    g.wcols = P.L;
+    g.ncols = cols;
+    g.wcols = wcols;
     g.Y = Yout;
-    g.ldy = P.L;
+    g.ldy = ldy;
     g.partials = at<char>(ws, P.part);
-    g.splits = trans ? P.splits_tn : P.splits_nn;
-    rsvd_handle::Rec rec{trans ? 2 : (X ? 1 : 0), nullptr, nullptr};
-    if (h->profiling) {
-        rec.start = h->get_event();
-        rec.stop = h->get_event();
-        if (!rec.start || !rec.stop) return RSVD_ERR_DEVICE;
-        RSVD_TRY(hipEventRecord(rec.start, s));
+    g.splits = splits;
+    if (!h || !h->profiling) {
+        RSVD_TRY(launch_gemm(P.dtype, g, s));
+        return RSVD_OK;
     }
-    RSVD_TRY(launch_gemm(P.dtype, g, s, h->profiling ? rec.stop : nullptr));
-    if (h->profiling) h->recs.push_back(rec);
+    rsvd_handle::Rec rec{trans ? 2 : (X ? 1 : 0), nullptr, nullptr};
+    rec.start = h->get_event();
+    rec.stop = h->get_event();
+    if (!rec.start || !rec.stop) return RSVD_ERR_DEVICE;
+    RSVD_TRY(hipEventRecord(rec.start, s));
+    RSVD_TRY(launch_gemm(P.dtype, g, s, rec.stop));
+    h->recs.push_back(rec);
+    return RSVD_OK;
+}
+
+// The products of Algorithm 4 on the solve's L-column buffers.
+rsvd_status run_gemm(rsvd_handle* h, const Plan& P, void* ws, const rsvd_matrix* A, int trans, const void* X,
+                     uint64_t seed, void* Yout, hipStream_t s) {
+    const int cols = trans ? P.L : (X ? P.L : (int)P.l);
+    return run_product(h, P, ws, A, trans, X, P.L, seed, cols, P.L, trans ? P.splits_tn : P.splits_nn, Yout, P.L, s);
+}
+
+// ||A - Q Q^T A||_2 estimated by block power iteration on E = A - Q Q^T A
+// (the error measure of Theorems 2, 3 and 6): Z_0 = orth(Omega) with the
+// test-matrix generator on stream 2 (sb columns); `iters` times
+// Y = orth(E Z), Z = orth(E^T Y); then the largest singular value of E Z
+// (Rayleigh-Ritz on the final block).  E Z = A Z - Q (Q^T A Z) in FP64 from
+// the Gram of [Q | A Z]; E^T Y = A^T Y because Y is orthogonal to Q.  All
+// orthonormalisations report into a flag word of their own, so a fallback
+// here never shows in the solve's info.
+rsvd_status run_spectral(const Plan& P, void* ws, const rsvd_matrix* A, const void* Q, uint64_t seed, int iters,
+                         double* out, int fro_requested, hipStream_t s) {
+    const int dt = P.dtype, L = P.L, LW = P.L + kSpecBlock, b = P.sb, B = kSpecBlock;
+    const size_t es = esize(dt);
+    DevFlags* f2 = at<DevFlags>(ws, P.flags2);
+    char* QW = at<char>(ws, P.QW);
+    void* Za = at<char>(ws, P.Za);
+    void* Zb = at<char>(ws, P.Zb);
+    void* Wsp = at<char>(ws, P.Ws);
+    void* Ys = at<char>(ws, P.Ys);
+    double* Mc = at<double>(ws, P.Mc);
+    double* GP = at<double>(ws, P.GP);
+    RSVD_TRY(launch_init(nullptr, 0, f2, s));
+    RSVD_TRY(launch_copy2d(dt, Q, L, P.m, L, QW, LW, L, s));                 // [Q | .]
+    if (b < B) RSVD_TRY(launch_copy2d(dt, Za, B, P.n, 0, Za, B, B, s));    // zero padding columns
+    RSVD_TRY(launch_omega(dt, seed, 2, P.n, b, Za, B, s));
+    rsvd_status st;
+    if ((st = run_orth_cols(P, ws, f2, dt, P.n, b, B, Za, Zb, 0, s)) != RSVD_OK) return st;
+    // E Z for the block in Zb -> Wsp.
+    auto apply_E = [&]() -> rsvd_status {
+        rsvd_status r = run_product(nullptr, P, ws, A, 0, Zb, B, 0, B, B, P.splits16_nn, QW + es * L, LW, s);
+        if (r != RSVD_OK) return r;
+        RSVD_TRY(launch_gram(dt, QW, LW, P.m, LW, GP, nullptr, s));
+        RSVD_TRY(launch_proj_coef(GP, P.m, L, b, Mc, s));
+        RSVD_TRY(launch_apply(dt, QW, LW, P.m, LW, Mc, B, B, Wsp, B, 0, nullptr, nullptr, nullptr, nullptr, 0, s));
+        return RSVD_OK;
+    };
+    for (int it = 0; it < iters; ++it) {
+        if ((st = apply_E()) != RSVD_OK) return st;
+        if ((st = run_orth_cols(P, ws, f2, dt, P.m, b, B, Wsp, Ys, 0, s)) != RSVD_OK) return st;
+        if ((st = run_product(nullptr, P, ws, A, 1, Ys, B, 0, B, B, P.splits16_tn, Za, B, s)) != RSVD_OK) return st;
+        if ((st = run_orth_cols(P, ws, f2, dt, P.n, b, B, Za, Zb, 0, s)) != RSVD_OK) return st;
+    }
+    if ((st = apply_E()) != RSVD_OK) return st;
+    // Rayleigh-Ritz: singular values of E Z (m x b) through its Gram, as for B.
+    double* sigma2 = at<double>(ws, P.sigma2);
+    double* shift2 = at<double>(ws, P.shift2);
+    RSVD_TRY(launch_gram(dt, Wsp, B, P.m, B, GP, nullptr, s));
+    RSVD_TRY(launch_chol(GP, P.m, b, B, at<double>(ws, P.R), at<double>(ws, P.Rinv), f2, 2, shift2,
+                         at<double>(ws, P.work), 0.0, s));
+    RSVD_TRY(launch_jacobi(at<double>(ws, P.R), b, B, shift2, sigma2, at<double>(ws, P.Ut), at<double>(ws, P.Mv), f2,
+                           at<double>(ws, P.work), s));
+    RSVD_TRY(launch_residual_spec_final(sigma2, out, fro_requested, s));
     return RSVD_OK;
 }
 
@@ -177,7 +273,8 @@ rsvd_status check_params(const rsvd_matrix* A, const rsvd_params* p) {
     if (!p) return RSVD_ERR_INVALID_ARG;
     const int64_t mn = std::min(A->rows, A->cols);
     if (p->k < 1 || p->k > mn || p->p < 0 || p->q < 0 || p->q > 64) return RSVD_ERR_INVALID_ARG;
-    if (p->residual != 0 && p->residual != 2) return RSVD_ERR_INVALID_ARG;
+    if (p->residual < 0 || p->residual > 3 || p->residual_iters < 0 || p->residual_iters > 1000)
+        return RSVD_ERR_INVALID_ARG;
     if (round_up(std::min<int64_t>(p->k + p->p, mn), 16) > kMaxL) return RSVD_ERR_UNSUPPORTED;
     return RSVD_OK;
 }
@@ -258,7 +355,8 @@ rsvd_status rsvd_workspace_size(const rsvd_handle* h, const rsvd_matrix* A, cons
     if (st != RSVD_OK) return st;
     if ((st = check_params(A, params)) != RSVD_OK) return st;
     Plan P;
-    if (!make_plan(A->dtype, A->rows, A->cols, params->k, params->p, params->q, params->return_full_l, P))
+    if (!make_plan(A->dtype, A->rows, A->cols, params->k, params->p, params->q, params->return_full_l, P,
+                   params->residual & 1))
         return RSVD_ERR_UNSUPPORTED;
     *bytes = P.total;
     return RSVD_OK;
@@ -271,7 +369,8 @@ rsvd_status rsvd_solve(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* 
     if (st != RSVD_OK) return st;
     if ((st = check_params(A, params)) != RSVD_OK) return st;
     Plan P;
-    if (!make_plan(A->dtype, A->rows, A->cols, params->k, params->p, params->q, params->return_full_l, P))
+    if (!make_plan(A->dtype, A->rows, A->cols, params->k, params->p, params->q, params->return_full_l, P,
+                   params->residual & 1))
         return RSVD_ERR_UNSUPPORTED;
     if (!out->U || !out->S || !out->Vt || !out->info) return RSVD_ERR_INVALID_ARG;
     if (out->ldu < P.r || out->ldvt < P.n) return RSVD_ERR_INVALID_ARG;
@@ -325,9 +424,14 @@ rsvd_status rsvd_solve(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* 
     RSVD_TRY(launch_apply(dt, Q, L, P.m, L, Ut, L, r, out->U, out->ldu, 0, sign, nullptr, nullptr, nullptr, 0, s));
     RSVD_TRY(launch_scale_rows(dt, out->Vt, out->ldvt, r, P.n, sign, s));
     if (out->Q) RSVD_TRY(launch_copy2d(dt, Q, L, P.m, (int)P.l, out->Q, out->ldq, (int)P.l, s));
-    if (params->residual == 2)
+    if (params->residual & 2)
         RSVD_TRY(launch_residual_fro(dt, A->data, A->ld, P.m, P.n, Q, Bt, (int)P.l, L, at<double>(ws, P.res_part),
                                      out->residual, s));
+    if (params->residual & 1) {
+        const int iters = params->residual_iters ? params->residual_iters : kSpecItersDefault;
+        if ((st = run_spectral(P, ws, A, Q, params->seed, iters, out->residual, params->residual & 2, s)) != RSVD_OK)
+            return st;
+    }
     RSVD_TRY(launch_export_info(flags, out->info, s));
     return RSVD_OK;
 }

@@ -360,3 +360,56 @@ hipError_t launch_residual_fro(int dtype, const void* A, int64_t lda, int64_t m,
 }
 
 }  // namespace rsvd
+
+namespace rsvd {
+
+// Spectral norm of E = A - Q Q^T A by block power iteration, with E kept
+// implicit: for a block Z, E Z = W - Q C with W = A Z and C = Q^T W.  The
+// host stores [Q | W] side by side (L + 16 columns), the Gram kernel forms
+// its chunk partials, and this kernel reads C from the partial tiles (Q-block
+// rows, W-block column), summed in chunk order, and writes the coefficient
+// matrix M = [-C; I_b] ((L + 16) x 16, FP64), so that E Z = [Q | W] M is one
+// FP64 apply.  Columns b..15 of M are zero.
+__global__ __launch_bounds__(256) void proj_coef_kernel(const double* __restrict__ part, int nchunks, int L, int b,
+                                                        double* __restrict__ M) {
+    const int nt = L / 16 + 1, npairs = nt * (nt + 1) / 2, tw = nt - 1;
+    for (int idx = blockIdx.x * 256 + threadIdx.x; idx < (L + 16) * 16; idx += 256 * gridDim.x) {
+        const int a = idx >> 4, c = idx & 15;
+        double v = 0.0;
+        if (c < b) {
+            if (a < L) {
+                const int ta = a >> 4;
+                const int pr = ta * nt - ta * (ta - 1) / 2 + (tw - ta);    // row-major upper-triangle index
+                const int e = (a & 15) * 16 + c;
+                double sum = 0.0;
+                for (int ch = 0; ch < nchunks; ++ch) sum += part[((size_t)ch * npairs + pr) * 256 + e];
+                v = -sum;
+            } else {
+                v = (a - L == c) ? 1.0 : 0.0;
+            }
+        }
+        M[idx] = v;
+    }
+}
+
+hipError_t launch_proj_coef(const double* partials, int64_t rows, int L, int b, double* M, hipStream_t s) {
+    hipLaunchKernelGGL(proj_coef_kernel, dim3((unsigned)ceil_div((L + 16) * 16, 256)), dim3(256), 0, s, partials,
+                       gram_chunks(rows), L, b, M);
+    return hipGetLastError();
+}
+
+// residual[0] = largest Ritz value of the estimator; residual[1] = 0 when the
+// Frobenius norm was not requested.
+__global__ void residual_spec_final_kernel(const double* sigma, double* out, int fro_requested) {
+    if (threadIdx.x == 0) {
+        out[0] = sigma[0];
+        if (!fro_requested) out[1] = 0.0;
+    }
+}
+
+hipError_t launch_residual_spec_final(const double* sigma, double* out, int fro_requested, hipStream_t s) {
+    hipLaunchKernelGGL(residual_spec_final_kernel, dim3(1), dim3(64), 0, s, sigma, out, fro_requested);
+    return hipGetLastError();
+}
+
+}  // namespace rsvd

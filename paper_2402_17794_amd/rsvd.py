@@ -31,7 +31,7 @@ class rsvd_matrix(ctypes.Structure):
 class rsvd_params(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int64), ("p", ctypes.c_int64), ("q", ctypes.c_int64), ("seed", ctypes.c_uint64),
                 ("residual", ctypes.c_int32), ("return_full_l", ctypes.c_int32),
-                ("force_householder", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
+                ("force_householder", ctypes.c_int32), ("residual_iters", ctypes.c_int32)]
 
 
 class rsvd_result(ctypes.Structure):
@@ -137,12 +137,27 @@ def workspace_size(A, k, p=10, q=0, return_full_l=False):
     return nb.value
 
 
+RESIDUAL_SPECTRAL, RESIDUAL_FROBENIUS = 1, 2
+
+
+def _residual_mode(residual):
+    """True keeps the Frobenius norm alone; an int selects the header's bits."""
+    if residual is True:
+        return RESIDUAL_FROBENIUS
+    if not residual:
+        return 0
+    return int(residual)
+
+
 class Solver:
     """Reusable solve for one (shape, dtype, k, p, q): owns the output tensors
-    and the workspace, so repeated calls allocate nothing."""
+    and the workspace, so repeated calls allocate nothing.  residual: False,
+    True (Frobenius), or the header's bit mask (1 spectral estimate, 2
+    Frobenius, 3 both); residual_iters: power iterations of the spectral
+    estimate (0 = library default)."""
 
     def __init__(self, A, k, p=10, q=0, seed=0, residual=False, return_full_l=False, force_householder=False,
-                 return_q=False, stream=None):
+                 return_q=False, stream=None, residual_iters=0):
         self.lib = load_library()
         self.A = A
         self.M = _as_matrix(A)
@@ -150,7 +165,9 @@ class Solver:
         self.l = l_used(m, n, k, p)
         r = self.l if return_full_l else k
         dev = A.device
-        self.params = rsvd_params(k, p, q, seed, 2 if residual else 0, int(return_full_l), int(force_householder), 0)
+        residual = _residual_mode(residual)
+        self.params = rsvd_params(k, p, q, seed, residual, int(return_full_l), int(force_householder),
+                                  int(residual_iters))
         self.U = torch.empty((m, r), dtype=A.dtype, device=dev)
         self.S = torch.empty((r,), dtype=torch.float64, device=dev)
         self.Vt = torch.empty((r, n), dtype=A.dtype, device=dev)
@@ -178,11 +195,12 @@ class Solver:
 
 
 def solve(A, k, p=10, q=0, seed=0, residual=False, return_full_l=False, force_householder=False, return_q=False,
-          stream=None):
+          stream=None, residual_iters=0):
     """Randomized SVD (Algorithm 4) of a CUDA tensor A.  Returns a dict with
     U (m x r), S (r, float64), Vt (r x n), info (int), l, and optionally
-    residual (||A - QQ^T A||_F) and Q (m x l)."""
-    s = Solver(A, k, p, q, seed, residual, return_full_l, force_householder, return_q, stream)()
+    residual_t ([spectral estimate, Frobenius norm] of A - QQ^T A, float64
+    tensor) and Q (m x l)."""
+    s = Solver(A, k, p, q, seed, residual, return_full_l, force_householder, return_q, stream, residual_iters)()
     out = dict(U=s.U, S=s.S, Vt=s.Vt, l=s.l, info_tensor=s.info)
     if residual:
         out["residual_t"] = s.res

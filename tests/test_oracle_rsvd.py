@@ -183,3 +183,32 @@ def test_seed_determinism_and_omega_override():
     assert np.array_equal(a["U"], b["U"]) and np.array_equal(a["U"], c["U"])
     d = rsvd_alg4(A, 10, 5, 1, seed=43)
     assert not np.allclose(a["U"], d["U"]) or not np.allclose(a["S"], d["S"], rtol=0, atol=0)
+
+
+# ---- spectral-norm estimator (block power iteration with Rayleigh-Ritz) ----
+# Pins: when rank(E) <= block, one iteration puts range(E^T) inside range(Z),
+# so the Ritz value is sigma_1(E) exactly (library SVD); with a gap the
+# estimate converges to sigma_1; it never exceeds sigma_1 (a Ritz value of
+# E^T E on an orthonormal block), for any number of iterations.
+
+@pytest.mark.parametrize("m,n,rank", [(200, 60, 10), (60, 200, 16), (150, 150, 1)])
+def test_spectral_estimator_exact_when_rank_within_block(m, n, rank):
+    from oracle.rsvd import spectral_norm_power
+    A, _ = W.exact_rank(m, n, rank, 3, 4, top=2.0, ratio=0.8)
+    exact = np.linalg.svd(A, compute_uv=False)[0]
+    assert abs(spectral_norm_power(A, iters=1, block=16, seed=5) - exact) <= 1e-12 * exact
+
+
+def test_spectral_estimator_converges_and_bounds():
+    from oracle.rsvd import spectral_norm_power
+    sig = np.concatenate([[1.0], 0.5 * W.spectrum_geometric(79, 0.97)])     # gap after sigma_1
+    A = W.known_spectrum(300, 80, sig, 7, 8)
+    assert abs(spectral_norm_power(A, iters=30, block=16, seed=1) - 1.0) <= 1e-12
+    rng = np.random.default_rng(4)
+    for t in range(4):
+        G = rng.standard_normal((120, 90))
+        s1 = np.linalg.svd(G, compute_uv=False)[0]
+        for iters in (0, 1, 3):
+            est = spectral_norm_power(G, iters=iters, block=16, seed=t)
+            assert est <= s1 * (1 + 1e-13)
+            assert est >= 0.5 * s1
