@@ -27,6 +27,10 @@ if ROOT not in sys.path:
 
 METRIC = "RSVD solves/s + MFMA TFLOP/s at fixed rel. error vs FP64; p50/p99 latency"
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}      # MI355X dense MFMA peaks
+HBM_PEAK_GBS = 8000.0                          # MI355X HBM3E
+LP_KIND_NAMES = {0: "sketch A*Omega (lp_gemm_kernel<AB,false,true,LT>)",
+                 1: "A*W (lp_gemm_kernel<AB,false,false,LT>)",
+                 2: "A^T*Q (lp_gemm_kernel<AB,true,false,LT>)"}
 KIND_NAMES = {0: "sketch A*Omega (skinny_gemm_kernel<float,false,true,LT>)",
               1: "A*W (skinny_gemm_kernel<float,false,false,LT>)",
               2: "A^T*Q (skinny_gemm_kernel<float,true,false,LT>)"}
@@ -42,6 +46,108 @@ def _describe(name, cfg):
         spec = "60 Gaussian bumps + N(0,0.05^2) noise"
     return (f"{name}: A {cfg['m']}x{cfg['n']} {cfg['dtype']}, {spec}, Haar U,V (numpy PCG64 seeds 1,2); "
             f"k={cfg['k']} p={cfg['p']} q={cfg['q']}; Philox Omega seed 0")
+
+
+def _time_solver(torch, solver, steps, warmup):
+    for _ in range(warmup):
+        solver()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        evs[i][0].record()
+        solver()
+        evs[i][1].record()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dt, np.array([a.elapsed_time(b) for a, b in evs])
+
+
+def bench_lowp(args, cfg, A, torch, rsvd, workloads):
+    """The mixed-precision workload: the same FP32 matrix solved in FP32, and
+    stored in BF16 and in column-scaled FP8 (power iterations on the stored
+    A with one extra pass, Rayleigh-Ritz projection on the FP32 copy).  The
+    headline value is the BF16 form; every form carries its own roofline and
+    its error against the FP64 oracle on the FP32 matrix."""
+    m, n, k, p, q = cfg["m"], cfg["n"], cfg["k"], cfg["p"], cfg["q"]
+    dev = A.device
+    forms = {}
+    for name in ("f32", "bf16", "fp8"):
+        M = A if name == "f32" else rsvd.quantize(A, rsvd.RSVD_BF16 if name == "bf16" else rsvd.RSVD_FP8_E4M3)
+        solver = rsvd.Solver(M, k, p, q, seed=0)
+        l = solver.l
+        dt, lat = _time_solver(torch, solver, args.steps, args.warmup)
+        rsvd.profile_enable(dev, True)
+        for _ in range(max(2, args.steps // 4)):
+            solver()
+        torch.cuda.synchronize()
+        rsvd.profile_enable(dev, False)
+        kinds = {}
+        for kind in (0, 1, 2, 4):
+            tot, cnt = rsvd.profile_read(dev, kind)
+            if cnt:
+                kinds[kind] = (tot, cnt)
+        lp_kinds = [kk for kk in kinds if kk != 4]
+        dom = max(lp_kinds, key=lambda kk: kinds[kk][0])
+        dom_ms = kinds[dom][0] / kinds[dom][1]
+        if name == "f32":
+            achieved = 2.0 * m * n * l / (dom_ms * 1e-3) / 1e12
+            roof = {"bound": "mfma", "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s", "frac": achieved / 157.3}
+        else:
+            nbytes = m * n * (2 if name == "bf16" else 1)
+            achieved = nbytes / (dom_ms * 1e-3) / 1e9
+            roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": float(nbytes)}
+        kname = KIND_NAMES[dom] if name == "f32" else LP_KIND_NAMES[dom].replace("AB", "2" if name == "bf16" else "1")
+        roof.update({"kernel": kname,
+                     "avg_launch_ms": dom_ms, "launches_per_solve": kinds[dom][1] / max(2, args.steps // 4),
+                     "traffic": None})
+        if 4 in kinds:
+            roof["fp32_projection_ms"] = kinds[4][0] / kinds[4][1]
+        forms[name] = {"solves_per_s": args.steps / dt, "ms_per_step": dt / args.steps * 1e3,
+                       "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                       "power_iterations": q + (0 if name == "f32" else 1), "info": int(solver.info.item()),
+                       "S": solver.S.cpu().numpy(), "roofline": roof}
+        print(f"bench: {name}: {forms[name]['ms_per_step']:.2f} ms per solve", file=sys.stderr, flush=True)
+        del solver, M
+        torch.cuda.empty_cache()
+    sig = workloads.config_sigma(args.config)
+    for f in forms.values():
+        f["err_vs_true_spectrum_normwise"] = float(np.max(np.abs(f["S"] - sig[:k])) / sig[0])
+    out = {
+        "metric": METRIC, "value": forms["bf16"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": forms["bf16"]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": _describe(args.config, cfg) + "; stored in BF16 (headline), FP8 E4M3 with column "
+                   "scales, and FP32; one extra power iteration for BF16/FP8; FP32 Rayleigh-Ritz",
+                   "m": m, "n": n, "k": k, "p": p, "q": q, "l": rsvd.l_used(m, n, k, p)},
+        "p50_ms": forms["bf16"]["p50_ms"], "p99_ms": forms["bf16"]["p99_ms"],
+        "roofline": forms["bf16"]["roofline"],
+    }
+    if not args.no_cpu_baseline:
+        from oracle.rsvd import rsvd_alg4
+        Ah = A.double().cpu().numpy()
+        print("bench: running the FP64 CPU oracle on the FP32 matrix ...", file=sys.stderr, flush=True)
+        tc = time.perf_counter()
+        ref = rsvd_alg4(Ah, k, p, q, seed=0)
+        tcpu = time.perf_counter() - tc
+        del Ah
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+        except Exception:
+            threads = len(os.sched_getaffinity(0))
+        out["cpu_baseline"] = {"value": 1.0 / tcpu, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+                               "sample": f"1 full FP64 solve of the same workload ({m}x{n}, k={k}, p={p}, q={q}), "
+                                         f"{tcpu:.1f} s wall clock incl. Omega generation"}
+        for f in forms.values():
+            f["rel_err_vs_fp64_oracle"] = {
+                "sigma_normwise_max": float(np.max(np.abs(f["S"] - ref["S"])) / ref["S"][0]),
+                "sigma_relative_max": float(np.max(np.abs(f["S"] - ref["S"]) / ref["S"]))}
+    for f in forms.values():
+        del f["S"]
+    out["forms"] = forms
+    return out
 
 
 def main():
@@ -91,6 +197,10 @@ def main():
     torch.cuda.synchronize()
     del calib_src, calib_dst
 
+    if cfg.get("lowp") and args.input == "workload":
+        print(json.dumps(bench_lowp(args, cfg, A, torch, rsvd, workloads)), flush=True)
+        return
+
     solver = rsvd.Solver(A, k, p, q, seed=0)
     l = solver.l
     for _ in range(args.warmup):
@@ -132,6 +242,21 @@ def main():
     gemm_ms = sum(v[0] for v in kinds.values()) / args.steps
     flops_solve = (2 * q + 2) * 2.0 * m * n * l
 
+    # The residual ||A - QQ^T A|| (spectral estimate, t = 4, and Frobenius
+    # norm), optional in a solve and timed separately: ms per solve with it
+    # minus ms per solve without it.
+    res_solver = rsvd.Solver(A, k, p, q, seed=0, residual=3, residual_iters=4)
+    res_solver()
+    torch.cuda.synchronize()
+    nres = max(3, args.steps // 4)
+    tr0 = time.perf_counter()
+    for _ in range(nres):
+        res_solver()
+    torch.cuda.synchronize()
+    res_ms = (time.perf_counter() - tr0) / nres * 1e3 - dt / args.steps * 1e3
+    res_gpu = res_solver.res.cpu().numpy()
+    del res_solver
+
     # HBM bytes per launch of the dominant kernel from the committed counter
     # summary, only while the GEMM sources are the ones the counters measured.
     traffic = None
@@ -161,6 +286,8 @@ def main():
         "tflops_algorithmic": flops_solve / (dt / args.steps) / 1e12,
         "gemm_ms_per_solve": gemm_ms,
         "info": info,
+        "residual": {"spectral_estimate_t4": float(res_gpu[0]), "frobenius": float(res_gpu[1]),
+                     "ms_per_solve": res_ms},
         "roofline": {
             "bound": "mfma",
             "kernel": KIND_NAMES[dom].replace("float", "double") if cfg["dtype"] == "f64" else KIND_NAMES[dom],
@@ -198,6 +325,11 @@ def main():
                                "sample": f"{nsol} full solve(s) of the same workload ({m}x{n}, k={k}, p={p}, "
                                          f"q={q}) in float64, {tcpu:.1f} s wall clock incl. Omega generation"}
         S_ref = ref["S"]
+        from oracle.rsvd import spectral_norm_power
+        E = Ah - ref["Q"] @ (ref["Q"].T @ Ah)
+        out["residual"]["oracle_spectral_estimate_t4"] = spectral_norm_power(E, iters=4, block=16, seed=0)
+        out["residual"]["oracle_frobenius"] = float(np.linalg.norm(E))
+        del E
         out["rel_err_vs_fp64"] = {
             "sigma_normwise_max": float(np.max(np.abs(S_gpu - S_ref)) / S_ref[0]),
             "sigma_relative_max": float(np.max(np.abs(S_gpu - S_ref) / S_ref)),

@@ -55,8 +55,14 @@ typedef enum {
 
 typedef enum {
     RSVD_F64 = 0,                  /* double: all arithmetic in FP64 (FP64 MFMA) */
-    RSVD_F32 = 1                   /* float: products with A on FP32 MFMA, FP32
+    RSVD_F32 = 1,                  /* float: products with A on FP32 MFMA, FP32
                                       accumulation; Gram, Cholesky, small SVD FP64 */
+    RSVD_BF16 = 2,                 /* A stored as bfloat16 (uint16 patterns): products on the
+                                      BF16 matrix instructions with FP32 accumulation, the other
+                                      operand rounded to BF16; everything else as RSVD_F32 */
+    RSVD_FP8_E4M3 = 3              /* A stored as FP8 E4M3 (OCP E4M3FN, max 448) with per-column
+                                      FP32 scales: A = Aq diag(col_scale); products on the FP8
+                                      matrix instructions, FP32 accumulation */
 } rsvd_dtype;
 
 /* Bits of the device `info` word written by rsvd_solve / rsvd_orth. */
@@ -72,12 +78,23 @@ typedef struct rsvd_handle rsvd_handle;
 /* Input matrix A: rows x cols, row-major, leading dimension ld (elements),
  * 1 <= rows, cols < 2^31.  A is streamed with 16-byte loads when data is
  * 16-byte aligned and ld is a multiple of 4 (RSVD_F32) or 2 (RSVD_F64);
- * otherwise element loads are used (correct, slower). */
+ * otherwise element loads are used (correct, slower).  RSVD_BF16 and
+ * RSVD_FP8_E4M3 data must be 16-byte aligned with ld a multiple of 8 / 16
+ * (RSVD_ERR_UNSUPPORTED otherwise); rsvd_quantize produces such matrices.
+ *
+ * Low-precision forms (the precision layer; the thesis computes in double
+ * precision): the power iterations run on the stored A with one extra
+ * power iteration by default (rsvd_params.extra_power_pass), and the
+ * projection B = Q^T A of Algorithm 4 step 6 (the Rayleigh-Ritz step) uses
+ * `master`, an FP32 copy of A, when given; the residual norms need it. */
 typedef struct {
     const void* data;
     int32_t dtype;                 /* rsvd_dtype */
     int32_t reserved0;
     int64_t rows, cols, ld;
+    const float* col_scale;        /* RSVD_FP8_E4M3: cols scales (device), required; else NULL */
+    const float* master;           /* BF16 / FP8: optional FP32 copy of A (device), else NULL */
+    int64_t ld_master;             /* leading dimension of master (>= cols) */
 } rsvd_matrix;
 
 /* Parameters of Algorithm 4 (inputs A, k, p, q of the algorithm statement). */
@@ -97,11 +114,14 @@ typedef struct {
                                       Y = orth(E Z), Z = orth(E^T Y); the estimate is the largest singular value
                                       of E Z (a lower bound of ||E||_2 up to rounding, converging as t grows).
                                       0 <= residual_iters <= 1000. */
+    int32_t extra_power_pass;      /* BF16 / FP8 A: power iterations added to q; -1 = default (1);
+                                      ignored for RSVD_F32 / RSVD_F64 */
+    int32_t reserved1;
 } rsvd_params;
 
-/* Outputs.  r = k, or l when return_full_l is set.  U and Vt have the
- * dtype of A.  S, residual are doubles.  Q (optional) receives the final
- * m x l orthonormal basis of Stage 1. */
+/* Outputs.  r = k, or l when return_full_l is set.  U, Vt and Q have the
+ * dtype of A (float for BF16 / FP8 A).  S, residual are doubles.  Q
+ * (optional) receives the final m x l orthonormal basis of Stage 1. */
 typedef struct {
     void* U;  int64_t ldu;         /* m x r, row-major, ldu >= r */
     double* S;                     /* r singular values, descending */
@@ -141,10 +161,22 @@ const char* rsvd_status_string(rsvd_status s);
  * handle; the split-K reduction that follows the product is outside them).
  * rsvd_profile_read waits for the recorded events of one kind (0: the
  * sketch A * Omega with the generated test matrix, 1: A * X, 2: A^T * X,
- * 3: all kinds), returns the summed kernel time in milliseconds and the
- * number of launches, and forgets those records. */
+ * 3: all kinds, 4: the FP32 projection A^T Q on the master copy of a BF16 /
+ * FP8 A), returns the summed kernel time in milliseconds and the number of
+ * launches, and forgets those records (kind 3 forgets all). */
 rsvd_status rsvd_profile_enable(rsvd_handle* h, int32_t enable);
 rsvd_status rsvd_profile_read(rsvd_handle* h, int32_t kind, double* total_ms, int64_t* launches);
+
+/* Low-precision copy of an FP32 matrix (rows x cols, lda) on `stream`:
+ * dtype RSVD_BF16: out = uint16 BF16 patterns (round to nearest even), ldo;
+ * dtype RSVD_FP8_E4M3: amax_j = max_i |A_ij|, col_scale[j] = amax_j / 448
+ * (1 for a zero column), out_ij = e4m3(A_ij * (448 / amax_j)) (round to
+ * nearest even, saturating at 448), each division and product rounded in
+ * FP32.  All pointers device; col_scale (cols floats) is required for FP8.
+ * For use as an rsvd_matrix, out should be 16-byte aligned with ldo a
+ * multiple of 8 (BF16) / 16 (FP8). */
+rsvd_status rsvd_quantize(int32_t dtype, const float* A, int64_t rows, int64_t cols, int64_t lda, void* out,
+                          int64_t ldo, float* col_scale, void* stream);
 
 /* ---- Single steps of the path, for testing each kernel on its own. ---- */
 
@@ -168,7 +200,10 @@ rsvd_status rsvd_philox_words(uint64_t seed, uint32_t stream_id, const uint32_t*
 /* Y = A X (trans = 0; X is n x ncols, Y is m x ncols) or Y = A^T X
  * (trans = 1; X is m x ncols, Y is n x ncols) with the solve's MFMA kernels.
  * If X is NULL and trans = 0, X is the test matrix Omega(seed) (generated in
- * the kernel).  ncols <= 512.  Uses `workspace` (rsvd_gemm_workspace_size). */
+ * the kernel).  ncols <= 288.  For BF16 / FP8 A, X and Y are float and X is
+ * rounded to A's format first (FP8: rows of X scaled by col_scale for
+ * trans = 0, then per-column scales t_c = amax_c / 448), exactly as in a
+ * solve.  Uses `workspace` (rsvd_gemm_workspace_size). */
 rsvd_status rsvd_gemm_workspace_size(const rsvd_matrix* A, int32_t trans, int64_t ncols, size_t* bytes);
 rsvd_status rsvd_gemm(rsvd_handle* h, const rsvd_matrix* A, int32_t trans, const void* X, int64_t ldx,
                       uint64_t seed, int64_t ncols, void* Y, int64_t ldy,

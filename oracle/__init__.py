@@ -20,5 +20,5 @@ Everything is real (the paper's conjugate transpose becomes a transpose) and
 computed in float64.
 """
 
-from . import philox, linalg, rsvd, bounds  # noqa: F401
+from . import philox, linalg, rsvd, bounds, quant  # noqa: F401
 from .rsvd import rsvd_alg4, rsvd_alg3, residual_norms  # noqa: F401

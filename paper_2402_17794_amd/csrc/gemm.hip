@@ -397,6 +397,14 @@ hipError_t launch_gemm(int dtype, GemmArgs a, hipStream_t s, hipEvent_t product_
     return hipGetLastError();
 }
 
+hipError_t launch_splitk_reduce_f32(const float* partials, int64_t M, int L, int splits, float* Y, int64_t ldy,
+                                    int wcols, hipStream_t s) {
+    const int64_t nvec = M * (L / 4);
+    hipLaunchKernelGGL((splitk_reduce_kernel<float, kMaxSplits>), dim3((unsigned)ceil_div(nvec, 256)), dim3(256), 0, s,
+                       partials, M, L, splits, Y, ldy, wcols);
+    return hipGetLastError();
+}
+
 // ---- test entry points: Omega materialised, raw Philox words ----
 template <typename T>
 __global__ void omega_kernel(uint64_t seed, uint32_t stream, int64_t n, int64_t l, T* out, int64_t ld) {

@@ -37,6 +37,40 @@ int gemm_row_tiles(int dtype, int64_t M, int ncols);
 // before the split-K reduction, so that it times the product alone.
 hipError_t launch_gemm(int dtype, GemmArgs a, hipStream_t s, hipEvent_t product_done = nullptr);
 
+// Y (ldy, first wcols columns) = sum of the `splits` FP32 slices of M x L
+// partial products, in slice order.
+hipError_t launch_splitk_reduce_f32(const float* partials, int64_t M, int L, int splits, float* Y, int64_t ldy,
+                                    int wcols, hipStream_t s);
+
+// ---- products with a low-precision A (gemm_lp.hip) ----
+constexpr int kFmtBf16 = 2, kFmtFp8 = 3;           // RSVD_BF16, RSVD_FP8_E4M3
+struct LpGemmArgs {
+    const void* A; int64_t lda;     // BF16 or FP8 A, ld in elements (a multiple of 16 bytes), 16-byte aligned
+    const float* col_scale;         // FP8: the column scales of A, else NULL
+    int trans;                      // 0: Y = A X (M = rows, K = cols); 1: Y = A^T X
+    int64_t M, K;
+    const void* Xt; int64_t ldt;    // prepared operand (L x ldt, k-contiguous); NULL with trans = 0 -> Omega
+    const float* xscale;            // FP8: column scales of the operand (ncols), else NULL
+    const float* omega_scale;       // FP8 sketch: device pointer to max_j col_scale_j
+    uint64_t seed;
+    int ncols, wcols;
+    float* Y; int64_t ldy;
+    float* partials;                // splits * M * L floats (splits > 1)
+    int splits;
+};
+// FP32 A (rows x cols, lda) -> BF16 or column-scaled FP8 (col_scale: cols floats).
+hipError_t launch_quantize(int fmt, const float* A, int64_t rows, int64_t cols, int64_t lda, void* Q, int64_t ldq,
+                           float* col_scale, hipStream_t s);
+// X (K x ncols FP32, ldx) -> Xt (L x ldt, k-contiguous, zero padded; ldt a
+// multiple of 64 >= K) in the format of A; FP8 also writes the column
+// scales tscale (ncols) and uses amax_tmp (L words).  row_scale (FP8, K
+// floats, nullable) multiplies the rows of X first.
+hipError_t launch_lp_operand(int fmt, const float* X, int64_t K, int ncols, int64_t ldx, const float* row_scale,
+                             void* Xt, int64_t ldt, int L, float* tscale, unsigned* amax_tmp, hipStream_t s);
+hipError_t launch_vec_max(const float* v, int64_t n, float* out, hipStream_t s);
+size_t lp_partials_elems(int64_t M, int64_t K, int ncols, int* splits_out);
+hipError_t launch_lp_gemm(int fmt, LpGemmArgs a, hipStream_t s, hipEvent_t product_done = nullptr);
+
 // ---- Gram, Cholesky, apply, Householder (orth.hip) ----
 // Chunk partials of G = Y^T Y (FP64) for Y rows x L (dtype, zero padding):
 // gram_partials_elems doubles, consumed by launch_chol with the same rows.

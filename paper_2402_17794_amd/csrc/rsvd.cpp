@@ -40,6 +40,10 @@ namespace {
 constexpr size_t kAlign = 256;
 
 size_t esize(int dtype) { return dtype == RSVD_F64 ? 8 : 4; }
+bool is_lowp(int dtype) { return dtype == RSVD_BF16 || dtype == RSVD_FP8_E4M3; }
+int lowp_bytes(int dtype) { return dtype == RSVD_BF16 ? 2 : 1; }
+// Working precision of the panels (Y, Q, W, U, V): float for BF16 / FP8 A.
+int work_dtype(int dtype) { return is_lowp(dtype) ? RSVD_F32 : dtype; }
 
 struct Carver {
     size_t off = 0;
@@ -59,6 +63,11 @@ struct Plan {
     int splits_nn = 1, splits_tn = 1;
     size_t counters, flags, part, Y, Q, W, Q1, GP, R, Rinv, Ut, Mv, sigma, shift, sign, amax_val, amax_idx, H, Qw,
         work, res_part, res;
+    // Low-precision A: format, prepared operand (L x ldt) and its scales.
+    int afmt = 0;
+    int splits_lp_nn = 1, splits_lp_tn = 1;
+    int64_t ldt = 0;
+    size_t Xt = 0, tsc = 0, amax = 0, smax = 0;
     // Spectral-norm estimator of the residual (allocated when requested):
     // block of sb <= 16 columns padded to 16.
     int spectral = 0, sb = 0;
@@ -70,8 +79,10 @@ struct Plan {
 constexpr int kSpecBlock = 16;      // block size of the spectral-norm estimator
 constexpr int kSpecItersDefault = 4;
 
-bool make_plan(int dtype, int64_t m, int64_t n, int64_t k, int64_t p, int64_t q, int full, Plan& P,
+bool make_plan(int adtype, int64_t m, int64_t n, int64_t k, int64_t p, int64_t q, int full, Plan& P,
                int spectral = 0) {
+    const int dtype = work_dtype(adtype);
+    P.afmt = adtype;
     P.dtype = dtype;
     P.m = m; P.n = n; P.k = k; P.p = p; P.q = q;
     P.l = std::min<int64_t>(k + p, std::min(m, n));
@@ -90,7 +101,12 @@ bool make_plan(int dtype, int64_t m, int64_t n, int64_t k, int64_t p, int64_t q,
     Carver c;
     P.counters = c.take(sizeof(int) * (size_t)P.ncounters);
     P.flags = c.take(sizeof(DevFlags));
-    P.part = c.take(es * std::max<size_t>({pn, pt, pn16, pt16, 1}));
+    size_t plp = 0;
+    if (is_lowp(adtype)) {
+        plp = std::max(lp_partials_elems(m, n, P.L, &P.splits_lp_nn), lp_partials_elems(n, m, P.L, &P.splits_lp_tn));
+        P.ldt = round_up(mx, 64);
+    }
+    P.part = c.take(es * std::max<size_t>({pn, pt, pn16, pt16, plp, 1}));
     P.Y = c.take(es * (size_t)mx * P.L);
     P.Q = c.take(es * (size_t)m * P.L);
     P.W = c.take(es * (size_t)n * P.L);
@@ -111,6 +127,12 @@ bool make_plan(int dtype, int64_t m, int64_t n, int64_t k, int64_t p, int64_t q,
     P.work = c.take(sizeof(double) * (size_t)kMaxL * kMaxL);
     P.res_part = c.take(sizeof(double) * residual_partials(m, n));
     P.res = c.take(sizeof(double) * 2);
+    if (is_lowp(adtype)) {
+        P.Xt = c.take((size_t)lowp_bytes(adtype) * (size_t)P.L * (size_t)P.ldt);
+        P.tsc = c.take(sizeof(float) * (size_t)P.L);
+        P.amax = c.take(sizeof(unsigned) * (size_t)P.L);
+        P.smax = c.take(sizeof(float));
+    }
     if (spectral) {
         P.flags2 = c.take(sizeof(DevFlags));
         P.QW = c.take(es * (size_t)m * (P.L + kSpecBlock));
@@ -170,7 +192,7 @@ rsvd_status run_orth(const Plan& P, void* ws, int dtype, int64_t rows, const voi
 // Timed (rsvd_profile_*) when h is not NULL and profiling is on.
 rsvd_status run_product(rsvd_handle* h, const Plan& P, void* ws, const rsvd_matrix* A, int trans, const void* X,
                         int64_t ldx, uint64_t seed, int cols, int wcols, int splits, void* Yout, int64_t ldy,
-                        hipStream_t s) {
+                        hipStream_t s, int kind = -1) {
     GemmArgs g{};
     g.A = A->data;
     g.lda = A->ld;
@@ -190,7 +212,7 @@ rsvd_status run_product(rsvd_handle* h, const Plan& P, void* ws, const rsvd_matr
         RSVD_TRY(launch_gemm(P.dtype, g, s));
         return RSVD_OK;
     }
-    rsvd_handle::Rec rec{trans ? 2 : (X ? 1 : 0), nullptr, nullptr};
+    rsvd_handle::Rec rec{kind >= 0 ? kind : (trans ? 2 : (X ? 1 : 0)), nullptr, nullptr};
     rec.start = h->get_event();
     rec.stop = h->get_event();
     if (!rec.start || !rec.stop) return RSVD_ERR_DEVICE;
@@ -200,11 +222,68 @@ rsvd_status run_product(rsvd_handle* h, const Plan& P, void* ws, const rsvd_matr
     return RSVD_OK;
 }
 
+// Product with a BF16 / FP8 A on the solve's L-column float buffers: the
+// operand is rounded to A's format (and transposed) first, the test matrix
+// is generated in the kernel.
+rsvd_status run_product_lowp(rsvd_handle* h, const Plan& P, void* ws, const rsvd_matrix* A, int trans,
+                             const void* X, uint64_t seed, void* Yout, hipStream_t s) {
+    const int fmt = A->dtype;
+    LpGemmArgs a{};
+    a.A = A->data;
+    a.lda = A->ld;
+    a.col_scale = fmt == RSVD_FP8_E4M3 ? A->col_scale : nullptr;
+    a.trans = trans;
+    a.M = trans ? A->cols : A->rows;
+    a.K = trans ? A->rows : A->cols;
+    a.seed = seed;
+    a.ncols = X ? P.L : (int)P.l;
+    a.wcols = P.L;
+    a.Y = static_cast<float*>(Yout);
+    a.ldy = P.L;
+    a.partials = at<float>(ws, P.part);
+    a.splits = trans ? P.splits_lp_tn : P.splits_lp_nn;
+    a.ldt = P.ldt;
+    if (X) {
+        float* tsc = at<float>(ws, P.tsc);
+        RSVD_TRY(launch_lp_operand(fmt, static_cast<const float*>(X), a.K, P.L, P.L,
+                                   (fmt == RSVD_FP8_E4M3 && !trans) ? A->col_scale : nullptr, at<char>(ws, P.Xt),
+                                   P.ldt, P.L, tsc, at<unsigned>(ws, P.amax), s));
+        a.Xt = at<char>(ws, P.Xt);
+        a.xscale = fmt == RSVD_FP8_E4M3 ? tsc : nullptr;
+    } else {
+        a.omega_scale = fmt == RSVD_FP8_E4M3 ? at<float>(ws, P.smax) : nullptr;
+    }
+    if (!h || !h->profiling) {
+        RSVD_TRY(launch_lp_gemm(fmt, a, s));
+        return RSVD_OK;
+    }
+    rsvd_handle::Rec rec{trans ? 2 : (X ? 1 : 0), h->get_event(), h->get_event()};
+    if (!rec.start || !rec.stop) return RSVD_ERR_DEVICE;
+    RSVD_TRY(hipEventRecord(rec.start, s));
+    RSVD_TRY(launch_lp_gemm(fmt, a, s, rec.stop));
+    h->recs.push_back(rec);
+    return RSVD_OK;
+}
+
 // The products of Algorithm 4 on the solve's L-column buffers.
 rsvd_status run_gemm(rsvd_handle* h, const Plan& P, void* ws, const rsvd_matrix* A, int trans, const void* X,
-                     uint64_t seed, void* Yout, hipStream_t s) {
+                     uint64_t seed, void* Yout, hipStream_t s, int kind = -1) {
+    if (is_lowp(A->dtype)) return run_product_lowp(h, P, ws, A, trans, X, seed, Yout, s);
     const int cols = trans ? P.L : (X ? P.L : (int)P.l);
-    return run_product(h, P, ws, A, trans, X, P.L, seed, cols, P.L, trans ? P.splits_tn : P.splits_nn, Yout, P.L, s);
+    return run_product(h, P, ws, A, trans, X, P.L, seed, cols, P.L, trans ? P.splits_tn : P.splits_nn, Yout, P.L, s,
+                       kind);
+}
+
+// The FP32 copy of a low-precision A (for the Rayleigh-Ritz projection and
+// the residual), as a matrix of its own.
+rsvd_matrix master_view(const rsvd_matrix* A) {
+    rsvd_matrix M{};
+    M.data = A->master;
+    M.dtype = RSVD_F32;
+    M.rows = A->rows;
+    M.cols = A->cols;
+    M.ld = A->ld_master;
+    return M;
 }
 
 // ||A - Q Q^T A||_2 estimated by block power iteration on E = A - Q Q^T A
@@ -263,9 +342,15 @@ rsvd_status run_spectral(const Plan& P, void* ws, const rsvd_matrix* A, const vo
 
 rsvd_status check_matrix(const rsvd_matrix* A) {
     if (!A || !A->data) return RSVD_ERR_INVALID_ARG;
-    if (A->dtype != RSVD_F32 && A->dtype != RSVD_F64) return RSVD_ERR_INVALID_ARG;
+    if (A->dtype != RSVD_F32 && A->dtype != RSVD_F64 && !is_lowp(A->dtype)) return RSVD_ERR_INVALID_ARG;
     if (A->rows < 1 || A->cols < 1 || A->ld < A->cols) return RSVD_ERR_INVALID_ARG;
     if (A->rows > (int64_t)1 << 31 || A->cols > (int64_t)1 << 31) return RSVD_ERR_UNSUPPORTED;
+    if (is_lowp(A->dtype)) {
+        if (A->dtype == RSVD_FP8_E4M3 && !A->col_scale) return RSVD_ERR_INVALID_ARG;
+        if (A->master && A->ld_master < A->cols) return RSVD_ERR_INVALID_ARG;
+        if ((reinterpret_cast<uintptr_t>(A->data) & 15) || (A->ld * lowp_bytes(A->dtype)) % 16)
+            return RSVD_ERR_UNSUPPORTED;
+    }
     return RSVD_OK;
 }
 
@@ -275,6 +360,8 @@ rsvd_status check_params(const rsvd_matrix* A, const rsvd_params* p) {
     if (p->k < 1 || p->k > mn || p->p < 0 || p->q < 0 || p->q > 64) return RSVD_ERR_INVALID_ARG;
     if (p->residual < 0 || p->residual > 3 || p->residual_iters < 0 || p->residual_iters > 1000)
         return RSVD_ERR_INVALID_ARG;
+    if (p->extra_power_pass < -1 || p->extra_power_pass > 8) return RSVD_ERR_INVALID_ARG;
+    if (is_lowp(A->dtype) && p->residual && !A->master) return RSVD_ERR_INVALID_ARG;
     if (round_up(std::min<int64_t>(p->k + p->p, mn), 16) > kMaxL) return RSVD_ERR_UNSUPPORTED;
     return RSVD_OK;
 }
@@ -327,7 +414,7 @@ rsvd_status rsvd_profile_enable(rsvd_handle* h, int32_t enable) {
 }
 
 rsvd_status rsvd_profile_read(rsvd_handle* h, int32_t kind, double* total_ms, int64_t* launches) {
-    if (!h || !total_ms || !launches || kind < 0 || kind > 3) return RSVD_ERR_INVALID_ARG;
+    if (!h || !total_ms || !launches || kind < 0 || kind > 4) return RSVD_ERR_INVALID_ARG;
     double tot = 0.0;
     int64_t cnt = 0;
     std::vector<rsvd_handle::Rec> keep;
@@ -381,7 +468,10 @@ rsvd_status rsvd_solve(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* 
     if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_DEVICE;
 
     hipStream_t s = as_stream(stream);
-    const int dt = A->dtype;
+    const int dt = P.dtype;                 // working precision of the panels
+    const bool lowp = is_lowp(A->dtype);
+    const rsvd_matrix Am = lowp && A->master ? master_view(A) : *A;   // FP32 A for step 6 and the residual
+    const int64_t qeff = P.q + (lowp ? (params->extra_power_pass < 0 ? 1 : params->extra_power_pass) : 0);
     const int L = P.L;
     DevFlags* flags = at<DevFlags>(ws, P.flags);
     int* cnt = at<int>(ws, P.counters);
@@ -391,18 +481,20 @@ rsvd_status rsvd_solve(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* 
     const int hh = params->force_householder;
 
     RSVD_TRY(launch_init(cnt, P.ncounters, flags, s));
+    if (A->dtype == RSVD_FP8_E4M3) RSVD_TRY(launch_vec_max(A->col_scale, A->cols, at<float>(ws, P.smax), s));
     // Stage 1: steps 1-3, sketch with the generated test matrix, then orth.
     if ((st = run_gemm(h, P, ws, A, 0, nullptr, params->seed, Y, s)) != RSVD_OK) return st;
     if ((st = run_orth(P, ws, dt, P.m, Y, Q, hh, s)) != RSVD_OK) return st;
     // Steps 4-5: q power iterations, each product re-orthonormalised.
-    for (int64_t t = 0; t < P.q; ++t) {
+    for (int64_t t = 0; t < qeff; ++t) {
         if ((st = run_gemm(h, P, ws, A, 1, Q, 0, Y, s)) != RSVD_OK) return st;
         if ((st = run_orth(P, ws, dt, P.n, Y, W, hh, s)) != RSVD_OK) return st;
         if ((st = run_gemm(h, P, ws, A, 0, W, 0, Y, s)) != RSVD_OK) return st;
         if ((st = run_orth(P, ws, dt, P.m, Y, Q, hh, s)) != RSVD_OK) return st;
     }
-    // Stage 2: step 6 as B^T = A^T Q (n x l), step 7 small SVD, step 8 lift.
-    if ((st = run_gemm(h, P, ws, A, 1, Q, 0, Y, s)) != RSVD_OK) return st;
+    // Stage 2: step 6 as B^T = A^T Q (n x l), with the FP32 copy of a
+    // low-precision A when there is one; step 7 small SVD, step 8 lift.
+    if ((st = run_gemm(h, P, ws, &Am, 1, Q, 0, Y, s, lowp && A->master ? 4 : -1)) != RSVD_OK) return st;
     const void* Bt = Y;
     double* R = at<double>(ws, P.R);
     double* sigma = at<double>(ws, P.sigma);
@@ -425,11 +517,11 @@ rsvd_status rsvd_solve(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* 
     RSVD_TRY(launch_scale_rows(dt, out->Vt, out->ldvt, r, P.n, sign, s));
     if (out->Q) RSVD_TRY(launch_copy2d(dt, Q, L, P.m, (int)P.l, out->Q, out->ldq, (int)P.l, s));
     if (params->residual & 2)
-        RSVD_TRY(launch_residual_fro(dt, A->data, A->ld, P.m, P.n, Q, Bt, (int)P.l, L, at<double>(ws, P.res_part),
+        RSVD_TRY(launch_residual_fro(dt, Am.data, Am.ld, P.m, P.n, Q, Bt, (int)P.l, L, at<double>(ws, P.res_part),
                                      out->residual, s));
     if (params->residual & 1) {
         const int iters = params->residual_iters ? params->residual_iters : kSpecItersDefault;
-        if ((st = run_spectral(P, ws, A, Q, params->seed, iters, out->residual, params->residual & 2, s)) != RSVD_OK)
+        if ((st = run_spectral(P, ws, &Am, Q, params->seed, iters, out->residual, params->residual & 2, s)) != RSVD_OK)
             return st;
     }
     RSVD_TRY(launch_export_info(flags, out->info, s));
@@ -451,10 +543,41 @@ rsvd_status rsvd_philox_words(uint64_t seed, uint32_t stream_id, const uint32_t*
     return RSVD_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// Workspace of a single product with a BF16 / FP8 A (rsvd_gemm).
+struct LpGemmLayout {
+    int L = 0, splits = 1;
+    int64_t ldt = 0;
+    size_t Xt = 0, tsc = 0, amax = 0, smax = 0, part = 0, total = 0;
+};
+LpGemmLayout lp_gemm_layout(const rsvd_matrix* A, int trans, int64_t ncols) {
+    LpGemmLayout W;
+    const int64_t M = trans ? A->cols : A->rows, K = trans ? A->rows : A->cols;
+    W.L = (int)round_up(ncols, 16);
+    W.ldt = round_up(K, 64);
+    Carver c;
+    W.Xt = c.take((size_t)lowp_bytes(A->dtype) * (size_t)W.L * (size_t)W.ldt);
+    W.tsc = c.take(sizeof(float) * (size_t)W.L);
+    W.amax = c.take(sizeof(unsigned) * (size_t)W.L);
+    W.smax = c.take(sizeof(float));
+    W.part = c.take(sizeof(float) * std::max<size_t>(1, lp_partials_elems(M, K, (int)ncols, &W.splits)));
+    W.total = c.off;
+    return W;
+}
+}  // namespace
+
+extern "C" {
+
 rsvd_status rsvd_gemm_workspace_size(const rsvd_matrix* A, int32_t trans, int64_t ncols, size_t* bytes) {
     rsvd_status st = check_matrix(A);
     if (st != RSVD_OK) return st;
     if (!bytes || ncols < 1 || ncols > kMaxL) return RSVD_ERR_INVALID_ARG;
+    if (is_lowp(A->dtype)) {
+        *bytes = lp_gemm_layout(A, trans, ncols).total;
+        return RSVD_OK;
+    }
     const int64_t M = trans ? A->cols : A->rows, K = trans ? A->rows : A->cols;
     Carver c;
     c.take(sizeof(int) * (size_t)gemm_row_tiles(A->dtype, M, (int)ncols));
@@ -478,6 +601,27 @@ rsvd_status rsvd_gemm(rsvd_handle* h, const rsvd_matrix* A, int32_t trans, const
     if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_DEVICE;
     hipStream_t s = as_stream(stream);
     const int64_t M = trans ? A->cols : A->rows, K = trans ? A->rows : A->cols;
+    if (is_lowp(A->dtype)) {
+        const int fmt = A->dtype;
+        const LpGemmLayout W = lp_gemm_layout(A, trans, ncols);
+        LpGemmArgs a{};
+        a.A = A->data; a.lda = A->ld; a.col_scale = fmt == RSVD_FP8_E4M3 ? A->col_scale : nullptr;
+        a.trans = trans; a.M = M; a.K = K; a.seed = seed; a.ncols = (int)ncols; a.wcols = (int)ncols;
+        a.Y = static_cast<float*>(Y); a.ldy = ldy; a.partials = at<float>(ws, W.part); a.splits = W.splits;
+        a.ldt = W.ldt;
+        if (X) {
+            RSVD_TRY(launch_lp_operand(fmt, static_cast<const float*>(X), K, (int)ncols, ldx,
+                                       (fmt == RSVD_FP8_E4M3 && !trans) ? A->col_scale : nullptr, at<char>(ws, W.Xt),
+                                       W.ldt, W.L, at<float>(ws, W.tsc), at<unsigned>(ws, W.amax), s));
+            a.Xt = at<char>(ws, W.Xt);
+            a.xscale = fmt == RSVD_FP8_E4M3 ? at<float>(ws, W.tsc) : nullptr;
+        } else if (fmt == RSVD_FP8_E4M3) {
+            RSVD_TRY(launch_vec_max(A->col_scale, A->cols, at<float>(ws, W.smax), s));
+            a.omega_scale = at<float>(ws, W.smax);
+        }
+        RSVD_TRY(launch_lp_gemm(fmt, a, s));
+        return RSVD_OK;
+    }
     Carver c;
     const size_t o_cnt = c.take(sizeof(int) * (size_t)gemm_row_tiles(A->dtype, M, (int)ncols));
     const size_t o_flags = c.take(sizeof(DevFlags));
@@ -490,6 +634,14 @@ rsvd_status rsvd_gemm(rsvd_handle* h, const rsvd_matrix* A, int32_t trans, const
     g.X = X; g.ldx = ldx; g.seed = seed; g.ncols = (int)ncols; g.wcols = (int)ncols;
     g.Y = Y; g.ldy = ldy; g.partials = at<char>(ws, o_part); g.splits = splits;
     RSVD_TRY(launch_gemm(A->dtype, g, s));
+    return RSVD_OK;
+}
+
+rsvd_status rsvd_quantize(int32_t dtype, const float* A, int64_t rows, int64_t cols, int64_t lda, void* out,
+                          int64_t ldo, float* col_scale, void* stream) {
+    if (!is_lowp(dtype) || !A || !out || rows < 0 || cols < 0 || lda < cols || ldo < cols) return RSVD_ERR_INVALID_ARG;
+    if (dtype == RSVD_FP8_E4M3 && !col_scale) return RSVD_ERR_INVALID_ARG;
+    RSVD_TRY(launch_quantize(dtype, A, rows, cols, lda, out, ldo, col_scale, as_stream(stream)));
     return RSVD_OK;
 }
 

@@ -14,7 +14,7 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "librsvd.so")
 
-RSVD_F64, RSVD_F32 = 0, 1
+RSVD_F64, RSVD_F32, RSVD_BF16, RSVD_FP8_E4M3 = 0, 1, 2, 3
 INFO_QR_FALLBACK = 1
 INFO_SHIFTED_CHOLESKY = 2
 INFO_JACOBI_NOT_CONVERGED = 4
@@ -25,13 +25,36 @@ _DTYPES = {torch.float64: RSVD_F64, torch.float32: RSVD_F32}
 
 class rsvd_matrix(ctypes.Structure):
     _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("reserved0", ctypes.c_int32),
-                ("rows", ctypes.c_int64), ("cols", ctypes.c_int64), ("ld", ctypes.c_int64)]
+                ("rows", ctypes.c_int64), ("cols", ctypes.c_int64), ("ld", ctypes.c_int64),
+                ("col_scale", ctypes.c_void_p), ("master", ctypes.c_void_p), ("ld_master", ctypes.c_int64)]
+
+
+class LowPrecisionMatrix:
+    """A stored as BF16 (uint16 patterns in an int16 tensor) or column-scaled
+    FP8 E4M3 (uint8 tensor + float32 col_scale), optionally with the FP32
+    master copy used for the Rayleigh-Ritz projection and the residual."""
+
+    def __init__(self, data, fmt, col_scale=None, master=None):
+        self.data, self.fmt, self.col_scale, self.master = data, fmt, col_scale, master
+        self.shape = tuple(data.shape)
+        self.device = data.device
+        self.dtype = torch.float32            # dtype of the outputs
+
+    def matrix(self):
+        m = rsvd_matrix(self.data.data_ptr(), self.fmt, 0, self.shape[0], self.shape[1], self.data.stride(0))
+        if self.col_scale is not None:
+            m.col_scale = self.col_scale.data_ptr()
+        if self.master is not None:
+            m.master = self.master.data_ptr()
+            m.ld_master = self.master.stride(0)
+        return m
 
 
 class rsvd_params(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int64), ("p", ctypes.c_int64), ("q", ctypes.c_int64), ("seed", ctypes.c_uint64),
                 ("residual", ctypes.c_int32), ("return_full_l", ctypes.c_int32),
-                ("force_householder", ctypes.c_int32), ("residual_iters", ctypes.c_int32)]
+                ("force_householder", ctypes.c_int32), ("residual_iters", ctypes.c_int32),
+                ("extra_power_pass", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
 
 
 class rsvd_result(ctypes.Structure):
@@ -41,8 +64,8 @@ class rsvd_result(ctypes.Structure):
 
 
 EXPORTS = ["rsvd_create", "rsvd_destroy", "rsvd_l_used", "rsvd_workspace_size", "rsvd_solve",
-           "rsvd_status_string", "rsvd_profile_enable", "rsvd_profile_read", "rsvd_omega", "rsvd_philox_words",
-           "rsvd_gemm_workspace_size", "rsvd_gemm", "rsvd_orth_workspace_size", "rsvd_orth"]
+           "rsvd_status_string", "rsvd_profile_enable", "rsvd_profile_read", "rsvd_quantize", "rsvd_omega",
+           "rsvd_philox_words", "rsvd_gemm_workspace_size", "rsvd_gemm", "rsvd_orth_workspace_size", "rsvd_orth"]
 
 _lib = None
 
@@ -67,6 +90,7 @@ def load_library(path=LIB_PATH):
         "rsvd_status_string": ([I32], ctypes.c_char_p),
         "rsvd_profile_enable": ([P, I32], I32),
         "rsvd_profile_read": ([P, I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)], I32),
+        "rsvd_quantize": ([I32, P, I64, I64, I64, P, I64, P, P], I32),
         "rsvd_omega": ([I32, U64, ctypes.c_uint32, I64, I64, P, I64, P], I32),
         "rsvd_philox_words": ([U64, ctypes.c_uint32, P, I64, P, P], I32),
         "rsvd_gemm_workspace_size": ([ctypes.POINTER(rsvd_matrix), I32, I64, ctypes.POINTER(SZ)], I32),
@@ -112,11 +136,37 @@ def _stream_ptr(stream, device):
 
 
 def _as_matrix(A):
+    if isinstance(A, LowPrecisionMatrix):
+        return A.matrix()
     if A.dim() != 2 or not A.is_cuda or A.dtype not in _DTYPES:
         raise ValueError("A must be a 2-D float32/float64 CUDA tensor")
     if A.stride(1) != 1:
         raise ValueError("A must be row-major (stride(1) == 1)")
-    return rsvd_matrix(A.data_ptr(), _DTYPES[A.dtype], 0, A.shape[0], A.shape[1], max(A.stride(0), A.shape[1]))
+    return rsvd_matrix(A.data_ptr(), _DTYPES[A.dtype], 0, A.shape[0], A.shape[1], max(A.stride(0), A.shape[1]),
+                       None, None, 0)
+
+
+def quantize(A, fmt, keep_master=True, stream=None):
+    """BF16 (fmt = RSVD_BF16) or column-scaled FP8 (RSVD_FP8_E4M3) copy of a
+    row-major float32 CUDA tensor, made by the library's kernels; the rows
+    are padded to a 16-byte multiple.  keep_master: A itself becomes the
+    FP32 copy for the Rayleigh-Ritz projection."""
+    if A.dtype != torch.float32 or A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError("A must be a row-major float32 CUDA tensor")
+    m, n = A.shape
+    if fmt == RSVD_BF16:
+        data = torch.empty((m, (n + 7) // 8 * 8), dtype=torch.int16, device=A.device)[:, :n]
+        scale = None
+    elif fmt == RSVD_FP8_E4M3:
+        data = torch.empty((m, (n + 15) // 16 * 16), dtype=torch.uint8, device=A.device)[:, :n]
+        scale = torch.empty((n,), dtype=torch.float32, device=A.device)
+    else:
+        raise ValueError("fmt must be RSVD_BF16 or RSVD_FP8_E4M3")
+    _check(load_library().rsvd_quantize(fmt, ctypes.c_void_p(A.data_ptr()), m, n, A.stride(0),
+                                        ctypes.c_void_p(data.data_ptr()), data.stride(0),
+                                        ctypes.c_void_p(scale.data_ptr()) if scale is not None else None,
+                                        _stream_ptr(stream, A.device)))
+    return LowPrecisionMatrix(data, fmt, scale, A if keep_master else None)
 
 
 def _workspace(nbytes, device):
@@ -131,7 +181,7 @@ def l_used(m, n, k, p):
 def workspace_size(A, k, p=10, q=0, return_full_l=False):
     lib = load_library()
     M = _as_matrix(A)
-    prm = rsvd_params(k, p, q, 0, 0, int(return_full_l), 0, 0)
+    prm = rsvd_params(k, p, q, 0, 0, int(return_full_l), 0, 0, -1, 0)
     nb = ctypes.c_size_t()
     _check(lib.rsvd_workspace_size(_handle(A.device), ctypes.byref(M), ctypes.byref(prm), ctypes.byref(nb)))
     return nb.value
@@ -157,7 +207,7 @@ class Solver:
     estimate (0 = library default)."""
 
     def __init__(self, A, k, p=10, q=0, seed=0, residual=False, return_full_l=False, force_householder=False,
-                 return_q=False, stream=None, residual_iters=0):
+                 return_q=False, stream=None, residual_iters=0, extra_power_pass=-1):
         self.lib = load_library()
         self.A = A
         self.M = _as_matrix(A)
@@ -167,7 +217,7 @@ class Solver:
         dev = A.device
         residual = _residual_mode(residual)
         self.params = rsvd_params(k, p, q, seed, residual, int(return_full_l), int(force_householder),
-                                  int(residual_iters))
+                                  int(residual_iters), int(extra_power_pass), 0)
         self.U = torch.empty((m, r), dtype=A.dtype, device=dev)
         self.S = torch.empty((r,), dtype=torch.float64, device=dev)
         self.Vt = torch.empty((r, n), dtype=A.dtype, device=dev)
@@ -195,12 +245,13 @@ class Solver:
 
 
 def solve(A, k, p=10, q=0, seed=0, residual=False, return_full_l=False, force_householder=False, return_q=False,
-          stream=None, residual_iters=0):
+          stream=None, residual_iters=0, extra_power_pass=-1):
     """Randomized SVD (Algorithm 4) of a CUDA tensor A.  Returns a dict with
     U (m x r), S (r, float64), Vt (r x n), info (int), l, and optionally
     residual_t ([spectral estimate, Frobenius norm] of A - QQ^T A, float64
     tensor) and Q (m x l)."""
-    s = Solver(A, k, p, q, seed, residual, return_full_l, force_householder, return_q, stream, residual_iters)()
+    s = Solver(A, k, p, q, seed, residual, return_full_l, force_householder, return_q, stream, residual_iters,
+               extra_power_pass)()
     out = dict(U=s.U, S=s.S, Vt=s.Vt, l=s.l, info_tensor=s.info)
     if residual:
         out["residual_t"] = s.res
@@ -249,7 +300,7 @@ def gemm(A, X=None, trans=False, seed=0, ncols=None):
     M = _as_matrix(A)
     if X is not None:
         if X.dtype != A.dtype or X.stride(1) != 1:
-            raise ValueError("X must match A's dtype and be row-major")
+            raise ValueError("X must match A's dtype (float32 for a low-precision A) and be row-major")
         ncols = X.shape[1]
     rows = A.shape[1] if trans else A.shape[0]
     nb = ctypes.c_size_t()

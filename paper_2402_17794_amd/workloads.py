@@ -12,7 +12,8 @@ Families
                   standard recipe for the Haar measure).
   spectra         the singular-value profiles of the benchmark configurations:
                   geometric 0.8^i (512 x 256), max(0.95^i, 1e-6) (8192^2),
-                  1/i (2048^2 slow decay), i^-1.5 (mixed precision).
+                  1/i (2048^2 slow decay), i^-1.5 (mixed precision,
+                  32768 x 16384).
   eq41_spectrum   the test family of eq. (4.1) (Section 4.2): singular values
                   gap/j for j <= r and 1/j after, m x n = 3000 x 300, r = 15.
                   The paper builds it from sparse nonnegative vectors of
@@ -128,6 +129,9 @@ CONFIGS = {
                                 spectrum=("image",)),
     "c3b_fp32_slow_2048": dict(m=2048, n=2048, k=50, p=10, q=1, dtype="f32",
                                spectrum=("power", 1.0)),
+    # Mixed precision: FP32 master, solved as FP32, BF16 and column-scaled FP8.
+    "c4_mixed_32768x16384": dict(m=32768, n=16384, k=256, p=16, q=2, dtype="f32",
+                                 spectrum=("power", 1.5), lowp=True),
 }
 
 
