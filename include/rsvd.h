@@ -178,6 +178,36 @@ rsvd_status rsvd_profile_read(rsvd_handle* h, int32_t kind, double* total_ms, in
 rsvd_status rsvd_quantize(int32_t dtype, const float* A, int64_t rows, int64_t cols, int64_t lda, void* out,
                           int64_t ldo, float* col_scale, void* stream);
 
+/* ---- Batched request server: continuous batching on one GPU. ----
+ *
+ * A server owns a device arena of hbm_budget_bytes (allocated once, at
+ * create), n_streams ordinary streams and a scheduler thread.  Submitted
+ * requests are queued and admitted in arrival order as soon as a stream is
+ * free and the request's workspace (rsvd_workspace_size) fits in the arena
+ * (admission by HBM footprint); an admitted request is one rsvd_solve on its
+ * stream, so requests that arrive while others run overlap on the device.
+ * A request borrows the caller's A and result buffers until it is done; its
+ * result is the same as that of rsvd_solve alone.  Submit, poll, wait,
+ * drain and stats may be called from any thread.  A request whose workspace
+ * exceeds the whole arena is refused at submit (RSVD_ERR_NO_MEMORY).
+ * Latency = time from submit until the scheduler sees the request's
+ * completion event. */
+typedef struct rsvd_server rsvd_server;
+rsvd_status rsvd_server_create(rsvd_server** out, int device, size_t hbm_budget_bytes, int n_streams);
+rsvd_status rsvd_server_submit(rsvd_server* s, const rsvd_matrix* A, const rsvd_params* params,
+                               const rsvd_result* out, uint64_t* ticket);
+/* done = 1 once the request's kernels have completed; final_status: its status. */
+rsvd_status rsvd_server_poll(rsvd_server* s, uint64_t ticket, int* done, rsvd_status* final_status);
+/* Block until the request is done; latency_ms (nullable) receives its latency. */
+rsvd_status rsvd_server_wait(rsvd_server* s, uint64_t ticket, rsvd_status* final_status, double* latency_ms);
+/* Block until every submitted request is done. */
+rsvd_status rsvd_server_drain(rsvd_server* s);
+/* Over the completed requests: latency percentiles, completed / (last completion - first submit). */
+rsvd_status rsvd_server_stats(rsvd_server* s, double* p50_ms, double* p99_ms, double* solves_per_s,
+                              int64_t* completed);
+/* Drains, then releases the arena, streams and thread. */
+rsvd_status rsvd_server_destroy(rsvd_server* s);
+
 /* ---- Single steps of the path, for testing each kernel on its own. ---- */
 
 /* The test matrix of Algorithm 4 step 1, materialised (the solve never does

@@ -21,7 +21,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "librsvd.so")
 ARCH = os.environ.get("RSVD_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["gemm.hip", "gemm_lp.hip", "orth.hip", "svd.hip", "rsvd.cpp"]
+SOURCES = ["gemm.hip", "gemm_lp.hip", "orth.hip", "svd.hip", "rsvd.cpp", "server.cpp"]
 
 COMMON_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -85,7 +85,7 @@ def build(verbose=False):
         print("warning: kernels spill registers to scratch: " + ", ".join(f"{k} ({v} B/lane)" for k, v in spills.items()),
               file=sys.stderr)
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *[o for o, _ in results]]
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp, *[o for o, _ in results]]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -65,7 +65,9 @@ class rsvd_result(ctypes.Structure):
 
 EXPORTS = ["rsvd_create", "rsvd_destroy", "rsvd_l_used", "rsvd_workspace_size", "rsvd_solve",
            "rsvd_status_string", "rsvd_profile_enable", "rsvd_profile_read", "rsvd_quantize", "rsvd_omega",
-           "rsvd_philox_words", "rsvd_gemm_workspace_size", "rsvd_gemm", "rsvd_orth_workspace_size", "rsvd_orth"]
+           "rsvd_philox_words", "rsvd_gemm_workspace_size", "rsvd_gemm", "rsvd_orth_workspace_size", "rsvd_orth",
+           "rsvd_server_create", "rsvd_server_submit", "rsvd_server_poll", "rsvd_server_wait", "rsvd_server_drain",
+           "rsvd_server_stats", "rsvd_server_destroy"]
 
 _lib = None
 
@@ -91,6 +93,15 @@ def load_library(path=LIB_PATH):
         "rsvd_profile_enable": ([P, I32], I32),
         "rsvd_profile_read": ([P, I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)], I32),
         "rsvd_quantize": ([I32, P, I64, I64, I64, P, I64, P, P], I32),
+        "rsvd_server_create": ([ctypes.POINTER(P), ctypes.c_int, SZ, ctypes.c_int], I32),
+        "rsvd_server_submit": ([P, ctypes.POINTER(rsvd_matrix), ctypes.POINTER(rsvd_params),
+                                ctypes.POINTER(rsvd_result), ctypes.POINTER(U64)], I32),
+        "rsvd_server_poll": ([P, U64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(I32)], I32),
+        "rsvd_server_wait": ([P, U64, ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_double)], I32),
+        "rsvd_server_drain": ([P], I32),
+        "rsvd_server_stats": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)], I32),
+        "rsvd_server_destroy": ([P], I32),
         "rsvd_omega": ([I32, U64, ctypes.c_uint32, I64, I64, P, I64, P], I32),
         "rsvd_philox_words": ([U64, ctypes.c_uint32, P, I64, P, P], I32),
         "rsvd_gemm_workspace_size": ([ctypes.POINTER(rsvd_matrix), I32, I64, ctypes.POINTER(SZ)], I32),
@@ -258,6 +269,77 @@ def solve(A, k, p=10, q=0, seed=0, residual=False, return_full_l=False, force_ho
     if return_q:
         out["Q"] = s.Q
     return out
+
+
+class Request:
+    """A submitted server request: owns its output tensors (and keeps A
+    alive) until it is done."""
+
+    def __init__(self, server, A, k, p, q, seed, return_full_l, extra_power_pass):
+        m, n = A.shape
+        self.A, self.l = A, l_used(m, n, k, p)
+        r = self.l if return_full_l else k
+        dev = A.device
+        self.U = torch.empty((m, r), dtype=A.dtype, device=dev)
+        self.S = torch.empty((r,), dtype=torch.float64, device=dev)
+        self.Vt = torch.empty((r, n), dtype=A.dtype, device=dev)
+        self.info = torch.zeros((1,), dtype=torch.int32, device=dev)
+        self._M = _as_matrix(A)
+        self._params = rsvd_params(k, p, q, seed, 0, int(return_full_l), 0, 0, int(extra_power_pass), 0)
+        self._result = rsvd_result(self.U.data_ptr(), r, self.S.data_ptr(), self.Vt.data_ptr(), n, None,
+                                   self.info.data_ptr(), None, self.l)
+        t = ctypes.c_uint64()
+        _check(server.lib.rsvd_server_submit(server.ptr, ctypes.byref(self._M), ctypes.byref(self._params),
+                                             ctypes.byref(self._result), ctypes.byref(t)))
+        self.ticket = t.value
+        self.server = server
+
+    def done(self):
+        d, st = ctypes.c_int(), ctypes.c_int32()
+        _check(self.server.lib.rsvd_server_poll(self.server.ptr, self.ticket, ctypes.byref(d), ctypes.byref(st)))
+        return bool(d.value)
+
+    def wait(self):
+        """Block until done; returns the latency in ms (submit to completion)."""
+        st, lat = ctypes.c_int32(), ctypes.c_double()
+        _check(self.server.lib.rsvd_server_wait(self.server.ptr, self.ticket, ctypes.byref(st), ctypes.byref(lat)))
+        _check(st.value)
+        return lat.value
+
+
+class Server:
+    """Continuous-batching request server (rsvd_server_*): requests are
+    admitted by HBM footprint into `n_streams` concurrent slots."""
+
+    def __init__(self, device="cuda:0", hbm_budget_bytes=16 << 30, n_streams=4):
+        self.lib = load_library()
+        dev = torch.device(device)
+        idx = dev.index if dev.index is not None else torch.cuda.current_device()
+        self.ptr = ctypes.c_void_p()
+        _check(self.lib.rsvd_server_create(ctypes.byref(self.ptr), idx, int(hbm_budget_bytes), int(n_streams)))
+
+    def submit(self, A, k, p=10, q=0, seed=0, return_full_l=False, extra_power_pass=-1):
+        return Request(self, A, k, p, q, seed, return_full_l, extra_power_pass)
+
+    def drain(self):
+        _check(self.lib.rsvd_server_drain(self.ptr))
+
+    def stats(self):
+        p50, p99, sps, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        _check(self.lib.rsvd_server_stats(self.ptr, ctypes.byref(p50), ctypes.byref(p99), ctypes.byref(sps),
+                                          ctypes.byref(n)))
+        return {"p50_ms": p50.value, "p99_ms": p99.value, "solves_per_s": sps.value, "completed": n.value}
+
+    def close(self):
+        if self.ptr:
+            _check(self.lib.rsvd_server_destroy(self.ptr))
+            self.ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 PROFILE_SKETCH, PROFILE_NN, PROFILE_TN, PROFILE_ALL = 0, 1, 2, 3

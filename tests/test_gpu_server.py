@@ -1,0 +1,70 @@
+"""The batched request server (continuous batching), through the C ABI.
+
+* Each result is bitwise the same alone (rsvd_solve on the default stream)
+  and in the mix (admitted by the server next to other requests on other
+  streams): every request runs the same deterministic kernels on its own
+  workspace.
+* Admission by HBM footprint: with an arena that holds only about one
+  request's workspace, requests still all complete (they queue); a request
+  larger than the whole arena is refused at submit.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2402_17794_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2402_17794_amd import rsvd
+    rsvd.load_library()
+    return rsvd
+
+
+def _requests(seed, count):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(count):
+        m, n = (int(x) for x in np.exp(rng.uniform(np.log(150), np.log(1600), 2)))
+        k = int(rng.integers(3, min(60, m, n)))
+        q = int(rng.integers(0, 3))
+        dtype = torch.float32 if i % 3 else torch.float64
+        sig = W.spectrum_geometric(min(m, n), float(rng.uniform(0.9, 0.99))) if i % 2 else \
+            W.spectrum_power(min(m, n), float(rng.uniform(1.0, 2.0)))
+        A = torch.from_numpy(W.known_spectrum(m, n, sig, 100 + i, 200 + i)).to(dtype).cuda()
+        reqs.append((A, k, 10, q, i))
+    return reqs
+
+
+@pytest.mark.parametrize("n_streams,budget", [(4, 2 << 30), (3, None)])
+def test_alone_equals_mix(R, n_streams, budget):
+    reqs = _requests(5, 24)
+    alone = []
+    for A, k, p, q, seed in reqs:
+        out = R.solve(A, k, p, q, seed=seed)
+        torch.cuda.synchronize()
+        alone.append((out["U"].cpu(), out["S"].cpu(), out["Vt"].cpu(), out["info_tensor"].item()))
+    if budget is None:                        # room for about one request at a time
+        budget = max(R.workspace_size(A, k, p, q) for A, k, p, q, _ in reqs) + (1 << 20)
+    srv = R.Server("cuda:0", hbm_budget_bytes=budget, n_streams=n_streams)
+    tickets = [srv.submit(A, k, p, q, seed=seed) for A, k, p, q, seed in reqs]
+    lat = [t.wait() for t in tickets]
+    torch.cuda.synchronize()
+    for t, (U, S, Vt, info) in zip(tickets, alone):
+        assert torch.equal(t.U.cpu(), U) and torch.equal(t.S.cpu(), S) and torch.equal(t.Vt.cpu(), Vt)
+        assert t.info.item() == info
+    st = srv.stats()
+    assert st["completed"] == len(reqs) and 0 < st["p50_ms"] <= st["p99_ms"] <= max(lat) + 1e-6
+    srv.close()
+
+
+def test_request_larger_than_arena_is_refused(R):
+    A = torch.randn(2000, 1500, device="cuda")
+    srv = R.Server("cuda:0", hbm_budget_bytes=1 << 20, n_streams=2)
+    with pytest.raises(R.RsvdError):
+        srv.submit(A, 50, 10, 1)
+    srv.close()
