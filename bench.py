@@ -150,6 +150,96 @@ def bench_lowp(args, cfg, A, torch, rsvd, workloads):
     return out
 
 
+def bench_serving(args, cfg, torch, rsvd, workloads):
+    """The serving workload through the request server: a Poisson replay of
+    the trace (latency percentiles at the offered load), then a saturation
+    replay (every request submitted at once: peak solves/s, the headline),
+    the alone-vs-mix identity of every result, and the FP64 oracle on a
+    sample of requests."""
+    dev = torch.device("cuda:0")
+    torch.backends.cuda.matmul.allow_tf32 = False
+    trace = workloads.serving_trace(cfg["count"], cfg["rate"])
+    print(f"bench: building {len(trace)} request matrices ...", file=sys.stderr, flush=True)
+    tg = time.perf_counter()
+    pool = workloads.HaarPool(dev, sorted({r["m"] for r in trace} | {r["n"] for r in trace}))
+    mats = [pool.matrix(r) for r in trace]
+    del pool
+    torch.cuda.synchronize()
+    print(f"bench: inputs ready in {time.perf_counter() - tg:.1f} s", file=sys.stderr, flush=True)
+    budget = int(cfg["budget_gb"] * (1 << 30))
+    for A, r in list(zip(mats, trace))[: args.warmup]:
+        rsvd.solve(A, r["k"], r["p"], r["q"], seed=r["seed"])
+    torch.cuda.synchronize()
+
+    def replay(poisson):
+        srv = rsvd.Server(dev, hbm_budget_bytes=budget, n_streams=cfg["streams"])
+        t0 = time.perf_counter()
+        reqs = []
+        for A, r in zip(mats, trace):
+            if poisson:
+                delay = t0 + r["arrival"] - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+            reqs.append(srv.submit(A, r["k"], r["p"], r["q"], seed=r["seed"]))
+        srv.drain()
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        return reqs, st, wall
+
+    reqs_p, st_p, wall_p = replay(True)
+    print(f"bench: Poisson replay: {st_p}", file=sys.stderr, flush=True)
+    reqs_s, st_s, wall_s = replay(False)
+    print(f"bench: saturation replay: {st_s}", file=sys.stderr, flush=True)
+    # Alone-vs-mix: every result of the saturation replay against a solve alone.
+    same = 0
+    for A, r, rq in zip(mats, trace, reqs_s):
+        out = rsvd.solve(A, r["k"], r["p"], r["q"], seed=r["seed"])
+        same += int(torch.equal(out["S"], rq.S) and torch.equal(out["U"], rq.U) and torch.equal(out["Vt"], rq.Vt))
+    torch.cuda.synchronize()
+    flops = sum((2 * r["q"] + 2) * 2.0 * r["m"] * r["n"] * rsvd.l_used(r["m"], r["n"], r["k"], r["p"]) for r in trace)
+    out = {
+        "metric": METRIC, "value": st_s["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": len(trace),
+        "warmup": args.warmup, "ms_per_step": 1e3 / st_s["solves_per_s"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"c5_serving: {len(trace)} FP32 requests, m,n log-uniform in [256, 8192] "
+                               "(half-octave grid), k in {10..128}, p=10, q in {0,1,2}, alternating geometric / "
+                               "polynomial spectra; request server with "
+                               f"{cfg['streams']} streams and a {cfg['budget_gb']} GiB workspace budget",
+                   "requests": len(trace), "offered_rate_per_s": cfg["rate"]},
+        "p50_ms": st_p["p50_ms"], "p99_ms": st_p["p99_ms"],
+        "poisson_replay": {"achieved_solves_per_s": len(trace) / wall_p, **st_p},
+        "saturation_replay": {"wall_s": wall_s, **st_s},
+        "tflops_algorithmic_saturation": flops / wall_s / 1e12,
+        "alone_equals_mix": f"{same}/{len(trace)}",
+        "roofline": None,
+    }
+    if not args.no_cpu_baseline:
+        from oracle.rsvd import rsvd_alg4
+        sample = [i for i, r in enumerate(trace) if r["m"] * r["n"] <= 1448 * 1448][:40]
+        tc = time.perf_counter()
+        errs = []
+        for i in sample:
+            r = trace[i]
+            Ah = mats[i].double().cpu().numpy()
+            ref = rsvd_alg4(Ah, r["k"], r["p"], r["q"], seed=r["seed"])
+            errs.append(float(np.max(np.abs(reqs_s[i].S.cpu().numpy() - ref["S"])) / ref["S"][0]))
+            if time.perf_counter() - tc > 25.0:
+                sample = sample[: len(errs)]
+                break
+        tcpu = time.perf_counter() - tc
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+        except Exception:
+            threads = len(os.sched_getaffinity(0))
+        out["cpu_baseline"] = {"value": len(errs) / tcpu, "unit": "solves/s", "cores": int(threads),
+                               "kind": "oracle", "sample": f"{len(errs)} requests of the trace with m*n <= 1448^2, "
+                                                           f"FP64, {tcpu:.1f} s"}
+        out["rel_err_vs_fp64_sample"] = {"sigma_normwise_max": max(errs), "requests": len(errs)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,6 +261,9 @@ def main():
     from paper_2402_17794_amd import prof_summary, rsvd, workloads
 
     cfg = workloads.CONFIGS[args.config]
+    if cfg.get("serving"):
+        print(json.dumps(bench_serving(args, cfg, torch, rsvd, workloads)), flush=True)
+        return
     m, n, k, p, q = cfg["m"], cfg["n"], cfg["k"], cfg["p"], cfg["q"]
     dtype = torch.float32 if cfg["dtype"] == "f32" else torch.float64
     dev = torch.device("cuda:0")

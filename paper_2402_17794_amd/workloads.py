@@ -129,6 +129,8 @@ CONFIGS = {
                                 spectrum=("image",)),
     "c3b_fp32_slow_2048": dict(m=2048, n=2048, k=50, p=10, q=1, dtype="f32",
                                spectrum=("power", 1.0)),
+    # Serving: 2000 FP32 requests, Poisson arrivals at 200 req/s (serving_trace below).
+    "c5_serving": dict(serving=True, count=2000, rate=200.0, dtype="f32", budget_gb=16, streams=8),
     # Mixed precision: FP32 master, solved as FP32, BF16 and column-scaled FP8.
     "c4_mixed_32768x16384": dict(m=32768, n=16384, k=256, p=16, q=2, dtype="f32",
                                  spectrum=("power", 1.5), lowp=True),
@@ -157,3 +159,54 @@ def config_matrix(name, device=None):
         import torch
         return torch.from_numpy(A).to(device)
     return known_spectrum(c["m"], c["n"], config_sigma(name), 1, 2, device)
+
+
+# ---------------------------------------------------------------- serving --
+# The request stream of the serving workload: Poisson arrivals, m and n
+# log-uniform in [256, 8192] (rounded to the half-octave grid below), k
+# uniform in {10..128} (at most min(m, n)), p = 10, q uniform in {0, 1, 2};
+# spectra alternate geometric (ratio U[0.9, 0.99]) and polynomial (i^-alpha,
+# alpha U[1, 2]), sigma_1 = 1.  Matrices are A = U_m[:, :d] diag(sigma) V_n[:, :d]^T
+# with one pair of Haar factors per grid size (a pool shared by the requests
+# of that size; each request has its own spectrum), formed on the device.
+SERVING_GRID = [int(round(256 * 2.0 ** (h / 2))) for h in range(11)]        # 256 ... 8192
+
+
+def serving_trace(count=2000, rate=200.0, seed=5):
+    rng = _rng(seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, count))
+    lg = np.log(np.array(SERVING_GRID, dtype=np.float64))
+    snap = lambda x: SERVING_GRID[int(np.argmin(np.abs(lg - x)))]
+    out = []
+    for r in range(count):
+        m = snap(rng.uniform(lg[0], lg[-1]))
+        n = snap(rng.uniform(lg[0], lg[-1]))
+        k = min(int(rng.integers(10, 129)), min(m, n))
+        q = int(rng.integers(0, 3))
+        spec = ("geometric", float(rng.uniform(0.9, 0.99))) if r % 2 == 0 else ("power", float(rng.uniform(1.0, 2.0)))
+        out.append(dict(arrival=float(arrivals[r]), m=m, n=n, k=k, p=10, q=q, spectrum=spec, seed=r))
+    return out
+
+
+def request_sigma(req):
+    d = min(req["m"], req["n"])
+    kind, x = req["spectrum"]
+    return spectrum_geometric(d, x) / x if kind == "geometric" else spectrum_power(d, x)
+
+
+class HaarPool:
+    """One pair of Haar factors per grid size on a torch device (FP64 QR,
+    stored in FP32), for the serving workload's matrices."""
+
+    def __init__(self, device, sizes):
+        self.U, self.V = {}, {}
+        for s in sizes:
+            self.U[s] = haar(s, s, 16000 + s, device).float()
+            self.V[s] = haar(s, s, 17000 + s, device).float()
+
+    def matrix(self, req):
+        import torch
+        m, n = req["m"], req["n"]
+        d = min(m, n)
+        sig = torch.from_numpy(request_sigma(req)).float().to(self.U[m].device)
+        return ((self.U[m][:, :d] * sig[None, :]) @ self.V[n][:, :d].T).contiguous()
