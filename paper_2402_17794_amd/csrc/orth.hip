@@ -18,6 +18,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -28,11 +29,12 @@ namespace rsvd {
 // ---------------------------------------------------------------- Gram --
 // Partial Gram matrices Y_c^T Y_c (FP64, on FP64 MFMA 16x16x4) for nchunks
 // row chunks Y_c of Y.  Output tiles of 16 x 16 on and above the diagonal.
-// A workgroup of 4 wavefronts computes one tile over one chunk: wavefront w
-// takes the 4-row steps w, w + 4, ... with two accumulators, and the eight
-// accumulators are summed in a fixed order.  The chunk partials are summed
-// (in chunk order) by the Cholesky kernel that consumes them, so no
-// workgroup ever waits for another.
+// A workgroup of 16 wavefronts computes one tile over one chunk: wavefront w
+// takes the 4-row steps w, w + 16, ... with two accumulators (so each
+// wavefront has only a few batches of loads in flight one after another),
+// and the 32 accumulators are summed in a fixed order.  The chunk partials
+// are summed (in chunk order) by the Cholesky kernel that consumes them, so
+// no workgroup ever waits for another.
 int gram_pairs(int L) {
     const int nt = (int)ceil_div(L, 16);
     return nt * (nt + 1) / 2;
@@ -40,9 +42,12 @@ int gram_pairs(int L) {
 int gram_chunks(int64_t rows) { return (int)std::min<int64_t>(8, std::max<int64_t>(1, ceil_div(rows, 1024))); }
 size_t gram_partials_elems(int64_t rows, int L) { return (size_t)gram_chunks(rows) * gram_pairs(L) * 256; }
 
+constexpr int kGramWaves = 16;
+
 template <typename T>
-__global__ __launch_bounds__(256) void gram_kernel(const T* __restrict__ Y, int64_t ldy, int64_t rows, int L,
-                                                   int nchunks, double* __restrict__ part, const DevFlags* skip) {
+__global__ __launch_bounds__(64 * kGramWaves) void gram_kernel(const T* __restrict__ Y, int64_t ldy, int64_t rows,
+                                                               int L, int nchunks, double* __restrict__ part,
+                                                               const DevFlags* skip) {
     if (skip && skip->orth_fail) return;
     const int nt = L / 16;
     const int npairs = nt * (nt + 1) / 2;
@@ -60,11 +65,12 @@ __global__ __launch_bounds__(256) void gram_kernel(const T* __restrict__ Y, int6
     const T* __restrict__ yb = Y + b * 16 + li;
     doublex4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
     constexpr int UNR = 8;          // 8 MFMA steps (32 rows per wavefront) per batch of loads
-    for (int64_t k0 = r0 + 4 * wave; k0 < r1; k0 += 16 * UNR) {
+    constexpr int STEP = 4 * kGramWaves;
+    for (int64_t k0 = r0 + 4 * wave; k0 < r1; k0 += STEP * UNR) {
         double va[UNR], vb[UNR];
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
-            const int64_t row = k0 + 16 * u + lk;
+            const int64_t row = k0 + STEP * u + lk;
             const bool ok = row < r1;
             va[u] = ok ? (double)ya[row * ldy] : 0.0;
             vb[u] = ok ? (double)yb[row * ldy] : 0.0;
@@ -76,11 +82,16 @@ __global__ __launch_bounds__(256) void gram_kernel(const T* __restrict__ Y, int6
         }
     }
     // acc[v] = G[a*16 + acc_row(lk, v)][b*16 + li] restricted to this chunk.
-    __shared__ double red[4][256];
+    __shared__ double red[kGramWaves][256];
 #pragma unroll
     for (int v = 0; v < 4; ++v) red[wave][acc_row<double>(lk, v) * 16 + li] = acc0[v] + acc1[v];
     __syncthreads();
-    part[((size_t)chunk * npairs + pair) * 256 + tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+    if (tid < 256) {
+        double sum = 0.0;
+#pragma unroll
+        for (int w = 0; w < kGramWaves; ++w) sum += red[w][tid];
+        part[((size_t)chunk * npairs + pair) * 256 + tid] = sum;
+    }
 }
 
 hipError_t launch_gram(int dtype, const void* Y, int64_t ldy, int64_t rows, int L, double* partials,
@@ -88,11 +99,11 @@ hipError_t launch_gram(int dtype, const void* Y, int64_t ldy, int64_t rows, int 
     const int nchunks = gram_chunks(rows);
     dim3 grid(nchunks * gram_pairs(L));
     if (dtype == 0)
-        hipLaunchKernelGGL(gram_kernel<double>, grid, dim3(256), 0, s, (const double*)Y, ldy, rows, L, nchunks,
-                           partials, skip);
+        hipLaunchKernelGGL(gram_kernel<double>, grid, dim3(64 * kGramWaves), 0, s, (const double*)Y, ldy, rows, L,
+                           nchunks, partials, skip);
     else
-        hipLaunchKernelGGL(gram_kernel<float>, grid, dim3(256), 0, s, (const float*)Y, ldy, rows, L, nchunks,
-                           partials, skip);
+        hipLaunchKernelGGL(gram_kernel<float>, grid, dim3(64 * kGramWaves), 0, s, (const float*)Y, ldy, rows, L,
+                           nchunks, partials, skip);
     return hipGetLastError();
 }
 
@@ -616,6 +627,145 @@ __global__ __launch_bounds__(256) void apply_kernel(const T* __restrict__ in, in
     }
 }
 
+// Variant for L <= 128 and at most 112 output columns (LDS: 32 x 129 + 128 x
+// 113 doubles): the workgroup's 32
+// rows of `in` and all of M are loaded into LDS at once (every load in
+// flight together), then the products run as above.  The argmax partials
+// reuse the LDS of the input rows.
+constexpr int kApplyLdsMax = 128;
+
+template <typename T, int CT>
+__global__ __launch_bounds__(256) void apply_lds_kernel(const T* __restrict__ in, int64_t ldi, int64_t rows, int L,
+                                                        const double* __restrict__ M, int ldm, int ncols_out,
+                                                        T* __restrict__ out, int64_t ldo, int transpose_out,
+                                                        const double* __restrict__ colscale, const DevFlags* skip,
+                                                        double* __restrict__ amax_val, int* __restrict__ amax_idx,
+                                                        int upper) {
+    if (skip && skip->orth_fail) return;
+    constexpr int W = CT * 16;
+    constexpr int NTW = (CT + 1) / 2;
+    constexpr int SI = kApplyLdsMax + 1;               // row stride of the input rows (odd)
+    constexpr int SM = W + 1;
+    static_assert(kApplyRows * SI >= kApplyRows * SM, "argmax partials reuse the input rows' LDS");
+    __shared__ double inS[kApplyRows * SI];
+    __shared__ double MS[kApplyLdsMax * SM];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int rb = 16 * (wave & 1), tw = wave >> 1;
+    const int64_t row0 = (int64_t)blockIdx.x * kApplyRows;
+    // Input rows (16-byte vectors of `in`) and M (pairs of doubles), every
+    // load of the thread issued before the first store.  L and W are
+    // multiples of 16, the leading dimensions multiples of 16 elements and
+    // the buffers 16-byte aligned (internal panels and workspace).
+    {
+        constexpr int VI = 16 / (int)sizeof(T);                       // elements per vector of `in`
+        constexpr int NI = (kApplyRows * kApplyLdsMax / VI + 255) / 256;
+        constexpr int NV = (kApplyLdsMax * W / 2 + 255) / 256;
+        using VT = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+        VT vi[NI];
+        double2 vm[NV];
+        const int ni = kApplyRows * L / VI, nm = L * W / 2;
+#pragma unroll
+        for (int u = 0; u < NI; ++u) {
+            const int idx = min(tid + 256 * u, ni - 1), rr = idx / (L / VI), aa = (idx - rr * (L / VI)) * VI;
+            const int64_t row = min(row0 + rr, rows - 1);              // rows past the end are never stored
+            vi[u] = *reinterpret_cast<const VT*>(in + row * ldi + aa);
+        }
+#pragma unroll
+        for (int u = 0; u < NV; ++u) {
+            const int idx = min(tid + 256 * u, nm - 1), aa = idx / (W / 2), cc = (idx - aa * (W / 2)) * 2;
+            vm[u] = *reinterpret_cast<const double2*>(M + (int64_t)aa * ldm + min(cc, ldm - 2));
+        }
+#pragma unroll
+        for (int u = 0; u < NI; ++u) {
+            const int idx = tid + 256 * u, rr = idx / (L / VI), aa = (idx - rr * (L / VI)) * VI;
+            if (idx < ni) {
+#pragma unroll
+                for (int e = 0; e < VI; ++e) {
+                    double x;
+                    if constexpr (sizeof(T) == 4) x = e == 0 ? vi[u].x : e == 1 ? vi[u].y : e == 2 ? vi[u].z : vi[u].w;
+                    else x = e == 0 ? vi[u].x : vi[u].y;
+                    inS[rr * SI + aa + e] = row0 + rr < rows ? x : 0.0;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < NV; ++u) {
+            const int idx = tid + 256 * u, aa = idx / (W / 2), cc = (idx - aa * (W / 2)) * 2;
+            if (idx < nm) {
+                MS[aa * SM + cc] = cc < ncols_out ? vm[u].x : 0.0;
+                MS[aa * SM + cc + 1] = cc + 1 < ncols_out ? vm[u].y : 0.0;
+            }
+        }
+    }
+    __syncthreads();
+    doublex4 acc[NTW];
+#pragma unroll
+    for (int j = 0; j < NTW; ++j) acc[j] = doublex4{0, 0, 0, 0};
+    for (int a0 = 0; a0 < L; a0 += 16) {
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+            const double av_ = inS[(rb + li) * SI + a0 + kk + lk];
+#pragma unroll
+            for (int j = 0; j < NTW; ++j) {
+                const int t = tw + 2 * j;
+                if (t >= CT) continue;
+                if (upper && a0 >= 16 * (t + 1)) continue;
+                acc[j] = mfma16x16x4(av_, MS[(a0 + kk + lk) * SM + 16 * t + li], acc[j]);
+            }
+        }
+    }
+    if (amax_val) __syncthreads();                     // the input rows' LDS becomes the argmax scratch
+    auto avs = [&](int rr, int col) -> double& { return inS[rr * SM + col]; };
+#pragma unroll
+    for (int j = 0; j < NTW; ++j) {
+        const int t = tw + 2 * j;
+        if (t >= CT) continue;
+        const int col = 16 * t + li;
+        if (col >= ncols_out) continue;
+        const double sc = colscale ? colscale[col] : 1.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int rr = rb + acc_row<double>(lk, v);
+            const int64_t row = row0 + rr;
+            const T val = (T)(acc[j][v] * sc);
+            if (row < rows) {
+                if (!transpose_out) out[row * ldo + col] = val;
+                else out[(int64_t)col * ldo + row] = val;
+            }
+            if (amax_val) avs(rr, col) = (row < rows) ? (double)val : 0.0;
+        }
+    }
+    if (!amax_val) return;
+    __syncthreads();
+    for (int col = tid; col < ncols_out; col += 256) {
+        double best = -1.0, val = 0.0;
+        int bi = 0;
+        for (int rr = 0; rr < kApplyRows; ++rr)      // lowest row wins ties
+            if (fabs(avs(rr, col)) > best) { best = fabs(avs(rr, col)); val = avs(rr, col); bi = rr; }
+        amax_val[(int64_t)blockIdx.x * ncols_out + col] = val;
+        amax_idx[(int64_t)blockIdx.x * ncols_out + col] = (int)(row0 + bi);
+    }
+}
+
+template <typename T>
+static hipError_t apply_lds_dispatch(int CT, dim3 grid, hipStream_t s, const T* in, int64_t ldi, int64_t rows, int L,
+                                     const double* M, int ldm, int ncols_out, T* out, int64_t ldo, int tr,
+                                     const double* colscale, const DevFlags* skip, double* av, int* ai, int upper) {
+#define RSVD_CT_CASE(N)                                                                                          \
+    case N:                                                                                                      \
+        hipLaunchKernelGGL((apply_lds_kernel<T, N>), grid, dim3(256), 0, s, in, ldi, rows, L, M, ldm, ncols_out,  \
+                           out, ldo, tr, colscale, skip, av, ai, upper);                                         \
+        break;
+    switch (CT) {
+        RSVD_CT_CASE(1) RSVD_CT_CASE(2) RSVD_CT_CASE(3) RSVD_CT_CASE(4) RSVD_CT_CASE(5) RSVD_CT_CASE(6)
+        RSVD_CT_CASE(7)
+        default: return hipErrorInvalidValue;
+    }
+#undef RSVD_CT_CASE
+    return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t apply_dispatch(int CT, dim3 grid, hipStream_t s, const T* in, int64_t ldi, int64_t rows, int L,
                                  const double* M, int ldm, int ncols_out, T* out, int64_t ldo, int tr,
@@ -642,6 +792,13 @@ hipError_t launch_apply(int dtype, const void* in, int64_t ldi, int64_t rows, in
     if (rows == 0 || ncols_out == 0) return hipSuccess;
     const int CT = (int)ceil_div(ncols_out, 16);
     dim3 grid(apply_blocks(rows));
+    if (L <= kApplyLdsMax && CT <= 7) {
+        if (dtype == 0)
+            return apply_lds_dispatch<double>(CT, grid, s, (const double*)in, ldi, rows, L, M, ldm, ncols_out,
+                                              (double*)out, ldo, transpose_out, colscale, skip, av, ai, upper);
+        return apply_lds_dispatch<float>(CT, grid, s, (const float*)in, ldi, rows, L, M, ldm, ncols_out, (float*)out,
+                                         ldo, transpose_out, colscale, skip, av, ai, upper);
+    }
     if (dtype == 0)
         return apply_dispatch<double>(CT, grid, s, (const double*)in, ldi, rows, L, M, ldm, ncols_out, (double*)out,
                                       ldo, transpose_out, colscale, skip, av, ai, upper);

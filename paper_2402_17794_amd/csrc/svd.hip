@@ -38,6 +38,19 @@ __device__ __forceinline__ double octet_sum(double x) {
     return x;
 }
 
+// Sum over the 4 lanes of each quad (xor 1, then xor 2), result in all 4.
+__device__ __forceinline__ double quad_sum(double x) {
+    x += dpp_f64<dpp_quad_xor1>(x);
+    x += dpp_f64<dpp_quad_xor2>(x);
+    return x;
+}
+
+template <int LPP>
+__device__ __forceinline__ double group_sum(double x) {
+    static_assert(LPP == 4 || LPP == 8, "lanes per pair");
+    return LPP == 4 ? quad_sum(x) : octet_sum(x);
+}
+
 // Round-robin (circle method) schedule: with n2 (even) columns, round r pairs
 // slot 0 with (n2 - 1, r) and slot s > 0 with ((r + s), (r - s)) mod (n2 - 1).
 __device__ __forceinline__ void rr_pair(int r, int s, int n2, int& p1, int& p2) {
@@ -47,11 +60,13 @@ __device__ __forceinline__ void rr_pair(int r, int s, int n2, int& p1, int& p2) 
     p2 = r - s + m; if (p2 >= m) p2 -= m;
 }
 
-// One-sided Jacobi on X = R^T; 8 lanes per column pair.  Columns are stored
-// with a padded stride (zero rows past l stay zero under rotations), so
-// every lane loads and stores its rows 2e, 2e+1, 2e+16, 2e+17, ... as 16-byte
-// pairs without bounds checks.  NP = row pairs per lane.
-template <int NP, bool IN_LDS, int NT>
+// One-sided Jacobi on X = R^T; LPP lanes per column pair.  Columns are
+// stored with a padded stride (zero rows past l stay zero under rotations),
+// so every lane loads and stores its rows 2e, 2e+1, 2e+2 LPP, 2e+2 LPP+1, ...
+// as 16-byte pairs without bounds checks.  NP = row pairs per lane.  Both
+// forms use 8 lanes per pair: with 4 (one wavefront per SIMD) a round was
+// slower, the latencies no longer hidden.
+template <int NP, bool IN_LDS, int NT, int LPP>
 __global__ __launch_bounds__(NT) void jacobi_kernel(const double* __restrict__ R, int l, int L,
                                                       const double* __restrict__ shift_p, double* __restrict__ sigma,
                                                       double* __restrict__ Ut, double* __restrict__ Mv,
@@ -62,7 +77,8 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const double* __restrict__ R
     __shared__ int rank_of[kMaxL];
     const int ld = IN_LDS ? kJacobiLdsMax : kMaxL;  // column stride (>= 16 * NP rows)
     double* X = IN_LDS ? lds : work;                // X[c * ld + r] = R[c][r], zero for r >= l
-    const int tid = threadIdx.x, grp = tid >> 3, e = tid & 7;
+    const int tid = threadIdx.x, grp = tid / LPP, e = tid % LPP;
+    static_assert(2 * NP * LPP <= (IN_LDS ? kJacobiLdsMax : kMaxL), "rows per column");
 
     for (int idx = tid; idx < l * ld; idx += NT) {
         const int c = idx / ld, r = idx - c * ld;
@@ -75,7 +91,7 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const double* __restrict__ R
         if (tid == 0) rotated = 0;
         __syncthreads();
         for (int r = 0; r < n2 - 1; ++r) {
-            for (int s = grp; s < n2 / 2; s += NT / 8) {
+            for (int s = grp; s < n2 / 2; s += NT / LPP) {
                 int p1, p2;
                 rr_pair(r, s, n2, p1, p2);
                 if (p1 >= l || p2 >= l) continue;
@@ -86,8 +102,8 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const double* __restrict__ R
                 double a = 0.0, b = 0.0, g = 0.0;
 #pragma unroll
                 for (int t = 0; t < NP; ++t) {
-                    xi[t] = xi_p[8 * t];
-                    xj[t] = xj_p[8 * t];
+                    xi[t] = xi_p[LPP * t];
+                    xj[t] = xj_p[LPP * t];
                 }
 #pragma unroll
                 for (int t = 0; t < NP; ++t) {
@@ -95,9 +111,9 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const double* __restrict__ R
                     b = fma(xj[t].x, xj[t].x, b); b = fma(xj[t].y, xj[t].y, b);
                     g = fma(xi[t].x, xj[t].x, g); g = fma(xi[t].y, xj[t].y, g);
                 }
-                a = octet_sum(a);
-                b = octet_sum(b);
-                g = octet_sum(g);
+                a = group_sum<LPP>(a);
+                b = group_sum<LPP>(b);
+                g = group_sum<LPP>(g);
                 if (fabs(g) > kJacobiTol * sqrt(a * b)) {
                     const double zeta = (b - a) / (2.0 * g);
                     const double az = fabs(zeta);
@@ -111,8 +127,8 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const double* __restrict__ R
                         ni.y = c * xi[u].y - sn * xj[u].y;
                         nj.x = sn * xi[u].x + c * xj[u].x;
                         nj.y = sn * xi[u].y + c * xj[u].y;
-                        xi_p[8 * u] = ni;
-                        xj_p[8 * u] = nj;
+                        xi_p[LPP * u] = ni;
+                        xj_p[LPP * u] = nj;
                     }
                     if (e == 0) rotated = 1;
                 }
@@ -125,10 +141,10 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const double* __restrict__ R
     }
     if (!converged && tid == 0) atomicOr(&flags->info, RSVD_INFO_JACOBI_NOT_CONVERGED);
 
-    for (int c = grp; c < l; c += NT / 8) {
+    for (int c = grp; c < l; c += NT / LPP) {
         double s2 = 0.0;
-        for (int row = e; row < l; row += 8) s2 = fma(X[c * ld + row], X[c * ld + row], s2);
-        s2 = octet_sum(s2);
+        for (int row = e; row < l; row += LPP) s2 = fma(X[c * ld + row], X[c * ld + row], s2);
+        s2 = group_sum<LPP>(s2);
         if (e == 0) nrm2[c] = s2;
     }
     __syncthreads();
@@ -164,12 +180,12 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const double* __restrict__ R
 hipError_t launch_jacobi(const double* R, int l, int L, const double* shift, double* sigma, double* Ut, double* Mv,
                          DevFlags* flags, double* work, hipStream_t s) {
     if (l <= kJacobiLdsMax)
-        hipLaunchKernelGGL((jacobi_kernel<kJacobiLdsMax / 16, true, 1024>), dim3(1), dim3(1024), 0, s, R, l, L,
+        hipLaunchKernelGGL((jacobi_kernel<kJacobiLdsMax / 16, true, 1024, 8>), dim3(1), dim3(1024), 0, s, R, l, L,
                            shift, sigma, Ut, Mv, flags, work);
     else
         // 36 register pairs per lane: 512 threads leave 256 VGPRs per lane.
-        hipLaunchKernelGGL((jacobi_kernel<kMaxL / 16, false, 512>), dim3(1), dim3(512), 0, s, R, l, L, shift, sigma,
-                           Ut, Mv, flags, work);
+        hipLaunchKernelGGL((jacobi_kernel<kMaxL / 16, false, 512, 8>), dim3(1), dim3(512), 0, s, R, l, L, shift,
+                           sigma, Ut, Mv, flags, work);
     return hipGetLastError();
 }
 
