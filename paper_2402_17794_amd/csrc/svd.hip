@@ -10,11 +10,8 @@
 // and the column norms its singular values; the right singular vectors are
 // V = B^T U~ Sigma^{-1}.  Neither the rotations nor R^{-1} are needed.
 //
-// The Jacobi runs in one workgroup of 16 wavefronts: each round of the
-// round-robin ordering pairs all columns disjointly, and each quarter-wave
-// (16 lanes) takes one pair, forming the three inner products with DPP lane
-// sums (no LDS traffic, no barrier) before rotating the two columns in LDS.
-// One barrier per round.
+// l <= 128: jacobi_oe_kernel, X held in registers (see its comment).
+// l  > 128: jacobi_kernel, X in global memory, one barrier per round.
 #include <math.h>
 
 #include <algorithm>
@@ -25,7 +22,7 @@
 
 namespace rsvd {
 
-constexpr int kJacobiLdsMax = 128;
+constexpr int kJacobiRegMax = 128;
 constexpr double kJacobiTol = 1e-15;
 constexpr int kJacobiMaxSweeps = 60;
 
@@ -51,6 +48,274 @@ __device__ __forceinline__ double group_sum(double x) {
     return LPP == 4 ? quad_sum(x) : octet_sum(x);
 }
 
+// Reciprocal and reciprocal square root: the hardware estimates refined by
+// Newton steps (each squares the relative error), to full FP64 accuracy
+// for normal arguments without the rescaling of the library forms.
+__device__ __forceinline__ double rcp_newton1(double x) {
+    const double y = __builtin_amdgcn_rcp(x);
+    return fma(y, fma(-x, y, 1.0), y);
+}
+__device__ __forceinline__ double rcp_newton(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(y, fma(-x, y, 1.0), y);
+    return fma(y, fma(-x, y, 1.0), y);
+}
+__device__ __forceinline__ double rsq_newton(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) y = fma(0.5 * y, fma(-(x * y), y, 1.0), y);
+    return y;
+}
+
+// Tangent t of the Jacobi rotation for a column pair with squared norms a, b
+// and inner product g: zeta = (b - a) / 2g, t = sign(zeta) / (|zeta| +
+// sqrt(1 + zeta^2)), which makes the rotated pair orthogonal.  t = 0 (and
+// `rot` untouched) when |g| <= tol sqrt(a b), the pair already orthogonal.
+__device__ __forceinline__ double jacobi_tan(double a, double b, double g, int& rot) {
+    const bool r = g * g > (kJacobiTol * kJacobiTol) * (a * b);
+    rot |= (int)r;
+    const double q = (b - a) * rcp_newton1(2.0 * (r ? g : 1.0));
+    const double aq = fabs(q);
+    const double h = fma(aq, aq, 1.0);
+    const double t = aq > 1e15 ? 0.5 * rcp_newton1(aq) : rcp_newton(aq + h * rsq_newton(h));
+    return r ? (q >= 0.0 ? t : -t) : 0.0;
+}
+
+// A column of X as held by jacobi_oe_kernel: the true column is sc times the
+// stored one; nr is its squared norm (tracked), isc = 1 / sc, id the
+// original column index.
+struct JColumn {
+    double nr, sc, isc;
+    int id;
+};
+
+// Rotation of the true pair (xi, xj) by tangent t (cosine c = (1 + t^2)^-1/2,
+// sine s = c t): xi' = c xi - s xj, xj' = s xi + c xj.  With the cosine
+// moved into the scales, the stored columns change by one FMA per element:
+// yi' = yi - tr yj and yj' = yj + tir yi with tr = t sc_j / sc_i, tir = t sc_i
+// / sc_j; the squared norms become a - t g and b + t g.
+struct JRot {
+    double tr, tir;
+    JColumn ci, cj;
+};
+__device__ __forceinline__ JRot jacobi_rot(const JColumn& ci, const JColumn& cj, double g, double t) {
+    const double u = fma(t, t, 1.0);
+    const double c = rsq_newton(u), ic = u * c;
+    JRot o;
+    o.tr = t * (cj.sc * ci.isc);
+    o.tir = t * (ci.sc * cj.isc);
+    o.ci = {fma(-t, g, ci.nr), c * ci.sc, ic * ci.isc, ci.id};
+    o.cj = {fma(t, g, cj.nr), c * cj.sc, ic * cj.isc, cj.id};
+    return o;
+}
+
+template <int R>
+__device__ __forceinline__ double partial_dot(const double (&xi)[R], const double (&xj)[R]) {
+    double g0 = 0.0, g1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < R; k += 2) {
+        g0 = fma(xi[k], xj[k], g0);
+        if (k + 1 < R) g1 = fma(xi[k + 1], xj[k + 1], g1);
+    }
+    return g0 + g1;
+}
+
+// Sorted singular values, U~ and M = U~ Sigma^-1 (L x L, zero padded) from
+// the final columns; `nrm2` holds the squared norm of each original column
+// (scaled by sc4), shared by the whole workgroup.
+__device__ __forceinline__ void jacobi_rank(const double* nrm2, int* rank_of, int l, double sc4, double shift,
+                                            double* sigma) {
+    for (int c = threadIdx.x; c < l; c += blockDim.x) {
+        const double sc = sqrt(fmax(nrm2[c] * sc4 - shift, 0.0));
+        int rank = 0;
+        for (int d = 0; d < l; ++d) {
+            const double sd = sqrt(fmax(nrm2[d] * sc4 - shift, 0.0));
+            rank += (sd > sc) || (sd == sc && d < c);   // stable descending order
+        }
+        rank_of[c] = rank;
+        sigma[rank] = sc;
+    }
+}
+
+// One-sided Jacobi for l <= 128 with X in registers.  Ordering: odd-even
+// transposition.  Round r pairs the columns at positions (2i, 2i + 1) (r
+// even) or (2i + 1, 2i + 2) (r odd), rotates each pair and swaps the two
+// columns' positions; n (even) rounds make a sweep in which every pair of
+// columns meets exactly once (the sequence is reversed, one adjacent swap
+// per pair).
+//
+// A group of 8 lanes holds positions 2g and 2g + 1, lane e rows e + 8k (k <
+// R, rows >= l zero).  Even rounds are group-local: three DPP lane sums and
+// no memory traffic.  Odd rounds pair the group's second column with the
+// next group's first: both groups write their two columns to LDS, read their
+// neighbours', and each group computes the cross pair's rotation itself
+// (same inputs, same instructions, so both get the same rotation) and keeps
+// its own output column.  Two barriers per two rounds; 7 wavefronts at l =
+// 110, one pair per group.
+//
+// Columns carry scales (JColumn), so a rotation costs one FMA per element
+// and output; at the start of every sweep the scales are folded back in and
+// the norms recomputed exactly.  X is first scaled by a power of two so
+// that its largest column norm is about 1.  Sweeps stop when a whole sweep
+// rotates nothing.
+template <int R>
+__global__ __launch_bounds__(512) void jacobi_oe_kernel(const double* __restrict__ Rm, int l, int L,
+                                                        const double* __restrict__ shift_p,
+                                                        double* __restrict__ sigma, double* __restrict__ Ut,
+                                                        double* __restrict__ Mv, DevFlags* flags) {
+    constexpr int LPP = 8, GMAX = kJacobiRegMax / 2;
+    constexpr int BUF = 2 * R * GMAX * LPP;                 // exchange buffer [side][k][group][lane]
+    static_assert(LPP * R <= kJacobiRegMax, "rows per column");
+    __shared__ double xch[BUF];
+    __shared__ JColumn xcol[2][GMAX];
+    __shared__ double nrm2[kJacobiRegMax];
+    __shared__ int rank_of[kJacobiRegMax];
+    const int tid = threadIdx.x, gi = tid / LPP, e = tid % LPP;
+    const int n2 = (l + 1) & ~1, G = n2 / 2;
+    const bool active = gi < G;
+    const bool hasR = gi < G - 1, hasL = active && gi > 0;
+    auto xidx = [&](int side, int k, int g) { return ((side * R + k) * GMAX + g) * LPP + e; };
+
+    double x0[R], x1[R];
+    JColumn c0, c1;
+    c0.id = 2 * gi;
+    c1.id = 2 * gi + 1;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int r = e + LPP * k;
+        x0[k] = (active && 2 * gi < l && r < l) ? Rm[(int64_t)(2 * gi) * L + r] : 0.0;
+        x1[k] = (active && 2 * gi + 1 < l && r < l) ? Rm[(int64_t)(2 * gi + 1) * L + r] : 0.0;
+    }
+    for (int i = tid; i < kJacobiRegMax; i += blockDim.x) nrm2[i] = 0.0;
+    __syncthreads();
+    {
+        const double s0 = octet_sum(partial_dot<R>(x0, x0)), s1 = octet_sum(partial_dot<R>(x1, x1));
+        if (active && e == 0) {
+            nrm2[2 * gi] = s0;
+            nrm2[2 * gi + 1] = s1;
+        }
+    }
+    __syncthreads();
+    double mx = 0.0;
+    for (int i = 0; i < n2; ++i) mx = fmax(mx, nrm2[i]);
+    const int ex = mx > 0.0 ? ilogb(mx) / 2 : 0;
+    c0.sc = c1.sc = ldexp(1.0, -ex);
+    c0.isc = c1.isc = 1.0;
+
+    bool converged = (l < 2);
+    for (int sweep = 0; sweep < kJacobiMaxSweeps && !converged; ++sweep) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            x0[k] *= c0.sc;
+            x1[k] *= c1.sc;
+        }
+        c0.sc = c1.sc = c0.isc = c1.isc = 1.0;
+        {
+            const double p0 = partial_dot<R>(x0, x0), p1 = partial_dot<R>(x1, x1);
+            c0.nr = octet_sum(p0);
+            c1.nr = octet_sum(p1);
+        }
+        int rot = 0;
+        for (int h = 0; h < G; ++h) {
+            {   // even round: pair (2g, 2g + 1); position 2g takes the rotated second column
+                const double g = octet_sum(partial_dot<R>(x0, x1)) * (c0.sc * c1.sc);
+                const JRot o = jacobi_rot(c0, c1, g, jacobi_tan(c0.nr, c1.nr, g, rot));
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const double yi = x0[k], yj = x1[k];
+                    x0[k] = fma(o.tir, yi, yj);
+                    x1[k] = fma(-o.tr, yj, yi);
+                }
+                c0 = o.cj;
+                c1 = o.ci;
+            }
+            // odd round: pairs (2g + 1, 2g + 2) across neighbouring groups
+            if (active) {
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    xch[xidx(0, k, gi)] = x0[k];
+                    xch[xidx(1, k, gi)] = x1[k];
+                }
+                if (e == 0) {
+                    xcol[0][gi] = c0;
+                    xcol[1][gi] = c1;
+                }
+            }
+            __syncthreads();
+            const int gr = hasR ? gi + 1 : gi, gl = hasL ? gi - 1 : gi;
+            double yr[R], yl[R];
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                yr[k] = xch[xidx(0, k, gr)];
+                yl[k] = xch[xidx(1, k, gl)];
+            }
+            JColumn cr = xcol[0][gr], cl = xcol[1][gl];
+            __syncthreads();
+            const double pr = partial_dot<R>(x1, yr), pl = partial_dot<R>(yl, x0);
+            const double gR = hasR ? octet_sum(pr) * (c1.sc * cr.sc) : 0.0;
+            const double gL = hasL ? octet_sum(pl) * (cl.sc * c0.sc) : 0.0;
+            if (!hasR) cr = {0.0, 1.0, 1.0, 0};
+            if (!hasL) cl = {0.0, 1.0, 1.0, 0};
+            const JRot oR = jacobi_rot(c1, cr, gR, jacobi_tan(c1.nr, cr.nr, gR, rot));
+            const JRot oL = jacobi_rot(cl, c0, gL, jacobi_tan(cl.nr, c0.nr, gL, rot));
+            if (hasR) {       // position 2g + 1 takes the rotated right neighbour
+#pragma unroll
+                for (int k = 0; k < R; ++k) x1[k] = fma(oR.tir, x1[k], yr[k]);
+                c1 = oR.cj;
+            }
+            if (hasL) {       // position 2g takes the rotated left neighbour
+#pragma unroll
+                for (int k = 0; k < R; ++k) x0[k] = fma(-oL.tr, x0[k], yl[k]);
+                c0 = oL.ci;
+            }
+        }
+        converged = !__syncthreads_or(rot);
+    }
+    if (!converged && tid == 0) atomicOr(&flags->info, RSVD_INFO_JACOBI_NOT_CONVERGED);
+
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        x0[k] *= c0.sc;
+        x1[k] *= c1.sc;
+    }
+    __syncthreads();
+    {
+        const double s0 = octet_sum(partial_dot<R>(x0, x0)), s1 = octet_sum(partial_dot<R>(x1, x1));
+        if (active && e == 0) {
+            if (c0.id < l) nrm2[c0.id] = s0;
+            if (c1.id < l) nrm2[c1.id] = s1;
+        }
+    }
+    __syncthreads();
+    const double shift = *shift_p, sc4 = ldexp(1.0, 2 * ex);
+    jacobi_rank(nrm2, rank_of, l, sc4, shift, sigma);
+    for (int idx = tid; idx < L * L; idx += blockDim.x) {
+        Ut[idx] = 0.0;
+        Mv[idx] = 0.0;
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int c = q ? c1.id : c0.id;
+            if (c >= l) continue;
+            const double nc = sqrt(nrm2[c]);
+            const double sc = sqrt(fmax(nrm2[c] * sc4 - shift, 0.0));
+            const double inv = nc > 0.0 ? 1.0 / nc : 0.0;
+            const int col = rank_of[c];
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const int r = e + LPP * k;
+                if (r < l) {
+                    const double u = nc > 0.0 ? (q ? x1[k] : x0[k]) * inv : (r == c ? 1.0 : 0.0);
+                    Ut[(int64_t)r * L + col] = u;
+                    Mv[(int64_t)r * L + col] = sc > 0.0 ? u / sc : 0.0;
+                }
+            }
+        }
+    }
+}
+
 // Round-robin (circle method) schedule: with n2 (even) columns, round r pairs
 // slot 0 with (n2 - 1, r) and slot s > 0 with ((r + s), (r - s)) mod (n2 - 1).
 __device__ __forceinline__ void rr_pair(int r, int s, int n2, int& p1, int& p2) {
@@ -60,25 +325,23 @@ __device__ __forceinline__ void rr_pair(int r, int s, int n2, int& p1, int& p2) 
     p2 = r - s + m; if (p2 >= m) p2 -= m;
 }
 
-// One-sided Jacobi on X = R^T; LPP lanes per column pair.  Columns are
-// stored with a padded stride (zero rows past l stay zero under rotations),
-// so every lane loads and stores its rows 2e, 2e+1, 2e+2 LPP, 2e+2 LPP+1, ...
-// as 16-byte pairs without bounds checks.  NP = row pairs per lane.  Both
-// forms use 8 lanes per pair: with 4 (one wavefront per SIMD) a round was
-// slower, the latencies no longer hidden.
-template <int NP, bool IN_LDS, int NT, int LPP>
+// One-sided Jacobi for l > 128 with X = R^T in global memory (work, column
+// stride kMaxL), LPP lanes per column pair, one barrier per round of the
+// round-robin ordering.  Zero rows past l stay zero under rotations, so every
+// lane loads and stores its rows 2e, 2e+1, 2e+2 LPP, 2e+2 LPP+1, ... as
+// 16-byte pairs without bounds checks.  NP = row pairs per lane.
+template <int NP, int NT, int LPP>
 __global__ __launch_bounds__(NT) void jacobi_kernel(const double* __restrict__ R, int l, int L,
                                                       const double* __restrict__ shift_p, double* __restrict__ sigma,
                                                       double* __restrict__ Ut, double* __restrict__ Mv,
                                                       DevFlags* flags, double* __restrict__ work) {
-    __shared__ __attribute__((aligned(16))) double lds[IN_LDS ? kJacobiLdsMax * kJacobiLdsMax : 2];
     __shared__ int rotated;
     __shared__ double nrm2[kMaxL];
     __shared__ int rank_of[kMaxL];
-    const int ld = IN_LDS ? kJacobiLdsMax : kMaxL;  // column stride (>= 16 * NP rows)
-    double* X = IN_LDS ? lds : work;                // X[c * ld + r] = R[c][r], zero for r >= l
+    const int ld = kMaxL;
+    double* X = work;                               // X[c * ld + r] = R[c][r], zero for r >= l
     const int tid = threadIdx.x, grp = tid / LPP, e = tid % LPP;
-    static_assert(2 * NP * LPP <= (IN_LDS ? kJacobiLdsMax : kMaxL), "rows per column");
+    static_assert(2 * NP * LPP <= kMaxL, "rows per column");
 
     for (int idx = tid; idx < l * ld; idx += NT) {
         const int c = idx / ld, r = idx - c * ld;
@@ -149,17 +412,7 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const double* __restrict__ R
     }
     __syncthreads();
     const double shift = *shift_p;
-    // Stable descending order of the singular values sqrt(max(nrm2 - shift, 0)).
-    for (int c = tid; c < l; c += NT) {
-        const double sc = sqrt(fmax(nrm2[c] - shift, 0.0));
-        int rank = 0;
-        for (int d = 0; d < l; ++d) {
-            const double sd = sqrt(fmax(nrm2[d] - shift, 0.0));
-            rank += (sd > sc) || (sd == sc && d < c);
-        }
-        rank_of[c] = rank;
-        sigma[rank] = sc;
-    }
+    jacobi_rank(nrm2, rank_of, l, 1.0, shift, sigma);
     __syncthreads();
     for (int idx = tid; idx < L * L; idx += NT) {
         Ut[idx] = 0.0;
@@ -177,15 +430,34 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const double* __restrict__ R
     }
 }
 
+template <int R>
+static void launch_jacobi_oe(const double* Rm, int l, int L, const double* shift, double* sigma, double* Ut,
+                             double* Mv, DevFlags* flags, hipStream_t s) {
+    const int groups = ((l + 1) & ~1) / 2;
+    const int threads = (int)round_up(groups * 8, kWave);
+    hipLaunchKernelGGL(jacobi_oe_kernel<R>, dim3(1), dim3(threads), 0, s, Rm, l, L, shift, sigma, Ut, Mv, flags);
+}
+
 hipError_t launch_jacobi(const double* R, int l, int L, const double* shift, double* sigma, double* Ut, double* Mv,
                          DevFlags* flags, double* work, hipStream_t s) {
-    if (l <= kJacobiLdsMax)
-        hipLaunchKernelGGL((jacobi_kernel<kJacobiLdsMax / 16, true, 1024, 8>), dim3(1), dim3(1024), 0, s, R, l, L,
-                           shift, sigma, Ut, Mv, flags, work);
-    else
+    if (l < 1 || l > kMaxL || L < l) return hipErrorInvalidValue;
+    if (l <= kJacobiRegMax) {
+        // rows per lane and column: 2 ceil(l / 16), so 8 lanes cover ceil(l / 16) * 16 >= l rows
+        switch ((l + 15) / 16) {
+            case 1: launch_jacobi_oe<2>(R, l, L, shift, sigma, Ut, Mv, flags, s); break;
+            case 2: launch_jacobi_oe<4>(R, l, L, shift, sigma, Ut, Mv, flags, s); break;
+            case 3: launch_jacobi_oe<6>(R, l, L, shift, sigma, Ut, Mv, flags, s); break;
+            case 4: launch_jacobi_oe<8>(R, l, L, shift, sigma, Ut, Mv, flags, s); break;
+            case 5: launch_jacobi_oe<10>(R, l, L, shift, sigma, Ut, Mv, flags, s); break;
+            case 6: launch_jacobi_oe<12>(R, l, L, shift, sigma, Ut, Mv, flags, s); break;
+            case 7: launch_jacobi_oe<14>(R, l, L, shift, sigma, Ut, Mv, flags, s); break;
+            default: launch_jacobi_oe<16>(R, l, L, shift, sigma, Ut, Mv, flags, s); break;
+        }
+    } else {
         // 36 register pairs per lane: 512 threads leave 256 VGPRs per lane.
-        hipLaunchKernelGGL((jacobi_kernel<kMaxL / 16, false, 512, 8>), dim3(1), dim3(512), 0, s, R, l, L, shift,
-                           sigma, Ut, Mv, flags, work);
+        hipLaunchKernelGGL((jacobi_kernel<kMaxL / 16, 512, 8>), dim3(1), dim3(512), 0, s, R, l, L, shift, sigma, Ut,
+                           Mv, flags, work);
+    }
     return hipGetLastError();
 }
 
