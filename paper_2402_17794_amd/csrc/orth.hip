@@ -123,162 +123,242 @@ hipError_t launch_gram(int dtype, const void* Y, int64_t ldy, int64_t rows, int 
 // is orthonormal to O(|E|^2).  Otherwise the exact factorisation runs.
 constexpr int kCholLdsMax = 128;
 
-template <bool IN_LDS>
-__global__ __launch_bounds__(1024) void chol_kernel(const double* __restrict__ part, int nchunks, int l, int L,
-                                                    double* __restrict__ R, double* __restrict__ Rinv,
-                                                    DevFlags* flags, int mode, double* shift_out,
-                                                    double* __restrict__ work, double tau) {
-    constexpr int LP = IN_LDS ? kCholLdsMax : 1;
-    __shared__ double lds[IN_LDS ? kCholLdsMax * kCholLdsMax : 1];
+// Form for 128 < l <= kMaxL: blocked right-looking Cholesky, panels of 16,
+// one workgroup of 16 wavefronts, the working matrix A (L x L, upper block
+// triangle) in global memory, where it stays in the L2 cache.  Per panel p:
+//   1. wavefront 0 factors the diagonal block A_pp = R_pp^T R_pp in LDS (16
+//      pivot steps inside one wavefront, no workgroup barrier) and inverts it;
+//   2. R_pq = R_pp^{-T} A_pq for the tiles right of it (FP64 MFMA);
+//   3. A_qr -= R_pq^T R_pr for p < q <= r (FP64 MFMA, R_p. from LDS).
+// Three barriers per panel.  R^{-1} (modes 0, 1) then comes from the block
+// triangle, bottom block row first: X_ij = -R_ii^{-1} sum_{i<k<=j} R_ik X_kj.
+// Padding rows and columns (l <= index < L) carry an identity block, which
+// no elimination step couples to the leading l x l block; the outputs are
+// zero there.  Breakdown, the first-order second pass and the mode-2 shift
+// retries follow the l <= 128 form.
+constexpr int kCholBlkNt = kMaxL / 16;
+constexpr int kCholBlkLd = kMaxL + 4;          // LDS panel row stride (doubles)
+
+__device__ __forceinline__ void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
+
+__global__ __launch_bounds__(1024) void chol_blk_kernel(const double* __restrict__ part, int nchunks, int l, int L,
+                                                        double* __restrict__ R, double* __restrict__ Rinv,
+                                                        DevFlags* flags, int mode, double* shift_out,
+                                                        double* __restrict__ A, double tau) {
+    __shared__ double T[16 * 17];                   // diagonal block being factored
+    __shared__ double Dinv[kCholBlkNt][256];        // R_pp^{-1} of every diagonal block (row-major 16 x 16)
+    __shared__ double Prow[16 * kCholBlkLd];        // the current panel rows R_p. (16 x L)
     __shared__ double dg[kMaxL];
-    __shared__ double inv_r[kMaxL];
     __shared__ unsigned long long s_emax;
+    __shared__ int s_nonfinite, s_broke;
     if (mode == 1 && flags->orth_fail) return;
-    double* M = IN_LDS ? lds : work;
-    const int ldm = IN_LDS ? LP : l;
-    const int tid = threadIdx.x, rg = tid >> 5, cl = tid & 31;
-    const int nt = L / 16, npairs = nt * (nt + 1) / 2;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int nt = L / 16, npairs = nt * (nt + 1) / 2, stride = npairs * 256;
+    const int li = lane & 15, lk = lane >> 4;       // MFMA operand coordinates
 
-    // Sum the chunk partials (chunk order) into the upper triangle of M;
-    // the strict lower triangle starts at zero.
-    if (tid == 0) s_emax = 0ull;
-    for (int a = rg; a < l; a += 32)
-        for (int c = cl; c < a; c += 32) M[a * ldm + c] = 0.0;
-    double emax = 0.0;
-    for (int idx = tid; idx < npairs * 256; idx += 1024) {
-        const int pr = idx >> 8, e = idx & 255;
-        int ta = 0, pp = pr;
-        while (pp >= nt - ta) { pp -= nt - ta; ++ta; }
-        const int row = ta * 16 + (e >> 4), col = (ta + pp) * 16 + (e & 15);
-        if (row > col || row >= l || col >= l) continue;
-        double sum = 0.0;
-        int c = 0;
-        for (; c + 4 <= nchunks; c += 4) {
-            const double x0 = part[((size_t)(c + 0) * npairs + pr) * 256 + e];
-            const double x1 = part[((size_t)(c + 1) * npairs + pr) * 256 + e];
-            const double x2 = part[((size_t)(c + 2) * npairs + pr) * 256 + e];
-            const double x3 = part[((size_t)(c + 3) * npairs + pr) * 256 + e];
-            sum = (((sum + x0) + x1) + x2) + x3;
+    // A = upper block triangle of G (+ shift on the leading diagonal), identity padding.
+    auto load = [&](double shift) {
+        double emax = 0.0;
+        bool nf = false;
+        for (int idx = tid; idx < stride; idx += 1024) {
+            const int pr = idx >> 8, e = idx & 255;
+            int ta = 0, pp = pr;
+            while (pp >= nt - ta) { pp -= nt - ta; ++ta; }
+            const int row = ta * 16 + (e >> 4), col = (ta + pp) * 16 + (e & 15);
+            double v;
+            if (row < l && col < l) {
+                double sum = 0.0;
+                for (int c = 0; c < nchunks; ++c) sum += part[(size_t)c * stride + idx];
+                if (row == col) {
+                    dg[row] = sum;
+                    if (!isfinite(sum)) nf = true;
+                }
+                double ee = fabs(sum - (row == col ? 1.0 : 0.0));
+                if (!(ee < 1e300)) ee = 1e300;
+                if (row <= col) emax = fmax(emax, ee);
+                v = sum + (row == col ? shift : 0.0);
+            } else {
+                v = row == col ? 1.0 : 0.0;
+            }
+            A[(size_t)row * L + col] = v;
         }
-        for (; c < nchunks; ++c) sum += part[((size_t)c * npairs + pr) * 256 + e];
-        M[row * ldm + col] = sum;
-        if (row == col) dg[row] = sum;
-        double ee = fabs(sum - (row == col ? 1.0 : 0.0));
-        if (!(ee < 1e300)) ee = 1e300;
-        emax = fmax(emax, ee);
-    }
-    if (mode == 1) atomicMax(&s_emax, (unsigned long long)__double_as_longlong(emax));
-    __syncthreads();
+        if (nf) s_nonfinite = 1;
+        return emax;
+    };
 
+    if (tid == 0) { s_emax = 0ull; s_nonfinite = 0; }
+    __syncthreads();
+    const double emax_t = load(0.0);
+    if (mode == 1) atomicMax(&s_emax, (unsigned long long)__double_as_longlong(emax_t));
+    __syncthreads();
     if (mode == 1 && __longlong_as_double((long long)s_emax) <= tau) {
-        // Second pass: first-order factor (see above).
-#pragma unroll 4
+        // Second pass: first-order factor R^{-1} = I - U, U = triu(E) - diag(E) / 2.
         for (int idx = tid; idx < L * L; idx += 1024) {
             const int a = idx / L, c = idx - a * L;
-            double r = 0.0, ri = 0.0;
+            double ri = 0.0;
             if (a <= c && c < l) {
-                const double e = M[a * ldm + c] - (a == c ? 1.0 : 0.0);
-                const double u = a < c ? e : 0.5 * e;
-                r = (a == c ? 1.0 : 0.0) + u;
-                ri = (a == c ? 1.0 : 0.0) - u;
+                const double e = A[(size_t)a * L + c] - (a == c ? 1.0 : 0.0);
+                ri = (a == c ? 1.0 : 0.0) - (a < c ? e : 0.5 * e);
             }
-            R[idx] = r;
             Rinv[idx] = ri;
         }
         if (tid == 0) flags->orth_fail = 0;
         return;
     }
-
+    const bool nonfinite = s_nonfinite != 0;
     double gmax = 0.0;
-    bool nonfinite = false;
-    for (int j = 0; j < l; ++j) {
-        const double d = dg[j];
-        if (!isfinite(d)) nonfinite = true;
-        else gmax = fmax(gmax, d);
-    }
+    for (int j = 0; j < l; ++j) gmax = fmax(gmax, dg[j]);
     const double rel = (mode == 0) ? 1e-12 : (mode == 1 ? 1e-2 : 0.0);
-    double shift = 0.0, applied = 0.0;
-    bool broke = false;
-    for (int attempt = 0; attempt < (mode == 2 ? 5 : 1); ++attempt) {
-        if (shift != applied) {        // retry: the factorisation overwrote M; restore with the new shift
+    double shift = 0.0;
+    bool broke = nonfinite;
+    for (int attempt = 0; attempt < (mode == 2 ? 5 : 1) && !nonfinite; ++attempt) {
+        if (attempt > 0) {
             __syncthreads();
-            for (int idx = tid; idx < npairs * 256; idx += 1024) {
-                const int pr = idx >> 8, e = idx & 255;
-                int ta = 0, pp = pr;
-                while (pp >= nt - ta) { pp -= nt - ta; ++ta; }
-                const int row = ta * 16 + (e >> 4), col = (ta + pp) * 16 + (e & 15);
-                if (row > col || row >= l || col >= l) continue;
-                double sum = 0.0;
-                for (int c = 0; c < nchunks; ++c) sum += part[((size_t)c * npairs + pr) * 256 + e];
-                M[row * ldm + col] = sum + (row == col ? shift : 0.0);
-            }
-            for (int a = rg; a < l; a += 32)
-                for (int c = cl; c < a; c += 32) M[a * ldm + c] = 0.0;
-            applied = shift;
-            __syncthreads();
+            load(shift);
         }
-        broke = nonfinite;
-        for (int j = 0; j < l && !broke; ++j) {
-            const double d = M[j * ldm + j];
-            if (!(d > rel * (dg[j] + shift)) || !(d > 0.0) || !isfinite(d)) { broke = true; break; }
-            const double inv_rj = 1.0 / sqrt(d), inv_d = inv_rj * inv_rj;
-            if (tid == 0) inv_r[j] = inv_rj;
-            if (IN_LDS) {
-                // Rows a = j+1+rg+32u (u < 4), columns c = cl+32v (v < 4); l <= 128.
-                double rowj[4], f[4], x[4][4];
+        if (tid == 0) s_broke = 0;
+        __syncthreads();
+        for (int p = 0; p < nt; ++p) {
+            const int j0 = 16 * p;
+            if (wid == 0) {
+                // 1. Diagonal block: lane owns row i, columns kq..kq+3 of T.
+                const int i = lane >> 2, kq = (lane & 3) * 4;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int k = kq + u;
+                    T[i * 17 + k] = k >= i ? A[(size_t)(j0 + i) * L + j0 + k] : A[(size_t)(j0 + k) * L + j0 + i];
+                }
+                wave_fence();
+                bool bad = false;
+                for (int j = 0; j < 16; ++j) {
+                    const double d = T[j * 17 + j];
+                    if (j0 + j < l && (!(d > rel * (dg[j0 + j] + shift)) || !(d > 0.0) || !isfinite(d))) {
+                        bad = true;       // same d in every lane
+                        break;
+                    }
+                    const double rinv = 1.0 / sqrt(d);
+                    if (i == j) {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            if (kq + u >= j) T[j * 17 + kq + u] *= rinv;
+                    }
+                    wave_fence();
+                    if (i > j) {
+                        const double rji = T[j * 17 + i];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int k = kq + u;
+                            if (k >= i) T[i * 17 + k] -= rji * T[j * 17 + k];
+                        }
+                    }
+                    wave_fence();
+                }
+                if (!bad) {
+                    // R_pp^{-1}: lane c < 16 forms column c, rows 15 down to 0.
+                    if (lane < 16) {
+                        const int c = lane;
+                        double x[16];
+#pragma unroll
+                        for (int r = 15; r >= 0; --r) {
+                            double sacc = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+                            for (int k = r + 1; k < 16; ++k)
+                                if (k <= c) sacc -= T[r * 17 + k] * x[k];
+                            x[r] = r <= c ? sacc / T[r * 17 + r] : 0.0;
+                        }
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) Dinv[p][r * 16 + c] = x[r];
+                    }
+                    // R_pp (upper) back into A for the mode-2 output.
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int k = kq + u;
+                        if (k >= i) A[(size_t)(j0 + i) * L + j0 + k] = T[i * 17 + k];
+                    }
+                } else if (lane == 0) {
+                    s_broke = 1;
+                }
+            }
+            __syncthreads();
+            if (s_broke) break;
+            // 2. Panel row tiles: R_pq = R_pp^{-T} A_pq.
+            for (int q = p + 1 + wid; q < nt; q += 16) {
+                doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int st = 0; st < 4; ++st) {
+                    const int k = 4 * st + lk;
+                    acc = mfma16x16x4(Dinv[p][k * 16 + li], A[(size_t)(j0 + k) * L + q * 16 + li], acc);
+                }
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int c = cl + 32 * v;
-                    rowj[v] = c < l ? M[j * ldm + c] : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int a = min(j + 1 + rg + 32 * u, LP - 1);
-                    f[u] = M[j * ldm + a] * inv_d;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) x[u][v] = M[a * ldm + cl + 32 * v];
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int a = j + 1 + rg + 32 * u;
-                    if (a >= l) continue;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int c = cl + 32 * v;
-                        if (c >= l) continue;
-                        if (c >= a || c < j) M[a * ldm + c] = x[u][v] - f[u] * rowj[v];
-                        else if (c == j) M[a * ldm + j] = -f[u];
-                    }
-                }
-            } else {
-                for (int a = j + 1 + rg; a < l; a += 32) {
-                    const double fa = M[j * ldm + a] * inv_d;
-                    for (int c = cl; c < l; c += 32) {
-                        if (c >= a || c < j) M[a * ldm + c] -= fa * M[j * ldm + c];
-                        else if (c == j) M[a * ldm + j] = -fa;
-                    }
+                    const int r = lk + 4 * v;
+                    A[(size_t)(j0 + r) * L + q * 16 + li] = acc[v];
+                    Prow[r * kCholBlkLd + q * 16 + li] = acc[v];
                 }
             }
             __syncthreads();
+            // 3. Trailing update of the tiles (q, r), p < q <= r.
+            const int nr = nt - p - 1, ntr = nr * (nr + 1) / 2;
+            for (int t = wid; t < ntr; t += 16) {
+                int qq = 0, tt = t;
+                while (tt >= nr - qq) { tt -= nr - qq; ++qq; }
+                const int q = p + 1 + qq, r = q + tt;
+                doublex4 acc;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[v] = A[(size_t)(q * 16 + lk + 4 * v) * L + r * 16 + li];
+#pragma unroll
+                for (int st = 0; st < 4; ++st) {
+                    const int k = 4 * st + lk;
+                    acc = mfma16x16x4(-Prow[k * kCholBlkLd + q * 16 + li], Prow[k * kCholBlkLd + r * 16 + li], acc);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) A[(size_t)(q * 16 + lk + 4 * v) * L + r * 16 + li] = acc[v];
+            }
+            __syncthreads();
         }
-        if (!broke || mode != 2 || nonfinite) break;
+        broke = s_broke != 0;
+        if (!broke || mode != 2) break;
         shift = (shift == 0.0) ? gmax * 0x1.0p-40 : shift * 1024.0;
         if (!(shift > 0.0)) shift = 0x1.0p-1000;
     }
-    __syncthreads();
-    // Row a of M holds row a of R (times r_aa) in its upper part and row a of
-    // R^{-T} (times r_aa) in its strict lower part; neither changes after step a.
     if (!broke) {
-#pragma unroll 4
-        for (int idx = tid; idx < L * L; idx += 1024) {
-            const int x = idx / L, y = idx - x * L;
-            double r = 0.0, ri = 0.0;
-            if (x < l && y < l) {
-                if (y >= x) r = M[x * ldm + y] * inv_r[x];
-                if (x <= y) ri = (x == y) ? inv_r[y] : M[y * ldm + x] * inv_r[y];
+        if (mode == 2) {
+            for (int idx = tid; idx < L * L; idx += 1024) {
+                const int x = idx / L, y = idx - x * L;
+                R[idx] = (x <= y && y < l) ? A[(size_t)x * L + y] : 0.0;
             }
-            R[idx] = r;
-            Rinv[idx] = ri;
+        } else {
+            // Diagonal blocks of R^{-1}, zero lower block triangle.
+            for (int idx = tid; idx < L * L; idx += 1024) {
+                const int x = idx / L, y = idx - x * L, bx = x >> 4, by = y >> 4;
+                if (bx > by) Rinv[idx] = 0.0;
+                else if (bx == by) Rinv[idx] = (x < l && y < l) ? Dinv[bx][(x & 15) * 16 + (y & 15)] : 0.0;
+            }
+            __syncthreads();
+            for (int i = nt - 2; i >= 0; --i) {
+                for (int j = i + 1 + wid; j < nt; j += 16) {
+                    doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+                    for (int k = i + 1; k <= j; ++k) {
+#pragma unroll
+                        for (int st = 0; st < 4; ++st) {
+                            const int kk = 4 * st + lk;
+                            acc = mfma16x16x4(A[(size_t)(i * 16 + li) * L + k * 16 + kk],
+                                              Rinv[(size_t)(k * 16 + kk) * L + j * 16 + li], acc);
+                        }
+                    }
+                    // The accumulator layout (rows lk + 4 v) is the B-operand layout
+                    // of k-step v, so acc feeds the product with R_ii^{-1} directly.
+                    doublex4 out = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int st = 0; st < 4; ++st) out = mfma16x16x4(Dinv[i][li * 16 + 4 * st + lk], acc[st], out);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int x = i * 16 + lk + 4 * v, y = j * 16 + li;
+                        Rinv[(size_t)x * L + y] = (x < l && y < l) ? -out[v] : 0.0;
+                    }
+                }
+                __syncthreads();
+            }
         }
     }
     if (tid == 0) {
@@ -517,7 +597,7 @@ hipError_t launch_chol(const double* partials, int64_t rows, int l, int L, doubl
         hipLaunchKernelGGL(chol_rl_kernel, dim3(1), dim3(kCholThreads), 0, s, partials, nchunks, l, L, R, Rinv, flags,
                            mode, shift_out, tau);
     else
-        hipLaunchKernelGGL(chol_kernel<false>, dim3(1), dim3(1024), 0, s, partials, nchunks, l, L, R, Rinv, flags,
+        hipLaunchKernelGGL(chol_blk_kernel, dim3(1), dim3(1024), 0, s, partials, nchunks, l, L, R, Rinv, flags,
                            mode, shift_out, work, tau);
     return hipGetLastError();
 }
