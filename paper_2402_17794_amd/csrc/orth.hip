@@ -590,10 +590,271 @@ __global__ __launch_bounds__(kCholThreads) void chol_rl_kernel(const double* __r
     }
 }
 
+// Form for L <= 112 (at most 7 tiles of 16): blocked right-looking
+// factorisation of the augmented matrix [G | I] with everything in LDS: the
+// upper block triangle of G (left tiles) and the lower block triangle of the
+// right half M.  For each block row p:
+//   1. one wavefront factors the diagonal tile, G_pp = R_pp^T R_pp, in
+//      registers: lane c < 16 holds column c of the tile and lane 16 + c
+//      column c of the identity; pivot j scales row j by d_j^{-1/2} and
+//      subtracts R_pp[j][i] times it from every row i > j, the row entries
+//      broadcast by lane reads (no LDS traffic, no barrier).  The same row
+//      operations turn the identity into R_pp^{-T};
+//   2. block row p is multiplied by R_pp^{-T}: its left tiles become the
+//      panel R_pq, its right tiles (c < p) rows of R^{-T} (FP64 MFMA);
+//   3. every later block row q subtracts R_pq^T times block row p: left
+//      tiles G_qr (q <= r), right tiles M_qc (c <= p) (FP64 MFMA).
+// Wavefront 0 updates the next diagonal tile first and factors it while
+// the others finish step 3 (look-ahead), so each block row costs two
+// barriers, against one per pivot in the per-pivot form.  At the end the left tiles hold R and the right tiles R^{-T}.
+// Padding rows and columns (l <= index < L) carry an identity, which no step
+// couples to the leading l x l block.  Breakdown, the first-order second
+// pass and the mode-2 shift retries follow the per-pivot form; mode 2 (R
+// only) keeps just the diagonal right tiles R_pp^{-T}, which step 2 needs.
+constexpr int kCholMfmaMaxNt = 7;
+constexpr int kTileLd = 17;                    // LDS row stride of a tile (odd: conflict-free operand reads)
+constexpr int kTileSz = 16 * kTileLd;
+
+__device__ __forceinline__ double lane_bcast(double x, int src) {      // x of lane `src` (uniform), in every lane
+    const int2 v = __builtin_bit_cast(int2, x);
+    int2 r;
+    r.x = __builtin_amdgcn_readlane(v.x, src);
+    r.y = __builtin_amdgcn_readlane(v.y, src);
+    return __builtin_bit_cast(double, r);
+}
+
+// 1 / sqrt(x) for a positive normal x: the hardware estimate and two Newton
+// steps (each squares the relative error), about one ulp.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) y = fma(0.5 * y, fma(-(x * y), y, 1.0), y);
+    return y;
+}
+
+__global__ __launch_bounds__(kCholThreads) void chol_mfma_kernel(const double* __restrict__ part, int nchunks, int l,
+                                                                 int L, double* __restrict__ R,
+                                                                 double* __restrict__ Rinv, DevFlags* flags, int mode,
+                                                                 double* shift_out, double tau) {
+    constexpr int NTT = kCholMfmaMaxNt * (kCholMfmaMaxNt + 1) / 2;
+    __shared__ double Gt[NTT * kTileSz];        // left tiles (a, b), a <= b
+    __shared__ double Mt[NTT * kTileSz];        // right tiles (q, c), c <= q
+    __shared__ double dg[16 * kCholMfmaMaxNt];
+    __shared__ unsigned long long s_emax;
+    __shared__ int s_nonfinite, s_broke;
+    if (mode == 1 && flags->orth_fail) return;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = kCholThreads / 64;
+    const int li = lane & 15, lk = lane >> 4;
+    const int nt = L / 16, npairs = nt * (nt + 1) / 2, stride = npairs * 256;
+    auto gt = [&](int a, int b) { return Gt + (a * nt - a * (a - 1) / 2 + (b - a)) * kTileSz; };
+    auto mt = [&](int q, int c) { return Mt + (q * (q + 1) / 2 + c) * kTileSz; };
+
+    // Sum the chunk partials in chunk order into the left tiles (identity
+    // outside the leading l x l block), 32 loads of a thread in flight.
+    auto load = [&](double shift) {
+        double emax = 0.0;
+        bool nf = false;
+        for (int i0 = tid; i0 < stride; i0 += 4 * kCholThreads) {
+            double x[4][8];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const int idx = min(i0 + u * kCholThreads, stride - 1), cc = min(c, nchunks - 1);
+                    x[u][c] = part[(size_t)cc * stride + idx];
+                }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int idx = i0 + u * kCholThreads;
+                if (idx >= stride) break;
+                double sum = 0.0;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) sum += c < nchunks ? x[u][c] : 0.0;
+                const int pr = idx >> 8, e = idx & 255;
+                int ta = 0, pp = pr;
+                while (pp >= nt - ta) { pp -= nt - ta; ++ta; }
+                const int row = ta * 16 + (e >> 4), col = (ta + pp) * 16 + (e & 15);
+                double v;
+                if (row < l && col < l) {
+                    if (row == col) {
+                        dg[row] = sum;
+                        if (!isfinite(sum)) nf = true;
+                    }
+                    if (row <= col) {
+                        double ee = fabs(sum - (row == col ? 1.0 : 0.0));
+                        if (!(ee < 1e300)) ee = 1e300;
+                        emax = fmax(emax, ee);
+                    }
+                    v = sum + (row == col ? shift : 0.0);
+                } else {
+                    v = row == col ? 1.0 : 0.0;
+                }
+                gt(ta, ta + pp)[(e >> 4) * kTileLd + (e & 15)] = v;
+            }
+        }
+        if (nf) s_nonfinite = 1;
+        return emax;
+    };
+
+    if (tid == 0) { s_emax = 0ull; s_nonfinite = 0; }
+    __syncthreads();
+    const double emax_t = load(0.0);
+    if (mode == 1) atomicMax(&s_emax, (unsigned long long)__double_as_longlong(emax_t));
+    __syncthreads();
+    if (mode == 1 && __longlong_as_double((long long)s_emax) <= tau) {
+        // Second pass: first-order factor R^{-1} = I - U, U = triu(E) - diag(E) / 2.
+        for (int idx = tid; idx < L * L; idx += kCholThreads) {
+            const int x = idx / L, y = idx - x * L;
+            double ri = 0.0;
+            if (x <= y && y < l) {
+                const double e = gt(x >> 4, y >> 4)[(x & 15) * kTileLd + (y & 15)] - (x == y ? 1.0 : 0.0);
+                ri = (x == y ? 1.0 : 0.0) - (x < y ? e : 0.5 * e);
+            }
+            Rinv[idx] = ri;
+        }
+        if (tid == 0) flags->orth_fail = 0;
+        return;
+    }
+    const bool nonfinite = s_nonfinite != 0;
+    double gmax = 0.0;
+    for (int j = 0; j < l; ++j) gmax = fmax(gmax, dg[j]);
+    const double rel = (mode == 0) ? 1e-12 : (mode == 1 ? 1e-2 : 0.0);
+    const bool inv = mode != 2;                 // R^{-1} wanted: the whole right half
+    double shift = 0.0;
+    bool broke = nonfinite;
+    for (int attempt = 0; attempt < (mode == 2 ? 5 : 1) && !nonfinite; ++attempt) {
+        if (attempt > 0) {                // the elimination overwrote G: reload it with the new shift
+            __syncthreads();
+            load(shift);
+        }
+        if (inv)
+            for (int idx = tid; idx < NTT * kTileSz; idx += kCholThreads) Mt[idx] = 0.0;
+        if (tid == 0) s_broke = 0;
+        __syncthreads();
+        // 1. Diagonal tile p in registers (wavefront 0), lane = column of [G_pp | I].
+        auto factor_diag = [&](int p) {
+            double* const T = gt(p, p);
+            const int c = lane & 15;
+            double x[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                x[r] = lane < 16 ? (r <= c ? T[r * kTileLd + c] : 0.0) : (lane < 32 && r == c ? 1.0 : 0.0);
+            // Straight-line elimination; the pivots are tested afterwards
+            // (a bad pivot only spoils the steps after it, which are then
+            // discarded), so no branch sits on the chain from one pivot
+            // to the next.
+            double dj[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                dj[j] = lane_bcast(x[j], j);                 // same value in every lane
+                x[j] *= rsqrt_nr(dj[j]);
+#pragma unroll
+                for (int i = j + 1; i < 16; ++i) x[i] = fma(-lane_bcast(x[j], i), x[j], x[i]);
+            }
+            bool bad = false;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int gj = 16 * p + j;
+                if (gj < l) bad |= !(dj[j] > rel * (dg[gj] + shift)) || !(dj[j] > 0.0) || !isfinite(dj[j]);
+            }
+            if (!bad) {
+                if (lane < 16) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) T[r * kTileLd + c] = r <= c ? x[r] : 0.0;
+                } else if (lane < 32) {
+                    double* const D = mt(p, p);
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) D[r * kTileLd + c] = x[r];
+                }
+            } else if (lane == 0) {
+                s_broke = 1;
+            }
+        };
+        if (wid == 0) factor_diag(0);
+        __syncthreads();
+        for (int p = 0; p < nt && !s_broke; ++p) {
+            // 2. Block row p times R_pp^{-T}: left tiles q > p, right tiles c < p.
+            const int nleft = nt - p - 1, nright = inv ? p : 0;
+            const double* const Dp = mt(p, p);
+            for (int jb = wid; jb < nleft + nright; jb += nw) {
+                double* const B = jb < nleft ? gt(p, p + 1 + jb) : mt(p, jb - nleft);
+                doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int st = 0; st < 4; ++st) {
+                    const int k = 4 * st + lk;
+                    acc = mfma16x16x4(Dp[li * kTileLd + k], B[k * kTileLd + li], acc);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) B[(lk + 4 * v) * kTileLd + li] = acc[v];
+            }
+            __syncthreads();
+            // 3. Trailing update of the later block rows.  Wavefront 0 takes
+            // the next diagonal tile (the first job) and factors it at once,
+            // while the others share the remaining jobs (look-ahead).
+            const int nq = nt - p - 1, nl = nq * (nq + 1) / 2, nr = inv ? nq * (p + 1) : 0;
+            for (int jb = wid == 0 ? 0 : wid; jb < (wid == 0 ? min(1, nl) : nl + nr); jb += nw - 1) {
+                const double* Aop;
+                const double* Bop;
+                double* C;
+                if (jb < nl) {
+                    int qq = 0, tt = jb;
+                    while (tt >= nq - qq) { tt -= nq - qq; ++qq; }
+                    const int q = p + 1 + qq, r = q + tt;
+                    Aop = gt(p, q);
+                    Bop = gt(p, r);
+                    C = gt(q, r);
+                } else {
+                    const int j2 = jb - nl, q = p + 1 + j2 / (p + 1), c = j2 % (p + 1);
+                    Aop = gt(p, q);
+                    Bop = mt(p, c);
+                    C = mt(q, c);
+                }
+                doublex4 acc;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[v] = C[(lk + 4 * v) * kTileLd + li];
+#pragma unroll
+                for (int st = 0; st < 4; ++st) {
+                    const int k = 4 * st + lk;
+                    acc = mfma16x16x4(-Aop[k * kTileLd + li], Bop[k * kTileLd + li], acc);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) C[(lk + 4 * v) * kTileLd + li] = acc[v];
+            }
+            if (wid == 0 && p + 1 < nt) factor_diag(p + 1);
+            __syncthreads();
+        }
+        broke = s_broke != 0;
+        if (!broke || mode != 2) break;
+        shift = (shift == 0.0) ? gmax * 0x1.0p-40 : shift * 1024.0;
+        if (!(shift > 0.0)) shift = 0x1.0p-1000;
+    }
+    if (!broke) {
+        for (int idx = tid; idx < L * L; idx += kCholThreads) {
+            const int x = idx / L, y = idx - x * L;
+            const bool in = x <= y && y < l;
+            if (mode == 2) R[idx] = in ? gt(x >> 4, y >> 4)[(x & 15) * kTileLd + (y & 15)] : 0.0;
+            else Rinv[idx] = in ? mt(y >> 4, x >> 4)[(y & 15) * kTileLd + (x & 15)] : 0.0;
+        }
+    }
+    if (tid == 0) {
+        if (mode == 2) {
+            *shift_out = shift;
+            if (shift > 0.0) atomicOr(&flags->info, RSVD_INFO_SHIFTED_CHOLESKY);
+            if (broke) atomicOr(&flags->info, RSVD_INFO_NONFINITE);
+        } else {
+            flags->orth_fail = broke ? 1 : 0;
+        }
+        if (nonfinite) atomicOr(&flags->info, RSVD_INFO_NONFINITE);
+    }
+}
+
 hipError_t launch_chol(const double* partials, int64_t rows, int l, int L, double* R, double* Rinv, DevFlags* flags,
                        int mode, double* shift_out, double* work, double tau, hipStream_t s) {
     const int nchunks = gram_chunks(rows);
-    if (l <= kCholLdsMax)
+    if (L <= 16 * kCholMfmaMaxNt)
+        hipLaunchKernelGGL(chol_mfma_kernel, dim3(1), dim3(kCholThreads), 0, s, partials, nchunks, l, L, R, Rinv, flags,
+                           mode, shift_out, tau);
+    else if (l <= kCholLdsMax)
         hipLaunchKernelGGL(chol_rl_kernel, dim3(1), dim3(kCholThreads), 0, s, partials, nchunks, l, L, R, Rinv, flags,
                            mode, shift_out, tau);
     else

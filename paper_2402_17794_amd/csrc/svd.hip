@@ -153,11 +153,20 @@ __device__ __forceinline__ void jacobi_rank(const double* nrm2, int* rank_of, in
 // its own output column.  Two barriers per two rounds; 7 wavefronts at l =
 // 110, one pair per group.
 //
+// The odd round has no branches: a group at either end of the row pairs its
+// column with itself through LDS with a zero inner product, which makes the
+// rotation the identity (t = 0) and the update y' = 0 * y + y.
+//
 // Columns carry scales (JColumn), so a rotation costs one FMA per element
 // and output; at the start of every sweep the scales are folded back in and
 // the norms recomputed exactly.  X is first scaled by a power of two so
 // that its largest column norm is about 1.  Sweeps stop when a whole sweep
-// rotates nothing.
+// rotates nothing, or earlier when a test of all pairs at a sweep start
+// finds none that would rotate: X^T X on FP64 MFMA (columns from the
+// exchange buffer) against the same threshold as the rotations.  The test
+// runs only after a sweep whose rotations all had |t| <= 2^-20, since with
+// the quadratic convergence of the last sweeps nothing earlier can pass it;
+// it saves the final sweep, which would rotate nothing.
 template <int R>
 __global__ __launch_bounds__(512) void jacobi_oe_kernel(const double* __restrict__ Rm, int l, int L,
                                                         const double* __restrict__ shift_p,
@@ -202,7 +211,11 @@ __global__ __launch_bounds__(512) void jacobi_oe_kernel(const double* __restrict
     c0.sc = c1.sc = ldexp(1.0, -ex);
     c0.isc = c1.isc = 1.0;
 
-    bool converged = (l < 2);
+    const int nwaves = (int)(blockDim.x / 64), wave = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+    // An end group pairs with itself: it reads back its own other column.
+    const int sr = hasR ? 0 : 1, gr = hasR ? gi + 1 : gi;
+    const int sl = hasL ? 1 : 0, gl = hasL ? gi - 1 : gi;
+    bool converged = (l < 2), small = false;
     for (int sweep = 0; sweep < kJacobiMaxSweeps && !converged; ++sweep) {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
@@ -215,11 +228,54 @@ __global__ __launch_bounds__(512) void jacobi_oe_kernel(const double* __restrict
             c0.nr = octet_sum(p0);
             c1.nr = octet_sum(p1);
         }
-        int rot = 0;
+        if (small) {
+            // Test of every pair of columns: G = X^T X, 16 x 16 tiles on and
+            // above the diagonal, against |g| <= tol sqrt(a b) with the norms
+            // of this sweep start.
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                xch[xidx(0, k, gi)] = x0[k];
+                xch[xidx(1, k, gi)] = x1[k];
+            }
+            if (e == 0) {
+                nrm2[2 * gi] = c0.nr;
+                nrm2[2 * gi + 1] = c1.nr;
+            }
+            __syncthreads();
+            const int ntc = (n2 + 15) / 16, ntiles = ntc * (ntc + 1) / 2;
+            int bad = 0;
+            for (int t = wave; t < ntiles; t += nwaves) {
+                int a = 0, b = t;
+                while (b >= ntc - a) { b -= ntc - a; ++a; }
+                b += a;
+                const int pa = 16 * a + li, pb = 16 * b + li;
+                doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int kk = 0; kk < LPP * R; kk += 4) {
+                    const int row = kk + lk;       // row = e' + 8 k'
+                    const int k = row / LPP, ee = row % LPP;
+                    const double av = xch[(((pa & 1) * R + k) * GMAX + (pa >> 1)) * LPP + ee];
+                    const double bv = xch[(((pb & 1) * R + k) * GMAX + (pb >> 1)) * LPP + ee];
+                    acc = mfma16x16x4(av, bv, acc);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = 16 * a + acc_row<double>(lk, v), j = pb;
+                    if (i < j && j < n2) bad |= (int)(acc[v] * acc[v] > (kJacobiTol * kJacobiTol) * (nrm2[i] * nrm2[j]));
+                }
+            }
+            if (!__syncthreads_or(bad)) {
+                converged = true;
+                break;
+            }
+        }
+        int rot = 0, big = 0;
         for (int h = 0; h < G; ++h) {
             {   // even round: pair (2g, 2g + 1); position 2g takes the rotated second column
                 const double g = octet_sum(partial_dot<R>(x0, x1)) * (c0.sc * c1.sc);
-                const JRot o = jacobi_rot(c0, c1, g, jacobi_tan(c0.nr, c1.nr, g, rot));
+                const double t = jacobi_tan(c0.nr, c1.nr, g, rot);
+                big |= (int)(fabs(t) > 0x1.0p-20);
+                const JRot o = jacobi_rot(c0, c1, g, t);
 #pragma unroll
                 for (int k = 0; k < R; ++k) {
                     const double yi = x0[k], yj = x1[k];
@@ -230,46 +286,44 @@ __global__ __launch_bounds__(512) void jacobi_oe_kernel(const double* __restrict
                 c1 = o.ci;
             }
             // odd round: pairs (2g + 1, 2g + 2) across neighbouring groups
-            if (active) {
 #pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    xch[xidx(0, k, gi)] = x0[k];
-                    xch[xidx(1, k, gi)] = x1[k];
-                }
-                if (e == 0) {
-                    xcol[0][gi] = c0;
-                    xcol[1][gi] = c1;
-                }
+            for (int k = 0; k < R; ++k) {
+                xch[xidx(0, k, gi)] = x0[k];
+                xch[xidx(1, k, gi)] = x1[k];
+            }
+            if (e == 0) {
+                xcol[0][gi] = c0;
+                xcol[1][gi] = c1;
             }
             __syncthreads();
-            const int gr = hasR ? gi + 1 : gi, gl = hasL ? gi - 1 : gi;
             double yr[R], yl[R];
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                yr[k] = xch[xidx(0, k, gr)];
-                yl[k] = xch[xidx(1, k, gl)];
+                yr[k] = xch[xidx(sr, k, gr)];
+                yl[k] = xch[xidx(sl, k, gl)];
             }
-            JColumn cr = xcol[0][gr], cl = xcol[1][gl];
+            const JColumn cr = xcol[sr][gr], cl = xcol[sl][gl];
             __syncthreads();
             const double pr = partial_dot<R>(x1, yr), pl = partial_dot<R>(yl, x0);
             const double gR = hasR ? octet_sum(pr) * (c1.sc * cr.sc) : 0.0;
             const double gL = hasL ? octet_sum(pl) * (cl.sc * c0.sc) : 0.0;
-            if (!hasR) cr = {0.0, 1.0, 1.0, 0};
-            if (!hasL) cl = {0.0, 1.0, 1.0, 0};
-            const JRot oR = jacobi_rot(c1, cr, gR, jacobi_tan(c1.nr, cr.nr, gR, rot));
-            const JRot oL = jacobi_rot(cl, c0, gL, jacobi_tan(cl.nr, c0.nr, gL, rot));
-            if (hasR) {       // position 2g + 1 takes the rotated right neighbour
+            const double tR = jacobi_tan(c1.nr, cr.nr, gR, rot);
+            const double tL = jacobi_tan(cl.nr, c0.nr, gL, rot);
+            big |= (int)(fmax(fabs(tR), fabs(tL)) > 0x1.0p-20);
+            const JRot oR = jacobi_rot(c1, cr, gR, tR);
+            const JRot oL = jacobi_rot(cl, c0, gL, tL);
+            // Position 2g + 1 takes the rotated right neighbour, position 2g
+            // the rotated left one (at an end: the column itself, t = 0).
 #pragma unroll
-                for (int k = 0; k < R; ++k) x1[k] = fma(oR.tir, x1[k], yr[k]);
-                c1 = oR.cj;
+            for (int k = 0; k < R; ++k) {
+                x1[k] = fma(oR.tir, x1[k], yr[k]);
+                x0[k] = fma(-oL.tr, x0[k], yl[k]);
             }
-            if (hasL) {       // position 2g takes the rotated left neighbour
-#pragma unroll
-                for (int k = 0; k < R; ++k) x0[k] = fma(-oL.tr, x0[k], yl[k]);
-                c0 = oL.ci;
-            }
+            c1 = oR.cj;
+            c0 = oL.ci;
         }
         converged = !__syncthreads_or(rot);
+        small = !__syncthreads_or(big);
     }
     if (!converged && tid == 0) atomicOr(&flags->info, RSVD_INFO_JACOBI_NOT_CONVERGED);
 
