@@ -112,7 +112,9 @@ hipError_t launch_householder(int dtype, const void* Y, int64_t ldy, int64_t row
 // One-sided Jacobi on X = R^T (l x l, from the Cholesky factor of B B^T).
 // Outputs sigma (sorted descending, shift removed), Ut (L x L, column c =
 // left singular vector c of B, sorted), Mv (L x L: Ut * diag(1/sigma)),
-// work: kMaxL * kMaxL doubles (used when l is too large for LDS).
+// work: kJacobiWorkDoubles doubles of device scratch (used when l > 128).
+constexpr int kJacobiBlockSweeps = 30;                   // sweep cap of the l > 128 form
+constexpr size_t kJacobiWorkDoubles = (size_t)kMaxL * kMaxL + kJacobiBlockSweeps + 8;
 hipError_t launch_jacobi(const double* R, int l, int L, const double* shift, double* sigma, double* Ut,
                          double* Mv, DevFlags* flags, double* work, hipStream_t s);
 

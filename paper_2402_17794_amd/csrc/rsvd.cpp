@@ -124,7 +124,7 @@ bool make_plan(int adtype, int64_t m, int64_t n, int64_t k, int64_t p, int64_t q
     P.amax_idx = c.take(sizeof(int) * (size_t)apply_blocks(n) * P.L);
     P.H = c.take(sizeof(double) * (size_t)mx * P.L);
     P.Qw = c.take(sizeof(double) * (size_t)mx * P.L);
-    P.work = c.take(sizeof(double) * (size_t)kMaxL * kMaxL);
+    P.work = c.take(sizeof(double) * kJacobiWorkDoubles);
     P.res_part = c.take(sizeof(double) * residual_partials(m, n));
     P.res = c.take(sizeof(double) * 2);
     if (is_lowp(adtype)) {

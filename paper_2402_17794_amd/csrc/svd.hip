@@ -11,7 +11,8 @@
 // V = B^T U~ Sigma^{-1}.  Neither the rotations nor R^{-1} are needed.
 //
 // l <= 128: jacobi_oe_kernel, X held in registers (see its comment).
-// l  > 128: jacobi_kernel, X in global memory, one barrier per round.
+// l  > 128: the block form (jacobi_blk_*), block pairs of 16 + 16 columns in
+//           registers, one launch per round of block pairs.
 #include <math.h>
 
 #include <algorithm>
@@ -33,19 +34,6 @@ __device__ __forceinline__ double octet_sum(double x) {
     x += dpp_f64<dpp_quad_xor2>(x);
     x += dpp_f64<dpp_half_mirror>(x);
     return x;
-}
-
-// Sum over the 4 lanes of each quad (xor 1, then xor 2), result in all 4.
-__device__ __forceinline__ double quad_sum(double x) {
-    x += dpp_f64<dpp_quad_xor1>(x);
-    x += dpp_f64<dpp_quad_xor2>(x);
-    return x;
-}
-
-template <int LPP>
-__device__ __forceinline__ double group_sum(double x) {
-    static_assert(LPP == 4 || LPP == 8, "lanes per pair");
-    return LPP == 4 ? quad_sum(x) : octet_sum(x);
 }
 
 // Reciprocal and reciprocal square root: the hardware estimates refined by
@@ -379,109 +367,188 @@ __device__ __forceinline__ void rr_pair(int r, int s, int n2, int& p1, int& p2) 
     p2 = r - s + m; if (p2 >= m) p2 -= m;
 }
 
-// One-sided Jacobi for l > 128 with X = R^T in global memory (work, column
-// stride kMaxL), LPP lanes per column pair, one barrier per round of the
-// round-robin ordering.  Zero rows past l stay zero under rotations, so every
-// lane loads and stores its rows 2e, 2e+1, 2e+2 LPP, 2e+2 LPP+1, ... as
-// 16-byte pairs without bounds checks.  NP = row pairs per lane.
-template <int NP, int NT, int LPP>
-__global__ __launch_bounds__(NT) void jacobi_kernel(const double* __restrict__ R, int l, int L,
-                                                      const double* __restrict__ shift_p, double* __restrict__ sigma,
-                                                      double* __restrict__ Ut, double* __restrict__ Mv,
-                                                      DevFlags* flags, double* __restrict__ work) {
-    __shared__ int rotated;
+// ------------------------------------------------ block form, l > 128 --
+// X = R^T (l x l) does not fit on one CU, and the single-workgroup form
+// above streams all of X through that CU's cache every round.  This form
+// splits the columns into blocks of 16 (a zero block is added when their
+// number is odd) and orders the block pairs round-robin: a round is one
+// launch in which every workgroup takes one pair of blocks, loads its 32
+// columns into registers (16 lanes per column pair, rows e + 16 k), runs one
+// odd-even transposition sweep over them (every pair of the 32 columns meets
+// once, exactly as in jacobi_oe_kernel) and writes them back.  The launches
+// of a sweep together meet every pair of columns at least once; the kernel
+// boundaries order the rounds, so no workgroup waits for another.  A word per
+// sweep records whether any pair rotated; the launches of a sweep return at
+// once when the previous sweep rotated nothing.  X is kept with column
+// stride kMaxL; rows >= l are zero and stay zero.
+constexpr int kBlkLpp = 16;
+constexpr int kBlkGroups = 16;                 // 32 columns per workgroup
+
+// X = 2^-ex R^T (zero padded), ex from the largest column norm; the sweep
+// words cleared; 2^{2 ex} stored after the sweep words.
+__global__ __launch_bounds__(1024) void jacobi_blk_prep_kernel(const double* __restrict__ R, int l, int L,
+                                                               double* __restrict__ work) {
+    __shared__ double red[16];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    double* X = work;
+    int* rotw = reinterpret_cast<int*>(work + (size_t)kMaxL * kMaxL);
+    double mx = 0.0;
+    for (int c = wid; c < l; c += 16) {           // wavefront per column
+        double s2 = 0.0;
+        for (int r = lane; r < l; r += 64) s2 = fma(R[(int64_t)c * L + r], R[(int64_t)c * L + r], s2);
+        mx = fmax(mx, wave_sum(s2));
+    }
+    if (lane == 0) red[wid] = mx;
+    __syncthreads();
+    mx = 0.0;
+    for (int w = 0; w < 16; ++w) mx = fmax(mx, red[w]);
+    const int ex = mx > 0.0 ? ilogb(mx) / 2 : 0;
+    const double sc = ldexp(1.0, -ex);
+    for (int idx = tid; idx < kMaxL * kMaxL; idx += 1024) {
+        const int c = idx / kMaxL, r = idx - c * kMaxL;
+        X[idx] = (c < l && r < l) ? R[(int64_t)c * L + r] * sc : 0.0;
+    }
+    for (int i = tid; i < kJacobiBlockSweeps; i += 1024) rotw[i] = 0;
+    if (tid == 0) work[(size_t)kMaxL * kMaxL + kJacobiBlockSweeps / 2 + 2] = ldexp(1.0, 2 * ex);
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlkLpp * kBlkGroups) void jacobi_blk_pair_kernel(double* __restrict__ work, int nb2,
+                                                                                int round, int sweep) {
+    constexpr int LPP = kBlkLpp, G = kBlkGroups;
+    __shared__ double xch[2 * R * G * LPP];          // [side][k][group][lane]
+    __shared__ JColumn xcol[2][G];
+    double* X = work;
+    int* rotw = reinterpret_cast<int*>(work + (size_t)kMaxL * kMaxL);
+    if (sweep > 0 && rotw[sweep - 1] == 0) return;   // the previous sweep rotated nothing
+    const int tid = threadIdx.x, gi = tid / LPP, e = tid % LPP;
+    auto xidx = [&](int side, int k, int g) { return ((side * R + k) * G + g) * LPP + e; };
+    int p1, p2;
+    rr_pair(round, blockIdx.x, nb2, p1, p2);
+    const int b0 = min(p1, p2), b1 = max(p1, p2);
+    auto colof = [&](int pos) { return pos < 16 ? 16 * b0 + pos : 16 * b1 + pos - 16; };
+    double x0[R], x1[R];
+    JColumn c0, c1;
+    c0.id = colof(2 * gi);
+    c1.id = colof(2 * gi + 1);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        x0[k] = X[(int64_t)c0.id * kMaxL + e + LPP * k];
+        x1[k] = X[(int64_t)c1.id * kMaxL + e + LPP * k];
+    }
+    c0.sc = c1.sc = c0.isc = c1.isc = 1.0;
+    c0.nr = quarter_sum(partial_dot<R>(x0, x0));
+    c1.nr = quarter_sum(partial_dot<R>(x1, x1));
+    const bool hasR = gi < G - 1, hasL = gi > 0;
+    const int sr = hasR ? 0 : 1, gr = hasR ? gi + 1 : gi;
+    const int sl = hasL ? 1 : 0, gl = hasL ? gi - 1 : gi;
+    int rot = 0;
+    for (int h = 0; h < G; ++h) {
+        {   // even round: pair (2g, 2g + 1); position 2g takes the rotated second column
+            const double g = quarter_sum(partial_dot<R>(x0, x1)) * (c0.sc * c1.sc);
+            const double t = jacobi_tan(c0.nr, c1.nr, g, rot);
+            const JRot o = jacobi_rot(c0, c1, g, t);
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const double yi = x0[k], yj = x1[k];
+                x0[k] = fma(o.tir, yi, yj);
+                x1[k] = fma(-o.tr, yj, yi);
+            }
+            c0 = o.cj;
+            c1 = o.ci;
+        }
+        // odd round: pairs (2g + 1, 2g + 2) across neighbouring groups (an end
+        // group pairs with itself, t = 0)
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            xch[xidx(0, k, gi)] = x0[k];
+            xch[xidx(1, k, gi)] = x1[k];
+        }
+        if (e == 0) {
+            xcol[0][gi] = c0;
+            xcol[1][gi] = c1;
+        }
+        __syncthreads();
+        double yr[R], yl[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            yr[k] = xch[xidx(sr, k, gr)];
+            yl[k] = xch[xidx(sl, k, gl)];
+        }
+        const JColumn cr = xcol[sr][gr], cl = xcol[sl][gl];
+        __syncthreads();
+        const double pr = partial_dot<R>(x1, yr), pl = partial_dot<R>(yl, x0);
+        const double gR = hasR ? quarter_sum(pr) * (c1.sc * cr.sc) : 0.0;
+        const double gL = hasL ? quarter_sum(pl) * (cl.sc * c0.sc) : 0.0;
+        const double tR = jacobi_tan(c1.nr, cr.nr, gR, rot);
+        const double tL = jacobi_tan(cl.nr, c0.nr, gL, rot);
+        const JRot oR = jacobi_rot(c1, cr, gR, tR);
+        const JRot oL = jacobi_rot(cl, c0, gL, tL);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            x1[k] = fma(oR.tir, x1[k], yr[k]);
+            x0[k] = fma(-oL.tr, x0[k], yl[k]);
+        }
+        c1 = oR.cj;
+        c0 = oL.ci;
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        X[(int64_t)c0.id * kMaxL + e + LPP * k] = x0[k] * c0.sc;
+        X[(int64_t)c1.id * kMaxL + e + LPP * k] = x1[k] * c1.sc;
+    }
+    if (__syncthreads_or(rot) && tid == 0) atomicOr(&rotw[sweep], 1);
+}
+
+// Column norms of the final X, sorted singular values, U~ and M = U~ Sigma^-1
+// (as at the end of the other forms); the sweep cap flag.
+__global__ __launch_bounds__(512) void jacobi_blk_finish_kernel(const double* __restrict__ work, int l, int L,
+                                                                const double* __restrict__ shift_p,
+                                                                double* __restrict__ sigma, double* __restrict__ Ut,
+                                                                double* __restrict__ Mv, DevFlags* flags) {
     __shared__ double nrm2[kMaxL];
     __shared__ int rank_of[kMaxL];
-    const int ld = kMaxL;
-    double* X = work;                               // X[c * ld + r] = R[c][r], zero for r >= l
-    const int tid = threadIdx.x, grp = tid / LPP, e = tid % LPP;
-    static_assert(2 * NP * LPP <= kMaxL, "rows per column");
-
-    for (int idx = tid; idx < l * ld; idx += NT) {
-        const int c = idx / ld, r = idx - c * ld;
-        X[idx] = r < l ? R[(int64_t)c * L + r] : 0.0;
-    }
-    const int n2 = l + (l & 1);
-    bool converged = (l < 2);
-    __syncthreads();
-    for (int sweep = 0; sweep < kJacobiMaxSweeps && !converged; ++sweep) {
-        if (tid == 0) rotated = 0;
-        __syncthreads();
-        for (int r = 0; r < n2 - 1; ++r) {
-            for (int s = grp; s < n2 / 2; s += NT / LPP) {
-                int p1, p2;
-                rr_pair(r, s, n2, p1, p2);
-                if (p1 >= l || p2 >= l) continue;
-                const int i = min(p1, p2), j = max(p1, p2);
-                double2* xi_p = reinterpret_cast<double2*>(X + i * ld) + e;
-                double2* xj_p = reinterpret_cast<double2*>(X + j * ld) + e;
-                double2 xi[NP], xj[NP];
-                double a = 0.0, b = 0.0, g = 0.0;
-#pragma unroll
-                for (int t = 0; t < NP; ++t) {
-                    xi[t] = xi_p[LPP * t];
-                    xj[t] = xj_p[LPP * t];
-                }
-#pragma unroll
-                for (int t = 0; t < NP; ++t) {
-                    a = fma(xi[t].x, xi[t].x, a); a = fma(xi[t].y, xi[t].y, a);
-                    b = fma(xj[t].x, xj[t].x, b); b = fma(xj[t].y, xj[t].y, b);
-                    g = fma(xi[t].x, xj[t].x, g); g = fma(xi[t].y, xj[t].y, g);
-                }
-                a = group_sum<LPP>(a);
-                b = group_sum<LPP>(b);
-                g = group_sum<LPP>(g);
-                if (fabs(g) > kJacobiTol * sqrt(a * b)) {
-                    const double zeta = (b - a) / (2.0 * g);
-                    const double az = fabs(zeta);
-                    double t = az > 1e150 ? 0.5 / az : 1.0 / (az + sqrt(1.0 + az * az));
-                    t = zeta >= 0.0 ? t : -t;
-                    const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
-#pragma unroll
-                    for (int u = 0; u < NP; ++u) {
-                        double2 ni, nj;
-                        ni.x = c * xi[u].x - sn * xj[u].x;
-                        ni.y = c * xi[u].y - sn * xj[u].y;
-                        nj.x = sn * xi[u].x + c * xj[u].x;
-                        nj.y = sn * xi[u].y + c * xj[u].y;
-                        xi_p[LPP * u] = ni;
-                        xj_p[LPP * u] = nj;
-                    }
-                    if (e == 0) rotated = 1;
-                }
-            }
-            __syncthreads();
-        }
-        const int any = rotated;
-        __syncthreads();
-        converged = (any == 0);
-    }
-    if (!converged && tid == 0) atomicOr(&flags->info, RSVD_INFO_JACOBI_NOT_CONVERGED);
-
-    for (int c = grp; c < l; c += NT / LPP) {
+    const double* X = work;
+    const int* rotw = reinterpret_cast<const int*>(work + (size_t)kMaxL * kMaxL);
+    const double sc4 = work[(size_t)kMaxL * kMaxL + kJacobiBlockSweeps / 2 + 2];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    if (tid == 0 && rotw[kJacobiBlockSweeps - 1] != 0) atomicOr(&flags->info, RSVD_INFO_JACOBI_NOT_CONVERGED);
+    for (int c = wid; c < l; c += 8) {
         double s2 = 0.0;
-        for (int row = e; row < l; row += LPP) s2 = fma(X[c * ld + row], X[c * ld + row], s2);
-        s2 = group_sum<LPP>(s2);
-        if (e == 0) nrm2[c] = s2;
+        for (int r = lane; r < l; r += 64) s2 = fma(X[(int64_t)c * kMaxL + r], X[(int64_t)c * kMaxL + r], s2);
+        s2 = wave_sum(s2);
+        if (lane == 0) nrm2[c] = s2;
     }
     __syncthreads();
     const double shift = *shift_p;
-    jacobi_rank(nrm2, rank_of, l, 1.0, shift, sigma);
+    jacobi_rank(nrm2, rank_of, l, sc4, shift, sigma);
     __syncthreads();
-    for (int idx = tid; idx < L * L; idx += NT) {
+    for (int idx = tid; idx < L * L; idx += 512) {
         Ut[idx] = 0.0;
         Mv[idx] = 0.0;
     }
     __syncthreads();
-    for (int idx = tid; idx < l * l; idx += NT) {
+    for (int idx = tid; idx < l * l; idx += 512) {
         const int c = idx / l, row = idx - c * l;
         const double nc = sqrt(nrm2[c]);
-        const double sc = sqrt(fmax(nrm2[c] - shift, 0.0));
-        const double u = nc > 0.0 ? X[c * ld + row] / nc : (row == c ? 1.0 : 0.0);
+        const double sv = sqrt(fmax(nrm2[c] * sc4 - shift, 0.0));
+        const double u = nc > 0.0 ? X[(int64_t)c * kMaxL + row] / nc : (row == c ? 1.0 : 0.0);
         const int col = rank_of[c];
         Ut[(int64_t)row * L + col] = u;
-        Mv[(int64_t)row * L + col] = sc > 0.0 ? u / sc : 0.0;
+        Mv[(int64_t)row * L + col] = sv > 0.0 ? u / sv : 0.0;
     }
+}
+
+template <int R>
+static void launch_jacobi_blk(const double* Rm, int l, int L, const double* shift, double* sigma, double* Ut,
+                              double* Mv, DevFlags* flags, double* work, hipStream_t s) {
+    const int nb = (l + 15) / 16, nb2 = nb + (nb & 1);
+    hipLaunchKernelGGL(jacobi_blk_prep_kernel, dim3(1), dim3(1024), 0, s, Rm, l, L, work);
+    for (int sweep = 0; sweep < kJacobiBlockSweeps; ++sweep)
+        for (int r = 0; r < nb2 - 1; ++r)
+            hipLaunchKernelGGL(jacobi_blk_pair_kernel<R>, dim3(nb2 / 2), dim3(kBlkLpp * kBlkGroups), 0, s, work, nb2,
+                               r, sweep);
+    hipLaunchKernelGGL(jacobi_blk_finish_kernel, dim3(1), dim3(512), 0, s, work, l, L, shift, sigma, Ut, Mv, flags);
 }
 
 template <int R>
@@ -508,9 +575,19 @@ hipError_t launch_jacobi(const double* R, int l, int L, const double* shift, dou
             default: launch_jacobi_oe<16>(R, l, L, shift, sigma, Ut, Mv, flags, s); break;
         }
     } else {
-        // 36 register pairs per lane: 512 threads leave 256 VGPRs per lane.
-        hipLaunchKernelGGL((jacobi_kernel<kMaxL / 16, 512, 8>), dim3(1), dim3(512), 0, s, R, l, L, shift, sigma, Ut,
-                           Mv, flags, work);
+        // rows per lane and column: ceil(l / 16), 16 lanes per column pair
+        switch ((l + 15) / 16) {
+            case 9: launch_jacobi_blk<9>(R, l, L, shift, sigma, Ut, Mv, flags, work, s); break;
+            case 10: launch_jacobi_blk<10>(R, l, L, shift, sigma, Ut, Mv, flags, work, s); break;
+            case 11: launch_jacobi_blk<11>(R, l, L, shift, sigma, Ut, Mv, flags, work, s); break;
+            case 12: launch_jacobi_blk<12>(R, l, L, shift, sigma, Ut, Mv, flags, work, s); break;
+            case 13: launch_jacobi_blk<13>(R, l, L, shift, sigma, Ut, Mv, flags, work, s); break;
+            case 14: launch_jacobi_blk<14>(R, l, L, shift, sigma, Ut, Mv, flags, work, s); break;
+            case 15: launch_jacobi_blk<15>(R, l, L, shift, sigma, Ut, Mv, flags, work, s); break;
+            case 16: launch_jacobi_blk<16>(R, l, L, shift, sigma, Ut, Mv, flags, work, s); break;
+            case 17: launch_jacobi_blk<17>(R, l, L, shift, sigma, Ut, Mv, flags, work, s); break;
+            default: launch_jacobi_blk<18>(R, l, L, shift, sigma, Ut, Mv, flags, work, s); break;
+        }
     }
     return hipGetLastError();
 }
