@@ -126,8 +126,9 @@ constexpr int kCholLdsMax = 128;
 // Form for 128 < l <= kMaxL: blocked right-looking Cholesky, panels of 16,
 // one workgroup of 16 wavefronts, the working matrix A (L x L, upper block
 // triangle) in global memory, where it stays in the L2 cache.  Per panel p:
-//   1. wavefront 0 factors the diagonal block A_pp = R_pp^T R_pp in LDS (16
-//      pivot steps inside one wavefront, no workgroup barrier) and inverts it;
+//   1. wavefront 0 factors the diagonal block A_pp = R_pp^T R_pp in registers
+//      (16 pivot steps inside one wavefront, no workgroup barrier) and gets
+//      R_pp^{-1} from the same row operations on an identity;
 //   2. R_pq = R_pp^{-T} A_pq for the tiles right of it (FP64 MFMA);
 //   3. A_qr -= R_pq^T R_pr for p < q <= r (FP64 MFMA, R_p. from LDS).
 // Three barriers per panel.  R^{-1} (modes 0, 1) then comes from the block
@@ -139,13 +140,27 @@ constexpr int kCholLdsMax = 128;
 constexpr int kCholBlkNt = kMaxL / 16;
 constexpr int kCholBlkLd = kMaxL + 4;          // LDS panel row stride (doubles)
 
-__device__ __forceinline__ void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
+__device__ __forceinline__ double lane_bcast(double x, int src) {      // x of lane `src` (uniform), in every lane
+    const int2 v = __builtin_bit_cast(int2, x);
+    int2 r;
+    r.x = __builtin_amdgcn_readlane(v.x, src);
+    r.y = __builtin_amdgcn_readlane(v.y, src);
+    return __builtin_bit_cast(double, r);
+}
+
+// 1 / sqrt(x) for a positive normal x: the hardware estimate and two Newton
+// steps (each squares the relative error), about one ulp.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) y = fma(0.5 * y, fma(-(x * y), y, 1.0), y);
+    return y;
+}
 
 __global__ __launch_bounds__(1024) void chol_blk_kernel(const double* __restrict__ part, int nchunks, int l, int L,
                                                         double* __restrict__ R, double* __restrict__ Rinv,
                                                         DevFlags* flags, int mode, double* shift_out,
                                                         double* __restrict__ A, double tau) {
-    __shared__ double T[16 * 17];                   // diagonal block being factored
     __shared__ double Dinv[kCholBlkNt][256];        // R_pp^{-1} of every diagonal block (row-major 16 x 16)
     __shared__ double Prow[16 * kCholBlkLd];        // the current panel rows R_p. (16 x L)
     __shared__ double dg[kMaxL];
@@ -156,31 +171,48 @@ __global__ __launch_bounds__(1024) void chol_blk_kernel(const double* __restrict
     const int nt = L / 16, npairs = nt * (nt + 1) / 2, stride = npairs * 256;
     const int li = lane & 15, lk = lane >> 4;       // MFMA operand coordinates
 
-    // A = upper block triangle of G (+ shift on the leading diagonal), identity padding.
+    // A = upper block triangle of G (+ shift on the leading diagonal), identity
+    // padding.  Chunk partials summed in chunk order; addresses are clamped so
+    // that every load is unconditional and the 16 loads of a batch are in
+    // flight together.
     auto load = [&](double shift) {
         double emax = 0.0;
         bool nf = false;
-        for (int idx = tid; idx < stride; idx += 1024) {
-            const int pr = idx >> 8, e = idx & 255;
-            int ta = 0, pp = pr;
-            while (pp >= nt - ta) { pp -= nt - ta; ++ta; }
-            const int row = ta * 16 + (e >> 4), col = (ta + pp) * 16 + (e & 15);
-            double v;
-            if (row < l && col < l) {
-                double sum = 0.0;
-                for (int c = 0; c < nchunks; ++c) sum += part[(size_t)c * stride + idx];
-                if (row == col) {
-                    dg[row] = sum;
-                    if (!isfinite(sum)) nf = true;
+        for (int i0 = tid; i0 < stride; i0 += 2 * 1024) {
+            double x[2][8];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const int idx = min(i0 + u * 1024, stride - 1), cc = min(c, nchunks - 1);
+                    x[u][c] = part[(size_t)cc * stride + idx];
                 }
-                double ee = fabs(sum - (row == col ? 1.0 : 0.0));
-                if (!(ee < 1e300)) ee = 1e300;
-                if (row <= col) emax = fmax(emax, ee);
-                v = sum + (row == col ? shift : 0.0);
-            } else {
-                v = row == col ? 1.0 : 0.0;
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int idx = i0 + u * 1024;
+                if (idx >= stride) break;
+                const int pr = idx >> 8, e = idx & 255;
+                int ta = 0, pp = pr;
+                while (pp >= nt - ta) { pp -= nt - ta; ++ta; }
+                const int row = ta * 16 + (e >> 4), col = (ta + pp) * 16 + (e & 15);
+                double v;
+                if (row < l && col < l) {
+                    double sum = 0.0;
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) sum += c < nchunks ? x[u][c] : 0.0;
+                    if (row == col) {
+                        dg[row] = sum;
+                        if (!isfinite(sum)) nf = true;
+                    }
+                    double ee = fabs(sum - (row == col ? 1.0 : 0.0));
+                    if (!(ee < 1e300)) ee = 1e300;
+                    if (row <= col) emax = fmax(emax, ee);
+                    v = sum + (row == col ? shift : 0.0);
+                } else {
+                    v = row == col ? 1.0 : 0.0;
+                }
+                A[(size_t)row * L + col] = v;
             }
-            A[(size_t)row * L + col] = v;
         }
         if (nf) s_nonfinite = 1;
         return emax;
@@ -221,59 +253,37 @@ __global__ __launch_bounds__(1024) void chol_blk_kernel(const double* __restrict
         for (int p = 0; p < nt; ++p) {
             const int j0 = 16 * p;
             if (wid == 0) {
-                // 1. Diagonal block: lane owns row i, columns kq..kq+3 of T.
-                const int i = lane >> 2, kq = (lane & 3) * 4;
+                // 1. Diagonal block in registers, lane = column of [A_pp | I]:
+                // pivot j scales row j by d_j^{-1/2} and subtracts R_pp[j][i]
+                // times it from every row i > j, the row entries broadcast by
+                // lane reads; the identity half becomes R_pp^{-T}.  The pivots
+                // are tested afterwards (a bad pivot only spoils later steps).
+                const int c = lane & 15;
+                double x[16];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int k = kq + u;
-                    T[i * 17 + k] = k >= i ? A[(size_t)(j0 + i) * L + j0 + k] : A[(size_t)(j0 + k) * L + j0 + i];
-                }
-                wave_fence();
-                bool bad = false;
+                for (int r = 0; r < 16; ++r)
+                    x[r] = lane < 16 ? (r <= c ? A[(size_t)(j0 + r) * L + j0 + c] : 0.0)
+                                     : (lane < 32 && r == c ? 1.0 : 0.0);
+                double dj[16];
+#pragma unroll
                 for (int j = 0; j < 16; ++j) {
-                    const double d = T[j * 17 + j];
-                    if (j0 + j < l && (!(d > rel * (dg[j0 + j] + shift)) || !(d > 0.0) || !isfinite(d))) {
-                        bad = true;       // same d in every lane
-                        break;
-                    }
-                    const double rinv = 1.0 / sqrt(d);
-                    if (i == j) {
+                    dj[j] = lane_bcast(x[j], j);
+                    x[j] *= rsqrt_nr(dj[j]);
 #pragma unroll
-                        for (int u = 0; u < 4; ++u)
-                            if (kq + u >= j) T[j * 17 + kq + u] *= rinv;
-                    }
-                    wave_fence();
-                    if (i > j) {
-                        const double rji = T[j * 17 + i];
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const int k = kq + u;
-                            if (k >= i) T[i * 17 + k] -= rji * T[j * 17 + k];
-                        }
-                    }
-                    wave_fence();
+                    for (int i = j + 1; i < 16; ++i) x[i] = fma(-lane_bcast(x[j], i), x[j], x[i]);
                 }
+                bool bad = false;
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    if (j0 + j < l) bad |= !(dj[j] > rel * (dg[j0 + j] + shift)) || !(dj[j] > 0.0) || !isfinite(dj[j]);
                 if (!bad) {
-                    // R_pp^{-1}: lane c < 16 forms column c, rows 15 down to 0.
-                    if (lane < 16) {
-                        const int c = lane;
-                        double x[16];
+                    if (lane < 16) {        // R_pp (upper) back into A for the mode-2 output
 #pragma unroll
-                        for (int r = 15; r >= 0; --r) {
-                            double sacc = (r == c) ? 1.0 : 0.0;
+                        for (int r = 0; r < 16; ++r)
+                            if (r <= c) A[(size_t)(j0 + r) * L + j0 + c] = x[r];
+                    } else if (lane < 32) { // R_pp^{-1}, row-major: column c of R_pp^{-T} is its row c
 #pragma unroll
-                            for (int k = r + 1; k < 16; ++k)
-                                if (k <= c) sacc -= T[r * 17 + k] * x[k];
-                            x[r] = r <= c ? sacc / T[r * 17 + r] : 0.0;
-                        }
-#pragma unroll
-                        for (int r = 0; r < 16; ++r) Dinv[p][r * 16 + c] = x[r];
-                    }
-                    // R_pp (upper) back into A for the mode-2 output.
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int k = kq + u;
-                        if (k >= i) A[(size_t)(j0 + i) * L + j0 + k] = T[i * 17 + k];
+                        for (int r = 0; r < 16; ++r) Dinv[p][c * 16 + r] = x[r];
                     }
                 } else if (lane == 0) {
                     s_broke = 1;
@@ -614,23 +624,6 @@ __global__ __launch_bounds__(kCholThreads) void chol_rl_kernel(const double* __r
 constexpr int kCholMfmaMaxNt = 7;
 constexpr int kTileLd = 17;                    // LDS row stride of a tile (odd: conflict-free operand reads)
 constexpr int kTileSz = 16 * kTileLd;
-
-__device__ __forceinline__ double lane_bcast(double x, int src) {      // x of lane `src` (uniform), in every lane
-    const int2 v = __builtin_bit_cast(int2, x);
-    int2 r;
-    r.x = __builtin_amdgcn_readlane(v.x, src);
-    r.y = __builtin_amdgcn_readlane(v.y, src);
-    return __builtin_bit_cast(double, r);
-}
-
-// 1 / sqrt(x) for a positive normal x: the hardware estimate and two Newton
-// steps (each squares the relative error), about one ulp.
-__device__ __forceinline__ double rsqrt_nr(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-#pragma unroll
-    for (int i = 0; i < 2; ++i) y = fma(0.5 * y, fma(-(x * y), y, 1.0), y);
-    return y;
-}
 
 __global__ __launch_bounds__(kCholThreads) void chol_mfma_kernel(const double* __restrict__ part, int nchunks, int l,
                                                                  int L, double* __restrict__ R,
