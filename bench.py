@@ -87,6 +87,7 @@ def bench_lowp(args, cfg, A, torch, rsvd, workloads):
             tot, cnt = rsvd.profile_read(dev, kind)
             if cnt:
                 kinds[kind] = (tot, cnt)
+        st1_tot, st1_cnt = rsvd.profile_read(dev, rsvd.PROFILE_STAGE1)
         lp_kinds = [kk for kk in kinds if kk != 4]
         dom = max(lp_kinds, key=lambda kk: kinds[kk][0])
         dom_ms = kinds[dom][0] / kinds[dom][1]
@@ -107,6 +108,7 @@ def bench_lowp(args, cfg, A, torch, rsvd, workloads):
         forms[name] = {"solves_per_s": args.steps / dt, "ms_per_step": dt / args.steps * 1e3,
                        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                        "power_iterations": q + (0 if name == "f32" else 1), "info": int(solver.info.item()),
+                       "range_finder_ms": st1_tot / max(1, st1_cnt),
                        "S": solver.S.cpu().numpy(), "roofline": roof}
         print(f"bench: {name}: {forms[name]['ms_per_step']:.2f} ms per solve", file=sys.stderr, flush=True)
         del solver, M
@@ -327,6 +329,7 @@ def main():
         tot, cnt = rsvd.profile_read(dev, kind)
         if cnt:
             kinds[kind] = (tot, cnt)
+    st1_tot, st1_cnt = rsvd.profile_read(dev, rsvd.PROFILE_STAGE1)
     dom = max(kinds, key=lambda kk: kinds[kk][0])
     dom_ms = kinds[dom][0] / kinds[dom][1]
     flops_launch = 2.0 * m * n * l
@@ -378,6 +381,12 @@ def main():
         "p99_ms": float(np.percentile(lat, 99)),
         "tflops_algorithmic": flops_solve / (dt / args.steps) / 1e12,
         "gemm_ms_per_solve": gemm_ms,
+        # The range finder as a whole (Stage 1: sketch, q power iterations and
+        # every orthonormalisation), (2q + 1) 2 m n l flops over its event time.
+        "range_finder": {"ms": st1_tot / max(1, st1_cnt),
+                         "tflops": (2 * q + 1) * 2.0 * m * n * l / (st1_tot / max(1, st1_cnt) * 1e-3) / 1e12,
+                         "frac_of_peak": (2 * q + 1) * 2.0 * m * n * l / (st1_tot / max(1, st1_cnt) * 1e-3) / 1e12
+                         / PEAK_TFLOPS[cfg["dtype"]]},
         "info": info,
         "residual": {"spectral_estimate_t4": float(res_gpu[0]), "frobenius": float(res_gpu[1]),
                      "ms_per_solve": res_ms},

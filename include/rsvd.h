@@ -161,9 +161,12 @@ const char* rsvd_status_string(rsvd_status s);
  * handle; the split-K reduction that follows the product is outside them).
  * rsvd_profile_read waits for the recorded events of one kind (0: the
  * sketch A * Omega with the generated test matrix, 1: A * X, 2: A^T * X,
- * 3: all kinds, 4: the FP32 projection A^T Q on the master copy of a BF16 /
- * FP8 A), returns the summed kernel time in milliseconds and the number of
- * launches, and forgets those records (kind 3 forgets all). */
+ * 3: all product kinds, 4: the FP32 projection A^T Q on the master copy of a
+ * BF16 / FP8 A), returns the summed kernel time in milliseconds and the
+ * number of launches, and forgets those records (kind 3 forgets all product
+ * records).  Kind 5 is the range finder of each solve (Stage 1 of Algorithm
+ * 4: the sketch, the power iterations and every orthonormalisation, from the
+ * first kernel after the flag reset to the last orth), one record per solve. */
 rsvd_status rsvd_profile_enable(rsvd_handle* h, int32_t enable);
 rsvd_status rsvd_profile_read(rsvd_handle* h, int32_t kind, double* total_ms, int64_t* launches);
 

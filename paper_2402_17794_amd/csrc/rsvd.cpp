@@ -414,12 +414,13 @@ rsvd_status rsvd_profile_enable(rsvd_handle* h, int32_t enable) {
 }
 
 rsvd_status rsvd_profile_read(rsvd_handle* h, int32_t kind, double* total_ms, int64_t* launches) {
-    if (!h || !total_ms || !launches || kind < 0 || kind > 4) return RSVD_ERR_INVALID_ARG;
+    if (!h || !total_ms || !launches || kind < 0 || kind > 5) return RSVD_ERR_INVALID_ARG;
     double tot = 0.0;
     int64_t cnt = 0;
     std::vector<rsvd_handle::Rec> keep;
     for (auto& r : h->recs) {
-        if (kind != 3 && r.kind != kind) { keep.push_back(r); continue; }
+        const bool match = kind == 3 ? r.kind != 5 : r.kind == kind;    // kind 3: every product kind
+        if (!match) { keep.push_back(r); continue; }
         if (hipEventSynchronize(r.stop) != hipSuccess) return RSVD_ERR_DEVICE;
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess) return RSVD_ERR_DEVICE;
@@ -481,6 +482,13 @@ rsvd_status rsvd_solve(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* 
     const int hh = params->force_householder;
 
     RSVD_TRY(launch_init(cnt, P.ncounters, flags, s));
+    rsvd_handle::Rec stage1{5, nullptr, nullptr};
+    if (h->profiling) {
+        stage1.start = h->get_event();
+        stage1.stop = h->get_event();
+        if (!stage1.start || !stage1.stop) return RSVD_ERR_DEVICE;
+        RSVD_TRY(hipEventRecord(stage1.start, s));
+    }
     if (A->dtype == RSVD_FP8_E4M3) RSVD_TRY(launch_vec_max(A->col_scale, A->cols, at<float>(ws, P.smax), s));
     // Stage 1: steps 1-3, sketch with the generated test matrix, then orth.
     if ((st = run_gemm(h, P, ws, A, 0, nullptr, params->seed, Y, s)) != RSVD_OK) return st;
@@ -491,6 +499,10 @@ rsvd_status rsvd_solve(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* 
         if ((st = run_orth(P, ws, dt, P.n, Y, W, hh, s)) != RSVD_OK) return st;
         if ((st = run_gemm(h, P, ws, A, 0, W, 0, Y, s)) != RSVD_OK) return st;
         if ((st = run_orth(P, ws, dt, P.m, Y, Q, hh, s)) != RSVD_OK) return st;
+    }
+    if (h->profiling) {
+        RSVD_TRY(hipEventRecord(stage1.stop, s));
+        h->recs.push_back(stage1);
     }
     // Stage 2: step 6 as B^T = A^T Q (n x l), with the FP32 copy of a
     // low-precision A when there is one; step 7 small SVD, step 8 lift.

@@ -342,7 +342,7 @@ class Server:
             pass
 
 
-PROFILE_SKETCH, PROFILE_NN, PROFILE_TN, PROFILE_ALL = 0, 1, 2, 3
+PROFILE_SKETCH, PROFILE_NN, PROFILE_TN, PROFILE_ALL, PROFILE_PROJ32, PROFILE_STAGE1 = 0, 1, 2, 3, 4, 5
 
 
 def profile_enable(device, enable=True):
@@ -351,7 +351,8 @@ def profile_enable(device, enable=True):
 
 
 def profile_read(device, kind=PROFILE_ALL):
-    """(total kernel milliseconds, launches) of the recorded products of `kind`."""
+    """(total milliseconds, records) of the recorded products of `kind`, or of
+    the range finders (Stage 1) of the profiled solves for PROFILE_STAGE1."""
     tot = ctypes.c_double()
     cnt = ctypes.c_int64()
     _check(load_library().rsvd_profile_read(_handle(device), kind, ctypes.byref(tot), ctypes.byref(cnt)))
