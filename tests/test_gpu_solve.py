@@ -121,6 +121,39 @@ def test_fp64_wide_l(R):
     assert np.max(np.abs(U.T @ U - np.eye(190))) <= 1e-12
 
 
+@pytest.mark.parametrize("m,n,k,p,ratio", [(500, 260, 120, 9, 0.97), (600, 320, 280, 8, 0.98)])
+def test_fp64_block_jacobi_edges(R, m, n, k, p, ratio):
+    """l = 129 (9 blocks of 16, one zero block added) and l = 288 (the largest l,
+    18 blocks): the block-pair Jacobi and the blocked Cholesky against the oracle."""
+    sig = W.spectrum_geometric(n, ratio)
+    A = W.known_spectrum(m, n, sig, 11, 12)
+    out = R.solve(torch.from_numpy(A).cuda(), k=k, p=p, q=0, seed=9)
+    torch.cuda.synchronize()
+    ref = rsvd_alg4(A, k, p, 0, seed=9)
+    assert out["l"] == k + p
+    assert out["info_tensor"].item() & R.INFO_JACOBI_NOT_CONVERGED == 0
+    assert np.max(np.abs(_np(out["S"]) - ref["S"])) <= 1e-12 * ref["S"][0]
+    U, Vt = _np(out["U"]), _np(out["Vt"])
+    assert np.max(np.abs(U.T @ U - np.eye(k))) <= 1e-12
+    assert np.max(np.abs(Vt @ Vt.T - np.eye(k))) <= 1e-12
+    _check_sign_convention(Vt)
+    idx = _separated(ref["S"], 1e-3)[:20]
+    assert np.max(np.abs(_align(U[:, idx], ref["U"][:, idx]) - ref["U"][:, idx])) <= 1e-8
+
+
+def test_rank_deficient_block_jacobi(R):
+    """Rank 100 with l = 140: the Gram of B is singular, so the small SVD's
+    Cholesky takes its shifted retry and the block Jacobi meets zero columns."""
+    A, sig = W.exact_rank(600, 300, 100, 5, 6)
+    out = R.solve(torch.from_numpy(A).cuda(), k=140, p=0, q=0, seed=2, return_full_l=True)
+    torch.cuda.synchronize()
+    S = _np(out["S"])
+    assert out["l"] == 140
+    assert np.max(np.abs(S[:100] - sig[:100])) <= 1e-12 * sig[0]
+    assert np.max(S[100:]) <= 1e-6 * sig[0]
+    assert np.all(np.diff(S) <= 0.0)
+
+
 def test_exact_rank_fp64(R):
     A, sig = W.exact_rank(700, 300, 12, 5, 6)
     out = R.solve(torch.from_numpy(A).cuda(), k=12, p=8, q=1, seed=4, residual=True)
