@@ -173,8 +173,9 @@ def bench_serving(args, cfg, torch, rsvd, workloads):
         rsvd.solve(A, r["k"], r["p"], r["q"], seed=r["seed"])
     torch.cuda.synchronize()
 
-    def replay(poisson):
+    def replay(poisson, graphs=True):
         srv = rsvd.Server(dev, hbm_budget_bytes=budget, n_streams=cfg["streams"])
+        srv.use_graphs(graphs)
         t0 = time.perf_counter()
         reqs = []
         for A, r in zip(mats, trace):
@@ -186,6 +187,7 @@ def bench_serving(args, cfg, torch, rsvd, workloads):
         srv.drain()
         wall = time.perf_counter() - t0
         st = srv.stats()
+        st["graph_launches"], st["graph_instantiations"] = srv.graph_stats()
         srv.close()
         return reqs, st, wall
 
@@ -193,6 +195,8 @@ def bench_serving(args, cfg, torch, rsvd, workloads):
     print(f"bench: Poisson replay: {st_p}", file=sys.stderr, flush=True)
     reqs_s, st_s, wall_s = replay(False)
     print(f"bench: saturation replay: {st_s}", file=sys.stderr, flush=True)
+    _, st_d, wall_d = replay(False, graphs=False)
+    print(f"bench: saturation replay, direct launches: {st_d}", file=sys.stderr, flush=True)
     # Alone-vs-mix: every result of the saturation replay against a solve alone.
     same = 0
     for A, r, rq in zip(mats, trace, reqs_s):
@@ -212,6 +216,7 @@ def bench_serving(args, cfg, torch, rsvd, workloads):
         "p50_ms": st_p["p50_ms"], "p99_ms": st_p["p99_ms"],
         "poisson_replay": {"achieved_solves_per_s": len(trace) / wall_p, **st_p},
         "saturation_replay": {"wall_s": wall_s, **st_s},
+        "saturation_replay_direct_launches": {"wall_s": wall_d, **st_d},
         "tflops_algorithmic_saturation": flops / wall_s / 1e12,
         "alone_equals_mix": f"{same}/{len(trace)}",
         "roofline": None,

@@ -208,7 +208,18 @@ rsvd_status rsvd_server_drain(rsvd_server* s);
 /* Over the completed requests: latency percentiles, completed / (last completion - first submit). */
 rsvd_status rsvd_server_stats(rsvd_server* s, double* p50_ms, double* p99_ms, double* solves_per_s,
                               int64_t* completed);
-/* Drains, then releases the arena, streams and thread. */
+/* Launch graphs (on by default): each admitted request's kernels are captured
+ * into a HIP graph and launched as one; every stream slot keeps the
+ * executable graphs of its last 8 shape buckets (precision, m, n, k, p, q
+ * and the options) and updates the one of a request's bucket with the
+ * request's pointers instead of instantiating a new one.  enable = 0 makes
+ * later admissions launch the kernels directly.  Results are the same either
+ * way. */
+rsvd_status rsvd_server_use_graphs(rsvd_server* s, int32_t enable);
+/* Requests launched as graphs so far, and executable graphs instantiated
+ * (launches minus instantiations = launches that reused an updated graph). */
+rsvd_status rsvd_server_graph_stats(rsvd_server* s, int64_t* launches, int64_t* instantiations);
+/* Drains, then releases the arena, streams, graphs and thread. */
 rsvd_status rsvd_server_destroy(rsvd_server* s);
 
 /* ---- Single steps of the path, for testing each kernel on its own. ---- */

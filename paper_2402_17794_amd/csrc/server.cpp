@@ -11,6 +11,16 @@
 // the request's completion event has fired; its workspace and slot return
 // to the pools).  Latency is measured from submit to the scheduler seeing
 // the completion.
+//
+// Launch graphs: by default an admitted request's kernels are captured from
+// rsvd_solve into a HIP graph and launched as one graph.  Each slot keeps
+// the executable graphs of its last few shape buckets (a bucket = every
+// parameter that fixes the kernel sequence: precision, m, n, k, p, q and the
+// options); a request of a cached bucket updates that executable graph in
+// place with its own pointers and sizes (hipGraphExecUpdate), otherwise a new
+// one is instantiated.  The captured kernels are exactly those rsvd_solve
+// enqueues (no memset or copy nodes), so a graph computes what the direct
+// launches compute.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -74,6 +84,23 @@ private:
     std::map<size_t, size_t> free_, used_;
 };
 
+// Everything about a request that decides which kernels rsvd_solve launches.
+struct BucketKey {
+    int64_t v[14];
+    bool operator==(const BucketKey& o) const {
+        for (int i = 0; i < 14; ++i)
+            if (v[i] != o.v[i]) return false;
+        return true;
+    }
+};
+
+struct GraphEntry {
+    BucketKey key;
+    hipGraphExec_t exec = nullptr;
+    uint64_t last_use = 0;
+};
+constexpr size_t kGraphsPerSlot = 8;
+
 struct Request {
     uint64_t ticket;
     rsvd_matrix A;
@@ -108,13 +135,86 @@ struct rsvd_server {
     bool stop = false;
     std::thread worker;
 
+    // launch graphs, per slot
+    std::atomic<bool> use_graphs{true};
+    std::vector<std::vector<GraphEntry>> graphs;       // touched by the scheduler thread only
+    uint64_t graph_clock = 0;
+    std::atomic<int64_t> graph_launches{0}, graph_instantiations{0};
+
     // statistics
     std::vector<double> latencies_ms;
     Clock::time_point t_first{}, t_last{};
     bool any = false;
 
     void loop();
+    rsvd_status launch(Request* r, int slot, void* ws);
 };
+
+namespace {
+
+BucketKey bucket_of(const Request* r) {
+    const rsvd_params& p = r->params;
+    return BucketKey{{(int64_t)r->A.dtype, r->A.rows, r->A.cols, p.k, p.p, p.q, (int64_t)p.extra_power_pass,
+                      (int64_t)p.residual, (int64_t)p.residual_iters, (int64_t)p.return_full_l,
+                      (int64_t)p.force_householder, r->out.Q != nullptr, r->A.master != nullptr,
+                      r->A.col_scale != nullptr}};
+}
+
+}  // namespace
+
+// Enqueue one admitted request on its slot's stream: directly, or captured
+// into a graph that replaces (or updates) the slot's graph of its bucket.
+rsvd_status rsvd_server::launch(Request* r, int slot, void* ws) {
+    hipStream_t st = streams[slot];
+    if (!use_graphs) return rsvd_solve(h, &r->A, &r->params, &r->out, ws, r->ws_bytes, st);
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) != hipSuccess) return RSVD_ERR_DEVICE;
+    const rsvd_status rs = rsvd_solve(h, &r->A, &r->params, &r->out, ws, r->ws_bytes, st);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(st, &g);
+    if (rs != RSVD_OK || ec != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return rs != RSVD_OK ? rs : RSVD_ERR_DEVICE;
+    }
+    const BucketKey key = bucket_of(r);
+    std::vector<GraphEntry>& cache = graphs[slot];
+    GraphEntry* ent = nullptr;
+    for (auto& e : cache)
+        if (e.key == key) ent = &e;
+    bool ready = false;
+    if (ent) {
+        hipGraphNode_t err_node = nullptr;
+        hipGraphExecUpdateResult res;
+        if (hipGraphExecUpdate(ent->exec, g, &err_node, &res) == hipSuccess && res == hipGraphExecUpdateSuccess) {
+            ready = true;
+        } else {
+            (void)hipGraphExecDestroy(ent->exec);
+            ent->exec = nullptr;
+        }
+    } else {
+        if (cache.size() >= kGraphsPerSlot) {         // evict the least recently used bucket
+            auto lru = std::min_element(cache.begin(), cache.end(),
+                                        [](const GraphEntry& a, const GraphEntry& b) { return a.last_use < b.last_use; });
+            if (lru->exec) (void)hipGraphExecDestroy(lru->exec);
+            cache.erase(lru);
+        }
+        cache.push_back(GraphEntry{key, nullptr, 0});
+        ent = &cache.back();
+    }
+    if (!ready) {
+        if (hipGraphInstantiate(&ent->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+            ent->exec = nullptr;
+            (void)hipGraphDestroy(g);
+            return RSVD_ERR_DEVICE;
+        }
+        ++graph_instantiations;
+    }
+    ent->last_use = ++graph_clock;
+    const hipError_t el = hipGraphLaunch(ent->exec, st);
+    (void)hipGraphDestroy(g);
+    if (el != hipSuccess) return RSVD_ERR_DEVICE;
+    ++graph_launches;
+    return RSVD_OK;
+}
 
 void rsvd_server::loop() {
     (void)hipSetDevice(device);
@@ -162,7 +262,7 @@ void rsvd_server::loop() {
             slot_busy[slot] = 1;
             void* ws = static_cast<char*>(arena_base) + off;
             lk.unlock();                        // launch without holding the lock
-            rsvd_status st = rsvd_solve(h, &r->A, &r->params, &r->out, ws, r->ws_bytes, streams[slot]);
+            rsvd_status st = launch(r, slot, ws);
             hipError_t e = hipEventRecord(events[slot], streams[slot]);
             lk.lock();
             if (st != RSVD_OK || e != hipSuccess) {
@@ -202,6 +302,7 @@ rsvd_status rsvd_server_create(rsvd_server** out, int device, size_t hbm_budget_
     s->streams.assign(n_streams, nullptr);
     s->events.assign(n_streams, nullptr);
     s->slot_busy.assign(n_streams, 0);
+    s->graphs.assign(n_streams, {});
     for (int i = 0; i < n_streams; ++i) {
         // default priority: every stream of the server is an ordinary stream
         if (hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) != hipSuccess ||
@@ -294,6 +395,19 @@ rsvd_status rsvd_server_stats(rsvd_server* s, double* p50_ms, double* p99_ms, do
     return RSVD_OK;
 }
 
+rsvd_status rsvd_server_use_graphs(rsvd_server* s, int32_t enable) {
+    if (!s) return RSVD_ERR_INVALID_ARG;
+    s->use_graphs = enable != 0;
+    return RSVD_OK;
+}
+
+rsvd_status rsvd_server_graph_stats(rsvd_server* s, int64_t* launches, int64_t* instantiations) {
+    if (!s) return RSVD_ERR_INVALID_ARG;
+    if (launches) *launches = s->graph_launches;
+    if (instantiations) *instantiations = s->graph_instantiations;
+    return RSVD_OK;
+}
+
 rsvd_status rsvd_server_destroy(rsvd_server* s) {
     if (!s) return RSVD_OK;
     {
@@ -303,6 +417,9 @@ rsvd_status rsvd_server_destroy(rsvd_server* s) {
     s->cv_work.notify_all();
     if (s->worker.joinable()) s->worker.join();
     for (auto& kv : s->all) delete kv.second;
+    for (auto& cache : s->graphs)
+        for (auto& e : cache)
+            if (e.exec) (void)hipGraphExecDestroy(e.exec);
     for (size_t i = 0; i < s->streams.size(); ++i) {
         if (s->streams[i]) (void)hipStreamDestroy(s->streams[i]);
         if (s->events[i]) (void)hipEventDestroy(s->events[i]);

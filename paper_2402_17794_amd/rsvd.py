@@ -67,7 +67,7 @@ EXPORTS = ["rsvd_create", "rsvd_destroy", "rsvd_l_used", "rsvd_workspace_size", 
            "rsvd_status_string", "rsvd_profile_enable", "rsvd_profile_read", "rsvd_quantize", "rsvd_omega",
            "rsvd_philox_words", "rsvd_gemm_workspace_size", "rsvd_gemm", "rsvd_orth_workspace_size", "rsvd_orth",
            "rsvd_server_create", "rsvd_server_submit", "rsvd_server_poll", "rsvd_server_wait", "rsvd_server_drain",
-           "rsvd_server_stats", "rsvd_server_destroy"]
+           "rsvd_server_stats", "rsvd_server_destroy", "rsvd_server_use_graphs", "rsvd_server_graph_stats"]
 
 _lib = None
 
@@ -102,6 +102,8 @@ def load_library(path=LIB_PATH):
         "rsvd_server_stats": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)], I32),
         "rsvd_server_destroy": ([P], I32),
+        "rsvd_server_use_graphs": ([P, I32], I32),
+        "rsvd_server_graph_stats": ([P, ctypes.POINTER(I64), ctypes.POINTER(I64)], I32),
         "rsvd_omega": ([I32, U64, ctypes.c_uint32, I64, I64, P, I64, P], I32),
         "rsvd_philox_words": ([U64, ctypes.c_uint32, P, I64, P, P], I32),
         "rsvd_gemm_workspace_size": ([ctypes.POINTER(rsvd_matrix), I32, I64, ctypes.POINTER(SZ)], I32),
@@ -323,6 +325,16 @@ class Server:
 
     def drain(self):
         _check(self.lib.rsvd_server_drain(self.ptr))
+
+    def use_graphs(self, enable=True):
+        """Launch later admissions as captured per-bucket graphs (default) or directly."""
+        _check(self.lib.rsvd_server_use_graphs(self.ptr, int(enable)))
+
+    def graph_stats(self):
+        """(requests launched as graphs, executable graphs instantiated)."""
+        n, inst = ctypes.c_int64(), ctypes.c_int64()
+        _check(self.lib.rsvd_server_graph_stats(self.ptr, ctypes.byref(n), ctypes.byref(inst)))
+        return n.value, inst.value
 
     def stats(self):
         p50, p99, sps, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()

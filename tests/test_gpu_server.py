@@ -7,6 +7,8 @@
 * Admission by HBM footprint: with an arena that holds only about one
   request's workspace, requests still all complete (they queue); a request
   larger than the whole arena is refused at submit.
+* Launch graphs: requests of one shape bucket replay an updated executable
+  graph; every replay equals the direct solve, with graphs on and off.
 """
 
 import numpy as np
@@ -67,4 +69,33 @@ def test_request_larger_than_arena_is_refused(R):
     srv = R.Server("cuda:0", hbm_budget_bytes=1 << 20, n_streams=2)
     with pytest.raises(R.RsvdError):
         srv.submit(A, 50, 10, 1)
+    srv.close()
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+def test_graph_replays_equal_direct_solves(R, graphs):
+    """Requests of two shape buckets, interleaved, each bucket several times
+    with different matrices and seeds on one slot: every result (first
+    capture and every update-and-replay) is bitwise the direct solve's, with
+    the solver's own work and synchronisations in between."""
+    shapes = [(700, 300, 20, 1, torch.float32), (400, 900, 30, 2, torch.float64)]
+    srv = R.Server("cuda:0", hbm_budget_bytes=1 << 30, n_streams=1)
+    srv.use_graphs(graphs)
+    for rep in range(4):
+        for b, (m, n, k, q, dtype) in enumerate(shapes):
+            sig = W.spectrum_geometric(min(m, n), 0.9 + 0.02 * rep)
+            A = torch.from_numpy(W.known_spectrum(m, n, sig, 30 + rep, 40 + b)).to(dtype).cuda()
+            seed = 10 * rep + b
+            direct = R.solve(A, k, 10, q, seed=seed)
+            torch.cuda.synchronize()
+            t = srv.submit(A, k, 10, q, seed=seed)
+            t.wait()
+            torch.cuda.synchronize()
+            for key, val in (("U", t.U), ("S", t.S), ("Vt", t.Vt)):
+                assert torch.equal(val, direct[key]), (rep, b, key)
+    launches, inst = srv.graph_stats()
+    if graphs:
+        assert launches == 8 and inst == 2       # one instantiation per bucket, six updates
+    else:
+        assert launches == 0 and inst == 0
     srv.close()
