@@ -56,3 +56,25 @@ def test_host_only_entry_points(lib):
     assert lib.rsvd_workspace_size(None, ctypes.byref(badld), ctypes.byref(good), ctypes.byref(nb)) == 1
     # solve with a NULL handle is rejected before any device work
     assert lib.rsvd_solve(None, ctypes.byref(A), ctypes.byref(good), None, None, 0, None) == 1
+
+
+def test_workspace_grows_with_the_block_jacobi_scratch(lib):
+    """The workspace holds the block Jacobi's X (kMaxL^2 doubles) and its
+    per-sweep words for any l, so an l > 128 solve needs nothing else."""
+    from paper_2402_17794_amd import rsvd
+    A = rsvd.rsvd_matrix(0x1000, rsvd.RSVD_F32, 0, 4096, 2048, 2048)
+    nb = ctypes.c_size_t()
+    p = rsvd.rsvd_params(256, 16, 1, 0, 0, 0, 0, 0)            # l = 272
+    assert lib.rsvd_workspace_size(None, ctypes.byref(A), ctypes.byref(p), ctypes.byref(nb)) == 0
+    assert nb.value >= 288 * 288 * 8 + 4096 * 272 * 4
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU: --gpus 2 exits with status 2 and says why,
+    before touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
