@@ -115,15 +115,6 @@ def rsvd_alg3(A, k, p=10, q=0, seed=0, omega=None, return_full_l=False):
     return out
 
 
-def range_finder(A, l, q, seed=0):
-    """Stage 1 of Algorithm 4 only: the m x l orthonormal Q."""
-    A = np.asarray(A, dtype=np.float64)
-    Q = orth(A @ gaussian_omega(seed, A.shape[1], l))
-    for _ in range(q):
-        Q = orth(A @ orth(A.T @ Q))
-    return Q
-
-
 def spectral_norm_power(E, iters=30, block=16, seed=0):
     """Largest singular value of E by block power iteration on E^T E with a
     Gaussian start block (Philox stream 2), re-orthonormalised every
@@ -155,5 +146,5 @@ def residual_norms(A, Q, exact_limit=1 << 22):
     return spec, fro
 
 
-__all__ = ["rsvd_alg4", "rsvd_alg3", "range_finder", "residual_norms",
+__all__ = ["rsvd_alg4", "rsvd_alg3", "residual_norms",
            "spectral_norm_power", "householder_qr", "jacobi_svd"]
