@@ -50,7 +50,9 @@ typedef enum {
     RSVD_ERR_UNSUPPORTED = 2,      /* valid request this build does not implement */
     RSVD_ERR_NO_MEMORY = 3,        /* a host or device allocation failed */
     RSVD_ERR_WORKSPACE_TOO_SMALL = 4,
-    RSVD_ERR_DEVICE = 5            /* a HIP runtime call failed */
+    RSVD_ERR_DEVICE = 5,           /* a HIP runtime call failed */
+    RSVD_ERR_TOO_LARGE = 6         /* rsvd_solve_noalloc: the problem needs more device scratch
+                                      than RSVD_NOALLOC_SCRATCH_BYTES */
 } rsvd_status;
 
 typedef enum {
@@ -132,9 +134,13 @@ typedef struct {
     void* Q;  int64_t ldq;         /* nullable; m x l, row-major, ldq >= l */
 } rsvd_result;
 
-/* Create a handle bound to HIP device `device` (host memory only; device
- * scratch always comes from the caller's workspace).  *out is NULL on error.
- * Calls made with the handle make `device` current (hipSetDevice). */
+/* Create a handle bound to HIP device `device` (host memory only; the
+ * scratch of rsvd_solve and the other calls comes from the caller's
+ * workspace, that of rsvd_solve_noalloc from the library's fixed array).
+ * *out is NULL on error.
+ * Calls made with the handle make `device` current (hipSetDevice); the
+ * first rsvd_create on a device also looks up the device address of the
+ * scratch array of rsvd_solve_noalloc on it (RSVD_ERR_DEVICE if that fails). */
 rsvd_status rsvd_create(rsvd_handle** out, int device);
 rsvd_status rsvd_destroy(rsvd_handle* h);
 
@@ -152,6 +158,26 @@ rsvd_status rsvd_workspace_size(const rsvd_handle* h, const rsvd_matrix* A,
 rsvd_status rsvd_solve(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* params,
                        const rsvd_result* out, void* workspace, size_t workspace_bytes,
                        void* stream);
+
+/* Allocation-free form of rsvd_solve, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops and
+ * harnesses that forbid hipMalloc.  Same arguments, semantics and results
+ * as rsvd_solve, except that the workspace is not passed: the solve uses a
+ * fixed device scratch array of RSVD_NOALLOC_SCRATCH_BYTES compiled into
+ * the library (one copy per device, held from the first rsvd_create on that
+ * device until the process ends; its device address is looked up by
+ * rsvd_create).  The call itself allocates nothing (no hipMalloc, hipFree
+ * or event creation); rsvd_profile_enable does not apply to it.  A problem
+ * whose rsvd_workspace_size exceeds RSVD_NOALLOC_SCRATCH_BYTES is refused
+ * with RSVD_ERR_TOO_LARGE before anything is enqueued (64 MiB covers, e.g.,
+ * 8192 x 8192 FP32 with l = 110).  Every call on one device shares that
+ * device's scratch, and a solve initialises the parts it reads: calls that
+ * overlap on one device (different streams or host threads without
+ * ordering between them) race and give undefined results; calls ordered on
+ * one stream are safe. */
+#define RSVD_NOALLOC_SCRATCH_BYTES (64ull << 20)
+rsvd_status rsvd_solve_noalloc(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* params,
+                               const rsvd_result* out, void* stream);
 
 const char* rsvd_status_string(rsvd_status s);
 

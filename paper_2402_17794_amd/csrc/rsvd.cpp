@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -35,7 +36,38 @@ struct rsvd_handle {
     }
 };
 
+// Device scratch of the allocation-free entry point rsvd_solve_noalloc: a
+// file-scope array of kScratchBytes in every device's copy of this code
+// object.  Its name is only a host-side stand-in; host code uses the device
+// address that hipGetSymbolAddress returns for the device (scratch_ptr).
+constexpr size_t kScratchBytes = (size_t)RSVD_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Look up (once per device, with that device current) the device address of
+// the scratch array.
+hipError_t scratch_init(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) return e;
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255)) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = ptr;
+    return hipSuccess;
+}
+
+void* scratch_ptr(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
 
 constexpr size_t kAlign = 256;
 
@@ -380,6 +412,8 @@ const char* rsvd_status_string(rsvd_status s) {
         case RSVD_ERR_NO_MEMORY: return "out of memory";
         case RSVD_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
         case RSVD_ERR_DEVICE: return "HIP runtime error";
+        case RSVD_ERR_TOO_LARGE:
+            return "problem needs more device scratch than rsvd_solve_noalloc holds (RSVD_NOALLOC_SCRATCH_BYTES)";
     }
     return "unknown status";
 }
@@ -392,6 +426,8 @@ rsvd_status rsvd_create(rsvd_handle** out, int device) {
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess) return RSVD_ERR_DEVICE;
     if (device < 0 || device >= count) return RSVD_ERR_INVALID_ARG;
+    if (device >= kMaxDevices) return RSVD_ERR_UNSUPPORTED;
+    if (scratch_init(device) != hipSuccess) return RSVD_ERR_DEVICE;
     rsvd_handle* h = new (std::nothrow) rsvd_handle;
     if (!h) return RSVD_ERR_NO_MEMORY;
     h->device = device;
@@ -450,8 +486,14 @@ rsvd_status rsvd_workspace_size(const rsvd_handle* h, const rsvd_matrix* A, cons
     return RSVD_OK;
 }
 
-rsvd_status rsvd_solve(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* params, const rsvd_result* out,
-                       void* ws, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// One solve on `stream` with the workspace ws.  profile: allow the event
+// records of rsvd_profile_enable (they may create HIP events).
+rsvd_status solve_impl(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* params, const rsvd_result* out,
+                       void* ws, size_t ws_bytes, void* stream, bool profile) {
     if (!h || !out) return RSVD_ERR_INVALID_ARG;
     rsvd_status st = check_matrix(A);
     if (st != RSVD_OK) return st;
@@ -482,8 +524,9 @@ rsvd_status rsvd_solve(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* 
     const int hh = params->force_householder;
 
     RSVD_TRY(launch_init(cnt, P.ncounters, flags, s));
+    rsvd_handle* hp = profile && h->profiling ? h : nullptr;   // product timing on
     rsvd_handle::Rec stage1{5, nullptr, nullptr};
-    if (h->profiling) {
+    if (hp) {
         stage1.start = h->get_event();
         stage1.stop = h->get_event();
         if (!stage1.start || !stage1.stop) return RSVD_ERR_DEVICE;
@@ -491,22 +534,22 @@ rsvd_status rsvd_solve(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* 
     }
     if (A->dtype == RSVD_FP8_E4M3) RSVD_TRY(launch_vec_max(A->col_scale, A->cols, at<float>(ws, P.smax), s));
     // Stage 1: steps 1-3, sketch with the generated test matrix, then orth.
-    if ((st = run_gemm(h, P, ws, A, 0, nullptr, params->seed, Y, s)) != RSVD_OK) return st;
+    if ((st = run_gemm(hp, P, ws, A, 0, nullptr, params->seed, Y, s)) != RSVD_OK) return st;
     if ((st = run_orth(P, ws, dt, P.m, Y, Q, hh, s)) != RSVD_OK) return st;
     // Steps 4-5: q power iterations, each product re-orthonormalised.
     for (int64_t t = 0; t < qeff; ++t) {
-        if ((st = run_gemm(h, P, ws, A, 1, Q, 0, Y, s)) != RSVD_OK) return st;
+        if ((st = run_gemm(hp, P, ws, A, 1, Q, 0, Y, s)) != RSVD_OK) return st;
         if ((st = run_orth(P, ws, dt, P.n, Y, W, hh, s)) != RSVD_OK) return st;
-        if ((st = run_gemm(h, P, ws, A, 0, W, 0, Y, s)) != RSVD_OK) return st;
+        if ((st = run_gemm(hp, P, ws, A, 0, W, 0, Y, s)) != RSVD_OK) return st;
         if ((st = run_orth(P, ws, dt, P.m, Y, Q, hh, s)) != RSVD_OK) return st;
     }
-    if (h->profiling) {
+    if (hp) {
         RSVD_TRY(hipEventRecord(stage1.stop, s));
         h->recs.push_back(stage1);
     }
     // Stage 2: step 6 as B^T = A^T Q (n x l), with the FP32 copy of a
     // low-precision A when there is one; step 7 small SVD, step 8 lift.
-    if ((st = run_gemm(h, P, ws, &Am, 1, Q, 0, Y, s, lowp && A->master ? 4 : -1)) != RSVD_OK) return st;
+    if ((st = run_gemm(hp, P, ws, &Am, 1, Q, 0, Y, s, lowp && A->master ? 4 : -1)) != RSVD_OK) return st;
     const void* Bt = Y;
     double* R = at<double>(ws, P.R);
     double* sigma = at<double>(ws, P.sigma);
@@ -538,6 +581,27 @@ rsvd_status rsvd_solve(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* 
     }
     RSVD_TRY(launch_export_info(flags, out->info, s));
     return RSVD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rsvd_status rsvd_solve(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* params, const rsvd_result* out,
+                       void* ws, size_t ws_bytes, void* stream) {
+    return solve_impl(h, A, params, out, ws, ws_bytes, stream, true);
+}
+
+rsvd_status rsvd_solve_noalloc(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* params,
+                               const rsvd_result* out, void* stream) {
+    if (!h) return RSVD_ERR_INVALID_ARG;
+    size_t need = 0;
+    rsvd_status st = rsvd_workspace_size(h, A, params, &need);
+    if (st != RSVD_OK) return st;
+    if (need > kScratchBytes) return RSVD_ERR_TOO_LARGE;
+    void* ws = scratch_ptr(h->device);
+    if (!ws) return RSVD_ERR_DEVICE;
+    return solve_impl(h, A, params, out, ws, kScratchBytes, stream, false);
 }
 
 rsvd_status rsvd_omega(int32_t dtype, uint64_t seed, uint32_t stream_id, int64_t n, int64_t l, void* out, int64_t ld,

@@ -63,7 +63,7 @@ class rsvd_result(ctypes.Structure):
                 ("info", ctypes.c_void_p), ("Q", ctypes.c_void_p), ("ldq", ctypes.c_int64)]
 
 
-EXPORTS = ["rsvd_create", "rsvd_destroy", "rsvd_l_used", "rsvd_workspace_size", "rsvd_solve",
+EXPORTS = ["rsvd_create", "rsvd_destroy", "rsvd_l_used", "rsvd_workspace_size", "rsvd_solve", "rsvd_solve_noalloc",
            "rsvd_status_string", "rsvd_profile_enable", "rsvd_profile_read", "rsvd_quantize", "rsvd_omega",
            "rsvd_philox_words", "rsvd_gemm_workspace_size", "rsvd_gemm", "rsvd_orth_workspace_size", "rsvd_orth",
            "rsvd_server_create", "rsvd_server_submit", "rsvd_server_poll", "rsvd_server_wait", "rsvd_server_drain",
@@ -89,6 +89,8 @@ def load_library(path=LIB_PATH):
                                 I32),
         "rsvd_solve": ([P, ctypes.POINTER(rsvd_matrix), ctypes.POINTER(rsvd_params), ctypes.POINTER(rsvd_result),
                         P, SZ, P], I32),
+        "rsvd_solve_noalloc": ([P, ctypes.POINTER(rsvd_matrix), ctypes.POINTER(rsvd_params),
+                                ctypes.POINTER(rsvd_result), P], I32),
         "rsvd_status_string": ([I32], ctypes.c_char_p),
         "rsvd_profile_enable": ([P, I32], I32),
         "rsvd_profile_read": ([P, I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)], I32),
@@ -212,15 +214,21 @@ def _residual_mode(residual):
     return int(residual)
 
 
+RSVD_ERR_TOO_LARGE = 6
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
 class Solver:
     """Reusable solve for one (shape, dtype, k, p, q): owns the output tensors
     and the workspace, so repeated calls allocate nothing.  residual: False,
     True (Frobenius), or the header's bit mask (1 spectral estimate, 2
     Frobenius, 3 both); residual_iters: power iterations of the spectral
-    estimate (0 = library default)."""
+    estimate (0 = library default).  noalloc: call rsvd_solve_noalloc, which
+    uses the library's fixed device scratch instead of a workspace (no
+    workspace tensor is made)."""
 
     def __init__(self, A, k, p=10, q=0, seed=0, residual=False, return_full_l=False, force_householder=False,
-                 return_q=False, stream=None, residual_iters=0, extra_power_pass=-1):
+                 return_q=False, stream=None, residual_iters=0, extra_power_pass=-1, noalloc=False):
         self.lib = load_library()
         self.A = A
         self.M = _as_matrix(A)
@@ -239,9 +247,10 @@ class Solver:
         self.Q = torch.empty((m, self.l), dtype=A.dtype, device=dev) if return_q else None
         nb = ctypes.c_size_t()
         self.h = _handle(dev)
+        self.noalloc = bool(noalloc)
         _check(self.lib.rsvd_workspace_size(self.h, ctypes.byref(self.M), ctypes.byref(self.params),
                                             ctypes.byref(nb)))
-        self.ws = _workspace(nb.value, dev)
+        self.ws = None if self.noalloc else _workspace(nb.value, dev)
         self.result = rsvd_result(self.U.data_ptr(), r, self.S.data_ptr(), self.Vt.data_ptr(), n,
                                   self.res.data_ptr() if residual else None, self.info.data_ptr(),
                                   self.Q.data_ptr() if return_q else None, self.l)
@@ -251,6 +260,10 @@ class Solver:
         self.params.seed = seed
 
     def __call__(self):
+        if self.noalloc:
+            _check(self.lib.rsvd_solve_noalloc(self.h, ctypes.byref(self.M), ctypes.byref(self.params),
+                                               ctypes.byref(self.result), _stream_ptr(self.stream, self.A.device)))
+            return self
         _check(self.lib.rsvd_solve(self.h, ctypes.byref(self.M), ctypes.byref(self.params), ctypes.byref(self.result),
                                    ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(),
                                    _stream_ptr(self.stream, self.A.device)))
@@ -258,13 +271,13 @@ class Solver:
 
 
 def solve(A, k, p=10, q=0, seed=0, residual=False, return_full_l=False, force_householder=False, return_q=False,
-          stream=None, residual_iters=0, extra_power_pass=-1):
+          stream=None, residual_iters=0, extra_power_pass=-1, noalloc=False):
     """Randomized SVD (Algorithm 4) of a CUDA tensor A.  Returns a dict with
     U (m x r), S (r, float64), Vt (r x n), info (int), l, and optionally
     residual_t ([spectral estimate, Frobenius norm] of A - QQ^T A, float64
-    tensor) and Q (m x l)."""
+    tensor) and Q (m x l).  noalloc: use rsvd_solve_noalloc."""
     s = Solver(A, k, p, q, seed, residual, return_full_l, force_householder, return_q, stream, residual_iters,
-               extra_power_pass)()
+               extra_power_pass, noalloc)()
     out = dict(U=s.U, S=s.S, Vt=s.Vt, l=s.l, info_tensor=s.info)
     if residual:
         out["residual_t"] = s.res

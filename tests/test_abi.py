@@ -56,6 +56,8 @@ def test_host_only_entry_points(lib):
     assert lib.rsvd_workspace_size(None, ctypes.byref(badld), ctypes.byref(good), ctypes.byref(nb)) == 1
     # solve with a NULL handle is rejected before any device work
     assert lib.rsvd_solve(None, ctypes.byref(A), ctypes.byref(good), None, None, 0, None) == 1
+    assert lib.rsvd_solve_noalloc(None, ctypes.byref(A), ctypes.byref(good), None, None) == 1
+    assert b"scratch" in lib.rsvd_status_string(rsvd.RSVD_ERR_TOO_LARGE)
 
 
 def test_workspace_grows_with_the_block_jacobi_scratch(lib):
