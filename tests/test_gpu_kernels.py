@@ -88,6 +88,26 @@ def test_products_with_A(R, dtype, m, n, nc):
     assert np.all(np.abs(S - A @ Om) <= tol)
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("m,n,nc", [(8192, 8192, 112), (8191, 8190, 109), (1000, 4103, 33), (257, 63, 288)])
+def test_integer_products_bit_exact(R, dtype, m, n, nc):
+    """Entries in {-4..4}: every product and every partial sum is an integer
+    below 2^24 in magnitude, so any summation order gives the exact result in
+    FP32.  The NN and TN products must then equal the integer product bit for
+    bit: a dropped, duplicated or misplaced term in any tile, K slice or
+    ragged edge shows."""
+    rng = np.random.default_rng(m + n + nc)
+    A = rng.integers(-4, 5, size=(m, n), dtype=np.int64)
+    X = rng.integers(-4, 5, size=(n, nc), dtype=np.int64)
+    Wm = rng.integers(-4, 5, size=(m, nc), dtype=np.int64)
+    Ad = _cuda(A.astype(np.float64), dtype)
+    Y = R.gemm(Ad, _cuda(X.astype(np.float64), dtype)).cpu().numpy()
+    assert np.array_equal(Y.astype(np.int64), A @ X)
+    assert np.all(Y == (A @ X).astype(Y.dtype))
+    Z = R.gemm(Ad, _cuda(Wm.astype(np.float64), dtype), trans=True).cpu().numpy()
+    assert np.all(Z == (A.T @ Wm).astype(Z.dtype))
+
+
 def test_products_strided_and_unaligned(R):
     rng = np.random.default_rng(3)
     big = torch.from_numpy(rng.standard_normal((300, 203)).astype(np.float32)).cuda()

@@ -64,6 +64,39 @@ def test_alone_equals_mix(R, n_streams, budget):
     srv.close()
 
 
+def test_served_results_match_the_oracle(R):
+    """Requests served together (FP32 and FP64, q = 0, 1, 2) against the FP64
+    oracle on the same matrices and seeds, at the tolerances of the single
+    solves: FP64 sigma within 1e-12 sigma_1, FP32 within 1e-5 sigma_1
+    (normwise), and FP32 ranges of the leading separated vectors."""
+    from oracle.rsvd import rsvd_alg4
+    cases = [(900, 500, 30, 0, torch.float32), (700, 1100, 40, 1, torch.float64), (1500, 800, 60, 2, torch.float32),
+             (600, 600, 25, 2, torch.float64), (1024, 777, 50, 1, torch.float32)]
+    mats = []
+    for i, (m, n, k, q, dtype) in enumerate(cases):
+        sig = W.spectrum_geometric(min(m, n), 0.93 + 0.01 * i)
+        A = W.known_spectrum(m, n, sig, 300 + i, 400 + i)
+        if dtype == torch.float32:
+            A = A.astype(np.float32).astype(np.float64)
+        mats.append((A, torch.from_numpy(A).to(dtype).cuda()))
+    srv = R.Server("cuda:0", hbm_budget_bytes=1 << 30, n_streams=3)
+    tickets = [srv.submit(Ad, k, 10, q, seed=7 + i) for i, ((_, Ad), (m, n, k, q, _)) in enumerate(zip(mats, cases))]
+    for t in tickets:
+        t.wait()
+    torch.cuda.synchronize()
+    for i, (t, (A, _), (m, n, k, q, dtype)) in enumerate(zip(tickets, mats, cases)):
+        ref = rsvd_alg4(A, k, 10, q, seed=7 + i)
+        S = t.S.cpu().numpy()
+        tol = 1e-12 if dtype == torch.float64 else 1e-5
+        assert np.max(np.abs(S - ref["S"])) <= tol * ref["S"][0], i
+        U = t.U.cpu().numpy().astype(np.float64)
+        Uk = ref["U"][:, :5]
+        # sin of the largest canonical angle between the leading 5 left vectors
+        sin = np.linalg.norm(Uk - U[:, :5] @ (U[:, :5].T @ Uk), 2)
+        assert sin <= (1e-9 if dtype == torch.float64 else 1e-4), i
+    srv.close()
+
+
 def test_request_larger_than_arena_is_refused(R):
     A = torch.randn(2000, 1500, device="cuda")
     srv = R.Server("cuda:0", hbm_budget_bytes=1 << 20, n_streams=2)

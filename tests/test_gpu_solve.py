@@ -5,10 +5,12 @@ Tolerances:
 * FP64 solve: singular values within 1e-12 sigma_1 (normwise), vectors of
   well-separated singular values within 1e-9, residual within 1e-9 relative.
 * FP32 solve: top-k singular values within 1e-5 sigma_1 (normwise; FP32
-  rounding perturbs every singular value by about u ||A||), the Frobenius
-  residual within 1% of the oracle's (plus the FP32 floor 16 u ||A||_F, which
-  matters only when the exact residual vanishes), and the subspaces of well-separated
-  leading singular vectors within 1e-3 (sin of the largest canonical angle).
+  rounding perturbs every singular value by about u ||A||) and within 1e-5
+  relative where sigma_k stays well above u ||A||, the Frobenius residual
+  within 1% of the oracle's (plus the FP32 floor 16 u ||A||_F, which matters
+  only when the exact residual vanishes), and every singular vector whose
+  gap to its neighbours exceeds 1e-4 sigma_1 within 8 u sigma_1 / gap_i
+  (u = 2^-24) of the oracle's.
 * Vectors are compared up to the sign of each column; the GPU's own output
   is separately checked to satisfy the sign convention.
 """
@@ -45,6 +47,14 @@ def _check_sign_convention(Vt):
     for i in range(Vt.shape[0]):
         idx = int(np.argmax(np.abs(Vt[i])))
         assert Vt[i, idx] >= 0.0
+
+
+def _gaps(S):
+    """gap_i = distance from sigma_i to its nearest neighbour among the returned values."""
+    gaps = np.full(S.size, np.inf)
+    gaps[:-1] = np.minimum(gaps[:-1], S[:-1] - S[1:])
+    gaps[1:] = np.minimum(gaps[1:], S[:-1] - S[1:])
+    return gaps
 
 
 def _separated(S, rel=1e-3):
@@ -91,6 +101,8 @@ def test_fp32_solve_matches_oracle(R, m, n, k, p, q, seed):
     ref = rsvd_alg4(Ad, k, p, q, seed=seed)
     S = _np(out["S"])
     assert np.max(np.abs(S - ref["S"])) <= 1e-5 * ref["S"][0]
+    # top-k relative error too (these spectra stay above the FP32 floor here)
+    assert np.max(np.abs(S - ref["S"]) / ref["S"]) <= 1e-5
     _, fro = residual_norms(Ad, ref["Q"])
     # 1% of the oracle's residual, above the FP32 rounding floor u ||A||_F
     # (when l = min(m, n) the exact residual is zero).
@@ -100,11 +112,19 @@ def test_fp32_solve_matches_oracle(R, m, n, k, p, q, seed):
     assert np.max(np.abs(U.T @ U - np.eye(k))) <= 1e-5
     assert np.max(np.abs(Vt @ Vt.T - np.eye(k))) <= 1e-5
     _check_sign_convention(Vt)
-    idx = _separated(ref["S"], 1e-2)[:10]
+    # Singular vectors, gap-scaled: the FP32 run differs from the FP64 one by a
+    # perturbation of about u ||A|| (u = 2^-24), which turns singular vector i
+    # by at most about u sigma_1 / gap_i (Wedin); allowed: 8 u sigma_1 / gap_i,
+    # on every index whose gap exceeds 1e-4 sigma_1 (measured: at most 0.62).
+    gap = _gaps(ref["S"])
+    idx = np.nonzero(gap > 1e-4 * ref["S"][0])[0]
+    tol = 8 * 2.0 ** -24 * ref["S"][0] / gap[idx]
     Ua = _align(U[:, idx], ref["U"][:, idx])
-    assert np.max(np.abs(Ua - ref["U"][:, idx])) <= 1e-3
+    errU = np.linalg.norm(Ua - ref["U"][:, idx], axis=0)
     Va = _align(Vt[idx].T, ref["Vt"][idx].T)
-    assert np.max(np.abs(Va - ref["Vt"][idx].T)) <= 1e-3
+    errV = np.linalg.norm(Va - ref["Vt"][idx].T, axis=0)
+    print(f"vector error / (u sigma_1 / gap): U {np.max(errU / tol * 8):.2f}, V {np.max(errV / tol * 8):.2f}")
+    assert np.all(errU <= tol) and np.all(errV <= tol)
 
 
 def test_fp64_wide_l(R):
@@ -188,6 +208,18 @@ def test_return_full_l_and_determinism(R):
         assert torch.equal(a[key], b[key])
     ref = rsvd_alg4(A.astype(np.float64), 25, 5, 1, seed=1, return_full_l=True)
     assert np.max(np.abs(_np(a["S"]) - ref["S"])) <= 1e-5 * ref["S"][0]
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_nonfinite_input_is_reported(R, dtype):
+    """A NaN in A reaches the Gram matrices: the solve completes (every loop
+    is bounded) and reports RSVD_INFO_NONFINITE."""
+    sig = W.spectrum_geometric(300, 0.9)
+    A = W.known_spectrum(500, 300, sig, 3, 4)
+    A[123, 45] = np.nan
+    out = R.solve(torch.from_numpy(A).to(dtype).cuda(), k=20, p=10, q=1, seed=0)
+    torch.cuda.synchronize()
+    assert out["info_tensor"].item() & R.INFO_NONFINITE
 
 
 def test_invalid_arguments_raise(R):
