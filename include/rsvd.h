@@ -74,6 +74,11 @@ typedef enum {
                                            shift was used (B rank-deficient) */
 #define RSVD_INFO_JACOBI_NOT_CONVERGED 4 /* small SVD hit the sweep cap */
 #define RSVD_INFO_NONFINITE          8  /* NaN or Inf met in a Gram matrix */
+#define RSVD_INFO_ORTH_BREAKDOWN    16  /* RSVD_ORTH_CHOLQR2: CholeskyQR broke down and no fallback
+                                           ran, so a basis is not orthonormal */
+#define RSVD_INFO_FALLBACK_TIMEOUT  32  /* a grid barrier of the Householder fallback did not
+                                           complete within its wait limit (device oversubscribed);
+                                           the basis of that orthonormalisation is not valid */
 
 typedef struct rsvd_handle rsvd_handle;
 
@@ -109,7 +114,10 @@ typedef struct {
                                       bit 0 (1): spectral norm, estimated (see residual_iters);
                                       bit 1 (2): Frobenius norm, exact (FP64 accumulation); 3: both */
     int32_t return_full_l;         /* 0: return the top k triplets; 1: all l */
-    int32_t force_householder;     /* 1: always orthonormalise by Householder QR */
+    int32_t orth;                  /* orth of Algorithms 1-4: RSVD_ORTH_AUTO (0, CholeskyQR2 with the
+                                      Householder fallback on breakdown), RSVD_ORTH_CHOLQR2 (1, CholeskyQR2
+                                      only: a breakdown is reported in info, no fallback is enqueued),
+                                      RSVD_ORTH_HOUSEHOLDER (2, always Householder QR) */
     int32_t residual_iters;        /* spectral estimate: block power iterations t on E = A - Q Q^T A,
                                       0 = default (4).  Start block: min(16, m, n) columns of the test-matrix
                                       generator on stream 2 (same seed), orthonormalised; each iteration
@@ -118,8 +126,19 @@ typedef struct {
                                       0 <= residual_iters <= 1000. */
     int32_t extra_power_pass;      /* BF16 / FP8 A: power iterations added to q; -1 = default (1);
                                       ignored for RSVD_F32 / RSVD_F64 */
+    int32_t algorithm;             /* 0 or 4: Algorithm 4 (orth after every product of the power scheme);
+                                      3: Algorithm 3 (Section 3.2): Y = A Omega, q times Y = A (A^T Y), and
+                                      orth only once, after the last product.  In FP32, sigma_1^(2q+1) must
+                                      stay inside the float range. */
+    int32_t jacobi_max_sweeps;     /* sweep cap of the small SVD's Jacobi iteration, 0 = default
+                                      (60; 30 for l > 128); reaching it sets RSVD_INFO_JACOBI_NOT_CONVERGED */
+    int32_t reserved0;
     int32_t reserved1;
 } rsvd_params;
+
+#define RSVD_ORTH_AUTO 0
+#define RSVD_ORTH_CHOLQR2 1
+#define RSVD_ORTH_HOUSEHOLDER 2
 
 /* Outputs.  r = k, or l when return_full_l is set.  U, Vt and Q have the
  * dtype of A (float for BF16 / FP8 A).  S, residual are doubles.  Q
@@ -282,10 +301,13 @@ rsvd_status rsvd_gemm(rsvd_handle* h, const rsvd_matrix* A, int32_t trans, const
 /* orth of Algorithms 1-4: Q (rows x l, ldq) = orthonormal basis of range(Y)
  * (rows x l, ldy), l <= rows, by CholeskyQR2 (FP64 Gram and Cholesky) with a
  * Householder QR fallback; diag(R) > 0 so Q is the Q factor of the thin QR.
- * info: device int32, RSVD_INFO_* flags OR-ed in (caller zeroes it). */
+ * orth_mode: RSVD_ORTH_AUTO, RSVD_ORTH_CHOLQR2 or RSVD_ORTH_HOUSEHOLDER (as
+ * rsvd_params.orth).  For FP32 Y the second CholeskyQR pass is skipped when
+ * the first factor shows that the first pass is already orthonormal to
+ * within 2^-24.  info: device int32, receives the RSVD_INFO_* flags. */
 rsvd_status rsvd_orth_workspace_size(int32_t dtype, int64_t rows, int64_t l, size_t* bytes);
 rsvd_status rsvd_orth(rsvd_handle* h, int32_t dtype, int64_t rows, int64_t l, const void* Y, int64_t ldy,
-                      void* Q, int64_t ldq, int32_t force_householder, int32_t* info,
+                      void* Q, int64_t ldq, int32_t orth_mode, int32_t* info,
                       void* workspace, size_t workspace_bytes, void* stream);
 
 #ifdef __cplusplus

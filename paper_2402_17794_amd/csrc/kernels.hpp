@@ -15,7 +15,10 @@ constexpr int kMaxSplits = 16;     // split-K slices of a product with A
 struct DevFlags {
     int orth_fail;      // CholeskyQR breakdown in the current orth -> Householder
     int info;           // RSVD_INFO_* bits accumulated over the solve
-    int pad[62];
+    int pass2_off;      // the second CholeskyQR pass of the current orth does not run
+    int fb_count;       // grid barrier of the Householder fallback: arrivals (0 between barriers)
+    int fb_gen;         // and its generation
+    int pad[59];
 };
 
 // ---- skinny products with A (gemm.hip) ----
@@ -77,36 +80,49 @@ hipError_t launch_lp_gemm(int fmt, LpGemmArgs a, hipStream_t s, hipEvent_t produ
 int gram_chunks(int64_t rows);
 size_t gram_partials_elems(int64_t rows, int L);
 int gram_pairs(int L);
+// skip (nullable): the kernel returns at once when *skip != 0.
 hipError_t launch_gram(int dtype, const void* Y, int64_t ldy, int64_t rows, int L, double* partials,
-                       const DevFlags* skip_if_fail, hipStream_t s);
+                       const int* skip, hipStream_t s);
 
 // Sum the Gram partials and factor G = R^T R, forming R^{-1} too (single
 // workgroup); R, Rinv: L x L, zero outside the leading l x l block.
-// mode 0 (orth pass 1): on breakdown set flags->orth_fail = 1 (else 0).
-// mode 1 (orth pass 2): skip if orth_fail; first-order factor when
-//                       max |G - I| <= tau; on breakdown set orth_fail = 1.
+// mode 0 (orth pass 1): on breakdown set flags->orth_fail = 1 (else 0);
+//                       flags->pass2_off = 1 on breakdown, or when
+//                       skip_tau > 0 and rows 2^-53 sum_ij G_ii Rinv_ij^2 <=
+//                       skip_tau (the first pass is already orthonormal to
+//                       below skip_tau), else 0.
+// mode 1 (orth pass 2): return at once if pass2_off; first-order factor when
+//                       max |G - I| <= tau; on breakdown set orth_fail = 1
+//                       and pass2_off = 1.
 // mode 2 (small SVD): on breakdown retry with a diagonal shift, report it in
 //                     info and store the shift in *shift_out.
+// report_breakdown (modes 0, 1): also set RSVD_INFO_ORTH_BREAKDOWN on breakdown.
 // work: L*L doubles of device scratch (used when l is too large for LDS).
 hipError_t launch_chol(const double* partials, int64_t rows, int l, int L, double* R, double* Rinv,
-                       DevFlags* flags, int mode, double* shift_out, double* work, double tau, hipStream_t s);
+                       DevFlags* flags, int mode, double* shift_out, double* work, double tau, hipStream_t s,
+                       double skip_tau = 0.0, int report_breakdown = 0);
 
 // out[rows x ncols_out] = in[rows x L] * M[L x ncols_out] with FP64 accumulation.
 // transpose_out: write out^T (ncols_out x rows, ld = ldo).  colscale (nullable):
-// multiply output column c by colscale[c].  skip_if_fail: return at once if
-// flags->orth_fail is set.  argmax (nullable, with transpose_out): per-block
+// multiply output column c by colscale[c].  skip (nullable): return at once
+// if *skip != 0.  argmax (nullable, with transpose_out): per-block
 // index/value of the largest |entry| of each output column.
 // upper: M is upper triangular (its zero blocks are skipped).
+// out may be in (same ld, no transpose): every workgroup reads all of its
+// rows before it writes them.
 hipError_t launch_apply(int dtype, const void* in, int64_t ldi, int64_t rows, int L, const double* M, int ldm,
                         int ncols_out, void* out, int64_t ldo, int transpose_out, const double* colscale,
-                        const DevFlags* skip_if_fail, double* argmax_val, int* argmax_idx, int upper,
+                        const int* skip, double* argmax_val, int* argmax_idx, int upper,
                         hipStream_t s);
 int apply_blocks(int64_t rows);
 
-// Householder QR fallback (single workgroup); runs only if flags->orth_fail
-// (or `force`).  H, Qw: rows * L doubles each.  Sets RSVD_INFO_QR_FALLBACK.
+// Householder QR fallback (TSQR tree over up to 64 workgroups); runs only if
+// flags->orth_fail (or `force`).  H, Qw: rows * L doubles each; up:
+// householder_scratch_doubles(rows, L) doubles.  Sets RSVD_INFO_QR_FALLBACK.
+size_t householder_scratch_doubles(int64_t rows, int L);
 hipError_t launch_householder(int dtype, const void* Y, int64_t ldy, int64_t rows, int l, int L, void* Q,
-                              int64_t ldq, double* H, double* Qw, DevFlags* flags, int force, hipStream_t s);
+                              int64_t ldq, double* H, double* Qw, double* up, DevFlags* flags, int force,
+                              hipStream_t s);
 
 // ---- small SVD and finishing (svd.hip) ----
 // One-sided Jacobi on X = R^T (l x l, from the Cholesky factor of B B^T).
@@ -115,8 +131,10 @@ hipError_t launch_householder(int dtype, const void* Y, int64_t ldy, int64_t row
 // work: kJacobiWorkDoubles doubles of device scratch (used when l > 128).
 constexpr int kJacobiBlockSweeps = 30;                   // sweep cap of the l > 128 form
 constexpr size_t kJacobiWorkDoubles = (size_t)kMaxL * kMaxL + kJacobiBlockSweeps + 8;
+// max_sweeps: sweep cap (0 = the default of the form); reaching it sets
+// RSVD_INFO_JACOBI_NOT_CONVERGED.
 hipError_t launch_jacobi(const double* R, int l, int L, const double* shift, double* sigma, double* Ut,
-                         double* Mv, DevFlags* flags, double* work, hipStream_t s);
+                         double* Mv, DevFlags* flags, double* work, hipStream_t s, int max_sweeps = 0);
 
 // Reduce the per-block argmax partials of the V columns, choose signs,
 // write S (r values) and sign[c].

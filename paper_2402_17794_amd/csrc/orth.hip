@@ -47,8 +47,8 @@ constexpr int kGramWaves = 16;
 template <typename T>
 __global__ __launch_bounds__(64 * kGramWaves) void gram_kernel(const T* __restrict__ Y, int64_t ldy, int64_t rows,
                                                                int L, int nchunks, double* __restrict__ part,
-                                                               const DevFlags* skip) {
-    if (skip && skip->orth_fail) return;
+                                                               const int* skip) {
+    if (skip && *skip) return;
     const int nt = L / 16;
     const int npairs = nt * (nt + 1) / 2;
     const int pair = blockIdx.x % npairs;
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(64 * kGramWaves) void gram_kernel(const T* __restri
 }
 
 hipError_t launch_gram(int dtype, const void* Y, int64_t ldy, int64_t rows, int L, double* partials,
-                       const DevFlags* skip, hipStream_t s) {
+                       const int* skip, hipStream_t s) {
     const int nchunks = gram_chunks(rows);
     dim3 grid(nchunks * gram_pairs(L));
     if (dtype == 0)
@@ -157,16 +157,56 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
     return y;
 }
 
+// End of a Cholesky kernel (modes 0, 1): the orth flags, and in mode 0 the
+// test that decides whether the second CholeskyQR pass can still improve
+// Q1 = Y R^{-1}.  Rounding in the FP64 Gram perturbs G by at most about
+// rows 2^-53 |Y|^T |Y|, which leaves Q1^T Q1 - I at most about
+// rows 2^-53 ||D R^{-1}||_F^2 (D = diag of the column norms of Y,
+// D_ii^2 = G_ii); the Cholesky factorisation and the FP64 apply add far less.
+// Below skip_tau the second pass is switched off.  R^{-1} is read back from
+// global memory, where this workgroup has just written it.  Every thread of
+// the workgroup calls this (block_sum has barriers).
+// part: this thread's share of sum_ij G_ii Rinv_ij^2 when the kernel has
+// accumulated it while writing R^{-1} (else negative: R^{-1} is read back).
+__device__ void chol_finish_orth(DevFlags* flags, int mode, bool broke, const double* Rinv, const double* dg, int l,
+                                 int L, double skip_scale, double skip_tau, int report, double* red,
+                                 double part = -1.0) {
+    bool off = broke;
+    if (mode == 0 && !broke && skip_tau > 0.0) {
+        double sum = part;
+        if (part < 0.0) {
+            __syncthreads();
+            sum = 0.0;
+            for (int idx = threadIdx.x; idx < L * L; idx += blockDim.x) {
+                const int x = idx / L;
+                if (x < l) {
+                    const double v = Rinv[idx];
+                    sum = fma(dg[x] * v, v, sum);
+                }
+            }
+        }
+        sum = block_sum(sum, red);
+        off = skip_scale * sum <= skip_tau;
+    }
+    if (threadIdx.x == 0) {
+        flags->orth_fail = broke ? 1 : 0;
+        flags->pass2_off = off ? 1 : 0;
+        if (broke && report) atomicOr(&flags->info, RSVD_INFO_ORTH_BREAKDOWN);
+    }
+}
+
 __global__ __launch_bounds__(1024) void chol_blk_kernel(const double* __restrict__ part, int nchunks, int l, int L,
                                                         double* __restrict__ R, double* __restrict__ Rinv,
                                                         DevFlags* flags, int mode, double* shift_out,
-                                                        double* __restrict__ A, double tau) {
+                                                        double* __restrict__ A, double tau, double skip_scale,
+                                                        double skip_tau, int report) {
     __shared__ double Dinv[kCholBlkNt][256];        // R_pp^{-1} of every diagonal block (row-major 16 x 16)
     __shared__ double Prow[16 * kCholBlkLd];        // the current panel rows R_p. (16 x L)
     __shared__ double dg[kMaxL];
+    __shared__ double red[16];
     __shared__ unsigned long long s_emax;
     __shared__ int s_nonfinite, s_broke;
-    if (mode == 1 && flags->orth_fail) return;
+    if (mode == 1 && flags->pass2_off) return;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int nt = L / 16, npairs = nt * (nt + 1) / 2, stride = npairs * 256;
     const int li = lane & 15, lk = lane >> 4;       // MFMA operand coordinates
@@ -371,13 +411,12 @@ __global__ __launch_bounds__(1024) void chol_blk_kernel(const double* __restrict
             }
         }
     }
+    if (mode != 2) chol_finish_orth(flags, mode, broke, Rinv, dg, l, L, skip_scale, skip_tau, report, red);
     if (tid == 0) {
         if (mode == 2) {
             *shift_out = shift;
             if (shift > 0.0) atomicOr(&flags->info, RSVD_INFO_SHIFTED_CHOLESKY);
             if (broke) atomicOr(&flags->info, RSVD_INFO_NONFINITE);
-        } else {
-            flags->orth_fail = broke ? 1 : 0;
         }
         if (nonfinite) atomicOr(&flags->info, RSVD_INFO_NONFINITE);
     }
@@ -406,7 +445,8 @@ constexpr int kCholT = 6;                         // tile edge: 2 * nb (nb + 1) 
 __global__ __launch_bounds__(kCholThreads) void chol_rl_kernel(const double* __restrict__ part, int nchunks, int l,
                                                                int L, double* __restrict__ R,
                                                                double* __restrict__ Rinv, DevFlags* flags, int mode,
-                                                               double* shift_out, double tau) {
+                                                               double* shift_out, double tau, double skip_scale,
+                                                               double skip_tau, int report) {
     constexpr int T = kCholT, NBM = (kCholLdsMax + kCholT - 1) / kCholT;
     // Row stride: slots up to NBM * T (the padded tile columns), odd for bank spread.
     constexpr int LP = NBM * T + 1;
@@ -415,9 +455,10 @@ __global__ __launch_bounds__(kCholThreads) void chol_rl_kernel(const double* __r
     __shared__ double RD[NBM * T * T];            // right half of the diagonal blocks: RD[blk][a][b]
     __shared__ double dg[kCholLdsMax];
     __shared__ double isd[kCholLdsMax];           // D_j^{-1/2}
+    __shared__ double red[kCholThreads / 64];
     __shared__ unsigned long long s_emax;
     __shared__ int s_nonfinite;
-    if (mode == 1 && flags->orth_fail) return;
+    if (mode == 1 && flags->pass2_off) return;
     const int tid = threadIdx.x;
     const int nt = L / 16, npairs = nt * (nt + 1) / 2, stride = npairs * 256;
     // Tile of this thread: tid < ntri -> left tile (bi, bj), bj >= bi; then right tile (bi, bj), bj <= bi.
@@ -588,13 +629,12 @@ __global__ __launch_bounds__(kCholThreads) void chol_rl_kernel(const double* __r
             out[x * L + y] = val;
         }
     }
+    if (mode != 2) chol_finish_orth(flags, mode, broke, Rinv, dg, l, L, skip_scale, skip_tau, report, red);
     if (tid == 0) {
         if (mode == 2) {
             *shift_out = shift;
             if (shift > 0.0) atomicOr(&flags->info, RSVD_INFO_SHIFTED_CHOLESKY);
             if (broke) atomicOr(&flags->info, RSVD_INFO_NONFINITE);
-        } else {
-            flags->orth_fail = broke ? 1 : 0;
         }
         if (nonfinite) atomicOr(&flags->info, RSVD_INFO_NONFINITE);
     }
@@ -628,14 +668,16 @@ constexpr int kTileSz = 16 * kTileLd;
 __global__ __launch_bounds__(kCholThreads) void chol_mfma_kernel(const double* __restrict__ part, int nchunks, int l,
                                                                  int L, double* __restrict__ R,
                                                                  double* __restrict__ Rinv, DevFlags* flags, int mode,
-                                                                 double* shift_out, double tau) {
+                                                                 double* shift_out, double tau, double skip_scale,
+                                                                 double skip_tau, int report) {
     constexpr int NTT = kCholMfmaMaxNt * (kCholMfmaMaxNt + 1) / 2;
     __shared__ double Gt[NTT * kTileSz];        // left tiles (a, b), a <= b
     __shared__ double Mt[NTT * kTileSz];        // right tiles (q, c), c <= q
     __shared__ double dg[16 * kCholMfmaMaxNt];
+    __shared__ double red[kCholThreads / 64];
     __shared__ unsigned long long s_emax;
     __shared__ int s_nonfinite, s_broke;
-    if (mode == 1 && flags->orth_fail) return;
+    if (mode == 1 && flags->pass2_off) return;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = kCholThreads / 64;
     const int li = lane & 15, lk = lane >> 4;
     const int nt = L / 16, npairs = nt * (nt + 1) / 2, stride = npairs * 256;
@@ -821,38 +863,45 @@ __global__ __launch_bounds__(kCholThreads) void chol_mfma_kernel(const double* _
         shift = (shift == 0.0) ? gmax * 0x1.0p-40 : shift * 1024.0;
         if (!(shift > 0.0)) shift = 0x1.0p-1000;
     }
+    double ssum = 0.0;                          // sum of G_ii Rinv_ij^2 over this thread's entries
     if (!broke) {
         for (int idx = tid; idx < L * L; idx += kCholThreads) {
             const int x = idx / L, y = idx - x * L;
             const bool in = x <= y && y < l;
-            if (mode == 2) R[idx] = in ? gt(x >> 4, y >> 4)[(x & 15) * kTileLd + (y & 15)] : 0.0;
-            else Rinv[idx] = in ? mt(y >> 4, x >> 4)[(y & 15) * kTileLd + (x & 15)] : 0.0;
+            if (mode == 2) {
+                R[idx] = in ? gt(x >> 4, y >> 4)[(x & 15) * kTileLd + (y & 15)] : 0.0;
+            } else {
+                const double v = in ? mt(y >> 4, x >> 4)[(y & 15) * kTileLd + (x & 15)] : 0.0;
+                Rinv[idx] = v;
+                if (in) ssum = fma(dg[x] * v, v, ssum);
+            }
         }
     }
+    if (mode != 2) chol_finish_orth(flags, mode, broke, Rinv, dg, l, L, skip_scale, skip_tau, report, red, ssum);
     if (tid == 0) {
         if (mode == 2) {
             *shift_out = shift;
             if (shift > 0.0) atomicOr(&flags->info, RSVD_INFO_SHIFTED_CHOLESKY);
             if (broke) atomicOr(&flags->info, RSVD_INFO_NONFINITE);
-        } else {
-            flags->orth_fail = broke ? 1 : 0;
         }
         if (nonfinite) atomicOr(&flags->info, RSVD_INFO_NONFINITE);
     }
 }
 
 hipError_t launch_chol(const double* partials, int64_t rows, int l, int L, double* R, double* Rinv, DevFlags* flags,
-                       int mode, double* shift_out, double* work, double tau, hipStream_t s) {
+                       int mode, double* shift_out, double* work, double tau, hipStream_t s, double skip_tau,
+                       int report_breakdown) {
     const int nchunks = gram_chunks(rows);
+    const double skip_scale = (double)rows * 0x1.0p-53;
     if (L <= 16 * kCholMfmaMaxNt)
         hipLaunchKernelGGL(chol_mfma_kernel, dim3(1), dim3(kCholThreads), 0, s, partials, nchunks, l, L, R, Rinv, flags,
-                           mode, shift_out, tau);
+                           mode, shift_out, tau, skip_scale, skip_tau, report_breakdown);
     else if (l <= kCholLdsMax)
         hipLaunchKernelGGL(chol_rl_kernel, dim3(1), dim3(kCholThreads), 0, s, partials, nchunks, l, L, R, Rinv, flags,
-                           mode, shift_out, tau);
+                           mode, shift_out, tau, skip_scale, skip_tau, report_breakdown);
     else
         hipLaunchKernelGGL(chol_blk_kernel, dim3(1), dim3(1024), 0, s, partials, nchunks, l, L, R, Rinv, flags,
-                           mode, shift_out, work, tau);
+                           mode, shift_out, work, tau, skip_scale, skip_tau, report_breakdown);
     return hipGetLastError();
 }
 
@@ -868,13 +917,13 @@ constexpr int kApplyRows = 32;
 int apply_blocks(int64_t rows) { return (int)ceil_div(rows, kApplyRows); }
 
 template <typename T, int CT>
-__global__ __launch_bounds__(256) void apply_kernel(const T* __restrict__ in, int64_t ldi, int64_t rows, int L,
+__global__ __launch_bounds__(256) void apply_kernel(const T* in, int64_t ldi, int64_t rows, int L,
                                                     const double* __restrict__ M, int ldm, int ncols_out,
-                                                    T* __restrict__ out, int64_t ldo, int transpose_out,
-                                                    const double* __restrict__ colscale, const DevFlags* skip,
+                                                    T* out, int64_t ldo, int transpose_out,
+                                                    const double* __restrict__ colscale, const int* skip,
                                                     double* __restrict__ amax_val, int* __restrict__ amax_idx,
                                                     int upper) {
-    if (skip && skip->orth_fail) return;
+    if (skip && *skip) return;
     constexpr int W = CT * 16;
     constexpr int NTW = (CT + 1) / 2;                  // column tiles per wavefront
     constexpr int NM = (16 * W + 255) / 256;           // M elements per thread per slice
@@ -969,13 +1018,13 @@ __global__ __launch_bounds__(256) void apply_kernel(const T* __restrict__ in, in
 constexpr int kApplyLdsMax = 128;
 
 template <typename T, int CT>
-__global__ __launch_bounds__(256) void apply_lds_kernel(const T* __restrict__ in, int64_t ldi, int64_t rows, int L,
+__global__ __launch_bounds__(256) void apply_lds_kernel(const T* in, int64_t ldi, int64_t rows, int L,
                                                         const double* __restrict__ M, int ldm, int ncols_out,
-                                                        T* __restrict__ out, int64_t ldo, int transpose_out,
-                                                        const double* __restrict__ colscale, const DevFlags* skip,
+                                                        T* out, int64_t ldo, int transpose_out,
+                                                        const double* __restrict__ colscale, const int* skip,
                                                         double* __restrict__ amax_val, int* __restrict__ amax_idx,
                                                         int upper) {
-    if (skip && skip->orth_fail) return;
+    if (skip && *skip) return;
     constexpr int W = CT * 16;
     constexpr int NTW = (CT + 1) / 2;
     constexpr int SI = kApplyLdsMax + 1;               // row stride of the input rows (odd)
@@ -1085,7 +1134,7 @@ __global__ __launch_bounds__(256) void apply_lds_kernel(const T* __restrict__ in
 template <typename T>
 static hipError_t apply_lds_dispatch(int CT, dim3 grid, hipStream_t s, const T* in, int64_t ldi, int64_t rows, int L,
                                      const double* M, int ldm, int ncols_out, T* out, int64_t ldo, int tr,
-                                     const double* colscale, const DevFlags* skip, double* av, int* ai, int upper) {
+                                     const double* colscale, const int* skip, double* av, int* ai, int upper) {
 #define RSVD_CT_CASE(N)                                                                                          \
     case N:                                                                                                      \
         hipLaunchKernelGGL((apply_lds_kernel<T, N>), grid, dim3(256), 0, s, in, ldi, rows, L, M, ldm, ncols_out,  \
@@ -1103,7 +1152,7 @@ static hipError_t apply_lds_dispatch(int CT, dim3 grid, hipStream_t s, const T* 
 template <typename T>
 static hipError_t apply_dispatch(int CT, dim3 grid, hipStream_t s, const T* in, int64_t ldi, int64_t rows, int L,
                                  const double* M, int ldm, int ncols_out, T* out, int64_t ldo, int tr,
-                                 const double* colscale, const DevFlags* skip, double* av, int* ai, int upper) {
+                                 const double* colscale, const int* skip, double* av, int* ai, int upper) {
 #define RSVD_CT_CASE(N)                                                                                         \
     case N:                                                                                                     \
         hipLaunchKernelGGL((apply_kernel<T, N>), grid, dim3(256),                                               \
@@ -1122,7 +1171,7 @@ static hipError_t apply_dispatch(int CT, dim3 grid, hipStream_t s, const T* in, 
 
 hipError_t launch_apply(int dtype, const void* in, int64_t ldi, int64_t rows, int L, const double* M, int ldm,
                         int ncols_out, void* out, int64_t ldo, int transpose_out, const double* colscale,
-                        const DevFlags* skip, double* av, int* ai, int upper, hipStream_t s) {
+                        const int* skip, double* av, int* ai, int upper, hipStream_t s) {
     if (rows == 0 || ncols_out == 0) return hipSuccess;
     const int CT = (int)ceil_div(ncols_out, 16);
     dim3 grid(apply_blocks(rows));
@@ -1141,81 +1190,284 @@ hipError_t launch_apply(int dtype, const void* in, int64_t ldi, int64_t rows, in
 }
 
 // ---------------------------------------------------------- Householder --
-// Fallback thin QR by Householder reflections in one workgroup of 16
-// wavefronts, working in FP64 in device scratch (H: reflectors / R,
-// Qw: the explicit Q).  Column j: reflect the trailing part onto
-// -sign(x_0) |x| e_1 and apply the reflector to the trailing columns
-// (wavefront c handles columns c, c + 16, ...).  Q is formed by applying the
-// reflectors last to first to the first l columns of the identity; columns
-// whose diagonal of R is negative are negated so that diag(R) >= 0.
-template <typename T>
-__global__ __launch_bounds__(1024) void householder_kernel(const T* __restrict__ Y, int64_t ldy, int64_t rows, int l,
-                                                           int L, T* __restrict__ Q, int64_t ldq,
-                                                           double* __restrict__ H, double* __restrict__ Qw,
-                                                           DevFlags* flags, int force, int pad_cols) {
-    if (!force && !flags->orth_fail) return;
-    __shared__ double tau[kMaxL], beta[kMaxL], red[16];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int64_t idx = tid; idx < rows * L; idx += 1024) {
-        const int64_t i = idx / L;
-        const int c = (int)(idx % L);
-        H[idx] = c < l ? (double)Y[i * ldy + c] : 0.0;
-        Qw[idx] = (c < l && i == c) ? 1.0 : 0.0;
+// Fallback thin QR by Householder reflections, for a Y that CholeskyQR
+// cannot factor (rank-deficient, zero, or too ill-conditioned), as a TSQR
+// tree on many workgroups.  Level 1 splits the rows into G1 <= 64 chunks of
+// at least L rows; each workgroup factors its chunk Y_c = Q_c R_c.  Each
+// higher level stacks up to 8 of the R factors below it and factors the
+// stack, until one factor R remains (the root).  Q is then formed top down:
+// the root's reflectors applied to the first l columns of the identity give
+// M (a stack of L x L blocks); each tile below applies its reflectors to
+// [its block of M; 0], and at level 1 that is the tile's rows of Q.  Columns
+// whose root diagonal entry of R is negative are negated (diag(R) >= 0).
+// All work is FP64 in device scratch: H (level-1 reflectors, rows x L),
+// Qw (level-1 Q, rows x L) and `up` (the stacks and M blocks of the higher
+// levels, the tau and beta vectors of every level).
+//
+// The levels are separated by a grid-wide barrier (one counter and one
+// generation word in the flags block, counter zero between barriers), so
+// the kernel is launched with one workgroup per level-1 chunk (<= 64
+// workgroups of 512 threads, all resident at once on 256 compute units);
+// the waits are bounded, and a barrier that does not complete sets
+// RSVD_INFO_FALLBACK_TIMEOUT instead of hanging.  When the CholeskyQR
+// passes succeeded (and the fallback is not forced) every workgroup returns
+// at once.
+constexpr int kHhThreads = 512;
+constexpr int kHhMaxChunks = 64;
+constexpr int kHhFanIn = 4;
+constexpr int kHhMaxLevels = 4;             // 64 -> 16 -> 4 -> 1
+// Reflectors of tiles up to kHhVsMax rows are staged in LDS (128 KB, one
+// workgroup per compute unit); longer level-1 chunks (more than about a
+// million rows) read them in place.
+constexpr int kHhVsMax = 16384;
+
+struct HhTree {
+    int nlev;
+    int n[kHhMaxLevels + 1];                // tiles per level (index 1..nlev)
+    int64_t s_off[kHhMaxLevels + 1];        // level h >= 2: stack of level h (n[h-1] L rows, L columns)
+    int64_t m_off[kHhMaxLevels + 1];        // level h >= 2: M blocks of level h (same shape)
+    int64_t t_off[kHhMaxLevels + 1];        // tau of level h (n[h] L), beta follows (n[h] L)
+    int64_t total;                          // doubles of `up`
+};
+
+static HhTree hh_tree(int64_t rows, int L) {
+    HhTree t{};
+    t.n[1] = (int)std::max<int64_t>(1, std::min<int64_t>(kHhMaxChunks, rows / L));
+    t.nlev = 1;
+    while (t.n[t.nlev] > 1) {
+        t.n[t.nlev + 1] = (t.n[t.nlev] + kHhFanIn - 1) / kHhFanIn;
+        ++t.nlev;
+    }
+    int64_t off = 0;
+    for (int h = 2; h <= t.nlev; ++h) {
+        t.s_off[h] = off;
+        off += (int64_t)t.n[h - 1] * L * L;
+        t.m_off[h] = off;
+        off += (int64_t)t.n[h - 1] * L * L;
+    }
+    for (int h = 1; h <= t.nlev; ++h) {
+        t.t_off[h] = off;
+        off += 2 * (int64_t)t.n[h] * L;
+    }
+    t.total = off;
+    return t;
+}
+
+size_t householder_scratch_doubles(int64_t rows, int L) { return (size_t)hh_tree(rows, L).total; }
+
+// Bounded grid barrier for `nblocks` workgroups: the last arrival resets the
+// counter and bumps the generation; agent-scope fences order every
+// workgroup's global writes before the barrier with the reads after it.
+__device__ void hh_grid_sync(DevFlags* flags, int nblocks) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned* ctr = reinterpret_cast<unsigned*>(&flags->fb_count);
+        unsigned* gen = reinterpret_cast<unsigned*>(&flags->fb_gen);
+        const unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        if (atomicAdd(ctr, 1u) == (unsigned)nblocks - 1u) {
+            __hip_atomic_store(ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned spins = 0;
+            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(8);
+                if (++spins == (1u << 24)) {              // about a second: give up, report it
+                    atomicOr(&flags->info, RSVD_INFO_FALLBACK_TIMEOUT);
+                    break;
+                }
+            }
+        }
+        __threadfence();
     }
     __syncthreads();
-    for (int j = 0; j < l; ++j) {
+}
+
+// Inner products and updates of one column c with the current reflector v
+// (v[i * vst], rows j..nr-1: in LDS with vst = 1, or in place in the tile
+// with vst = L), lanes striding the rows with four independent loads in
+// flight: w = v^T X[:, c] summed over the wavefront, then X[:, c] -= (tau w) v.
+__device__ __forceinline__ void hh_reflect_column(double* X, const double* v, int vst, int j, int nr, int L, int c,
+                                                  double tj) {
+    const int lane = threadIdx.x & 63;
+    const int64_t sv = vst;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int i = j + lane;
+    for (; i + 192 < nr; i += 256) {
+        const double x0 = X[(int64_t)i * L + c], x1 = X[(int64_t)(i + 64) * L + c];
+        const double x2 = X[(int64_t)(i + 128) * L + c], x3 = X[(int64_t)(i + 192) * L + c];
+        a0 = fma(v[i * sv], x0, a0);
+        a1 = fma(v[(i + 64) * sv], x1, a1);
+        a2 = fma(v[(i + 128) * sv], x2, a2);
+        a3 = fma(v[(i + 192) * sv], x3, a3);
+    }
+    for (; i < nr; i += 64) a0 = fma(v[i * sv], X[(int64_t)i * L + c], a0);
+    const double w = wave_sum((a0 + a1) + (a2 + a3)) * tj;
+    i = j + lane;
+    for (; i + 192 < nr; i += 256) {
+        const double x0 = X[(int64_t)i * L + c], x1 = X[(int64_t)(i + 64) * L + c];
+        const double x2 = X[(int64_t)(i + 128) * L + c], x3 = X[(int64_t)(i + 192) * L + c];
+        X[(int64_t)i * L + c] = fma(-w, v[i * sv], x0);
+        X[(int64_t)(i + 64) * L + c] = fma(-w, v[(i + 64) * sv], x1);
+        X[(int64_t)(i + 128) * L + c] = fma(-w, v[(i + 128) * sv], x2);
+        X[(int64_t)(i + 192) * L + c] = fma(-w, v[(i + 192) * sv], x3);
+    }
+    for (; i < nr; i += 64) X[(int64_t)i * L + c] = fma(-w, v[i * sv], X[(int64_t)i * L + c]);
+}
+
+// Householder QR in place of the tile T (nr rows, row stride L, FP64): for
+// column j < min(nr, l), the reflector v (v_0 on the diagonal, the rest
+// below it) with tau_j = 2 / v^T v maps the trailing part of column j onto
+// beta_j e_1; the trailing columns c < l are updated (one wavefront per
+// column).  Above the diagonal T then holds R; beta holds its diagonal.
+// vs: LDS for nr doubles.
+__device__ void hh_factor_tile(double* T, int nr, int L, int l, double* tau, double* beta, double* red, double* vs) {
+    const int tid = threadIdx.x, wave = tid >> 6, nw = blockDim.x >> 6;
+    const int jmax = min(nr, l);
+    const bool in_lds = nr <= kHhVsMax;
+    for (int j = 0; j < jmax; ++j) {
         double s = 0.0;
-        for (int64_t i = j + tid; i < rows; i += 1024) s += H[i * L + j] * H[i * L + j];
-        s = block_sum(s, red);
-        const double alpha = H[(int64_t)j * L + j];
+        for (int i = j + tid; i < nr; i += blockDim.x) {
+            const double x = T[(int64_t)i * L + j];
+            if (in_lds) vs[i] = x;
+            s = fma(x, x, s);
+        }
+        s = block_sum(s, red);                      // its barriers also publish vs
+        const double alpha = T[(int64_t)j * L + j];
         const double normx = sqrt(s);
-        __syncthreads();
         if (normx == 0.0) {
             if (tid == 0) { tau[j] = 0.0; beta[j] = 0.0; }
+            __syncthreads();
             continue;
         }
         const double bj = alpha >= 0.0 ? -normx : normx;
         const double v0 = alpha - bj;
-        const double vtv = s - alpha * alpha + v0 * v0;
-        const double tj = 2.0 / vtv;
-        if (tid == 0) { H[(int64_t)j * L + j] = v0; tau[j] = tj; beta[j] = bj; }
+        const double tj = 2.0 / (s - alpha * alpha + v0 * v0);
         __syncthreads();
-        for (int c = j + 1 + wave; c < l; c += 16) {
-            double w = 0.0;
-            for (int64_t i = j + lane; i < rows; i += 64) w += H[i * L + j] * H[i * L + c];
-            w = wave_sum(w) * tj;
-            for (int64_t i = j + lane; i < rows; i += 64) H[i * L + c] -= w * H[i * L + j];
+        if (tid == 0) {
+            T[(int64_t)j * L + j] = v0;
+            if (in_lds) vs[j] = v0;
+            tau[j] = tj;
+            beta[j] = bj;
         }
         __syncthreads();
+        const double* v = in_lds ? vs : T + j;
+        for (int c = j + 1 + wave; c < l; c += nw) hh_reflect_column(T, v, in_lds ? 1 : L, j, nr, L, c, tj);
+        __syncthreads();
     }
-    for (int j = l - 1; j >= 0; --j) {
+}
+
+// Z (nr x L) <- H_0 H_1 ... H_{jmax-1} Z with the reflectors of tile T (as
+// left by hh_factor_tile), columns c < l only.  vs: LDS for nr doubles.
+__device__ void hh_apply_tile(const double* T, int nr, int L, int l, const double* tau, double* Z, double* vs) {
+    const int tid = threadIdx.x, wave = tid >> 6, nw = blockDim.x >> 6;
+    const int jmax = min(nr, l);
+    const bool in_lds = nr <= kHhVsMax;
+    for (int j = jmax - 1; j >= 0; --j) {
         const double tj = tau[j];
-        if (tj == 0.0) continue;
-        for (int c = j + wave; c < l; c += 16) {
-            double w = 0.0;
-            for (int64_t i = j + lane; i < rows; i += 64) w += H[i * L + j] * Qw[i * L + c];
-            w = wave_sum(w) * tj;
-            for (int64_t i = j + lane; i < rows; i += 64) Qw[i * L + c] -= w * H[i * L + j];
-        }
+        if (tj == 0.0) continue;                    // same value in every thread
+        if (in_lds)
+            for (int i = j + tid; i < nr; i += blockDim.x) vs[i] = T[(int64_t)i * L + j];
+        __syncthreads();
+        const double* v = in_lds ? vs : T + j;
+        for (int c = wave; c < l; c += nw) hh_reflect_column(Z, v, in_lds ? 1 : L, j, nr, L, c, tj);
         __syncthreads();
     }
-    for (int64_t idx = tid; idx < rows * L; idx += 1024) {
-        const int64_t i = idx / L;
-        const int c = (int)(idx % L);
-        if (c < l) Q[i * ldq + c] = (T)(beta[c] < 0.0 ? -Qw[idx] : Qw[idx]);
-        else if (c < pad_cols) Q[i * ldq + c] = (T)0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kHhThreads) void householder_kernel(const T* __restrict__ Y, int64_t ldy, int64_t rows,
+                                                                 int l, int L, T* __restrict__ Q, int64_t ldq,
+                                                                 double* __restrict__ H, double* __restrict__ Qw,
+                                                                 double* __restrict__ up, DevFlags* flags, int force,
+                                                                 HhTree tr) {
+    if (!force && !flags->orth_fail) return;
+    __shared__ double red[kHhThreads / 64];
+    __shared__ double vs[kHhVsMax];                 // the current reflector (tile rows <= kHhVsMax)
+    const int tid = threadIdx.x, b = blockIdx.x, G = gridDim.x;
+    auto chunk = [&](int c) { return (int64_t)c * rows / tr.n[1]; };     // level-1 chunk c: rows [chunk(c), chunk(c+1))
+    auto tile_rows = [&](int h, int t) -> int {                           // rows of tile t at level h >= 2
+        return (min(kHhFanIn * (t + 1), tr.n[h - 1]) - kHhFanIn * t) * L;
+    };
+    auto tile_base = [&](int h, int t) -> double* {                       // stack of level h, tile t
+        return h == 1 ? H + chunk(t) * L : up + tr.s_off[h] + (int64_t)kHhFanIn * t * L * L;
+    };
+    auto m_base = [&](int h, int t) -> double* {                          // M of level h, tile t
+        return h == 1 ? Qw + chunk(t) * L : up + tr.m_off[h] + (int64_t)kHhFanIn * t * L * L;
+    };
+    auto nrows = [&](int h, int t) -> int { return h == 1 ? (int)(chunk(t + 1) - chunk(t)) : tile_rows(h, t); };
+
+    // Up the tree: factor, and pass R to the parent's stack.
+    for (int h = 1; h <= tr.nlev; ++h) {
+        if (b < tr.n[h]) {
+            double* Tt = tile_base(h, b);
+            const int nr = nrows(h, b);
+            if (h == 1) {
+                const int64_t r0 = chunk(b);
+                for (int64_t idx = tid; idx < (int64_t)nr * L; idx += kHhThreads) {
+                    const int64_t i = idx / L;
+                    const int c = (int)(idx % L);
+                    Tt[idx] = c < l ? (double)Y[(r0 + i) * ldy + c] : 0.0;
+                }
+                __syncthreads();
+            }
+            double* tau = up + tr.t_off[h] + (int64_t)b * L;
+            double* beta = tau + (int64_t)tr.n[h] * L;
+            hh_factor_tile(Tt, nr, L, l, tau, beta, red, vs);
+            if (h < tr.nlev) {                          // R of this tile -> block b of the level h + 1 stack
+                double* Rp = up + tr.s_off[h + 1] + (int64_t)b * L * L;
+                for (int idx = tid; idx < L * L; idx += kHhThreads) {
+                    const int x = idx / L, c = idx - x * L;
+                    double v = 0.0;
+                    if (x < nr && c < l) v = c == x ? beta[x] : (c > x ? Tt[(int64_t)x * L + c] : 0.0);
+                    Rp[idx] = v;
+                }
+            }
+        }
+        if (h < tr.nlev) hh_grid_sync(flags, G);
     }
-    if (tid == 0) atomicOr(&flags->info, RSVD_INFO_QR_FALLBACK);
+    // Down the tree: M of the root from the identity, then each tile's block.
+    const double* beta_root = up + tr.t_off[tr.nlev] + (int64_t)tr.n[tr.nlev] * L;
+    for (int h = tr.nlev; h >= 1; --h) {
+        if (b < tr.n[h]) {
+            const int nr = nrows(h, b);
+            double* Z = m_base(h, b);
+            const double* Min = h == tr.nlev ? nullptr : up + tr.m_off[h + 1] + (int64_t)b * L * L;
+            for (int64_t idx = tid; idx < (int64_t)nr * L; idx += kHhThreads) {
+                const int64_t i = idx / L;
+                const int c = (int)(idx % L);
+                double v = 0.0;
+                if (i < L) v = Min ? Min[idx] : ((i == c && c < l) ? 1.0 : 0.0);
+                Z[idx] = v;
+            }
+            __syncthreads();
+            const double* tau = up + tr.t_off[h] + (int64_t)b * L;
+            hh_apply_tile(tile_base(h, b), nr, L, l, tau, Z, vs);
+            if (h == 1) {                               // this chunk's rows of Q, signs from the root's R
+                const int64_t r0 = chunk(b);
+                for (int64_t idx = tid; idx < (int64_t)nr * L; idx += kHhThreads) {
+                    const int64_t i = idx / L;
+                    const int c = (int)(idx % L);
+                    Q[(r0 + i) * ldq + c] = c < l ? (T)(beta_root[c] < 0.0 ? -Z[idx] : Z[idx]) : (T)0;
+                }
+            }
+        }
+        if (h > 1) hh_grid_sync(flags, G);
+    }
+    if (tid == 0 && b == 0) atomicOr(&flags->info, RSVD_INFO_QR_FALLBACK);
 }
 
 hipError_t launch_householder(int dtype, const void* Y, int64_t ldy, int64_t rows, int l, int L, void* Q,
-                              int64_t ldq, double* H, double* Qw, DevFlags* flags, int force, hipStream_t s) {
+                              int64_t ldq, double* H, double* Qw, double* up, DevFlags* flags, int force,
+                              hipStream_t s) {
+    const HhTree tr = hh_tree(rows, L);
+    dim3 grid(tr.n[1]);
     if (dtype == 0)
-        hipLaunchKernelGGL(householder_kernel<double>, dim3(1), dim3(1024), 0, s, (const double*)Y, ldy, rows, l, L,
-                           (double*)Q, ldq, H, Qw, flags, force, L);
+        hipLaunchKernelGGL(householder_kernel<double>, grid, dim3(kHhThreads), 0, s, (const double*)Y, ldy, rows, l, L,
+                           (double*)Q, ldq, H, Qw, up, flags, force, tr);
     else
-        hipLaunchKernelGGL(householder_kernel<float>, dim3(1), dim3(1024), 0, s, (const float*)Y, ldy, rows, l, L,
-                           (float*)Q, ldq, H, Qw, flags, force, L);
+        hipLaunchKernelGGL(householder_kernel<float>, grid, dim3(kHhThreads), 0, s, (const float*)Y, ldy, rows, l, L,
+                           (float*)Q, ldq, H, Qw, up, flags, force, tr);
     return hipGetLastError();
 }
 

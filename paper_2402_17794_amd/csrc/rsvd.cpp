@@ -93,7 +93,7 @@ struct Plan {
     int L = 0;
     int ncounters = 0;
     int splits_nn = 1, splits_tn = 1;
-    size_t counters, flags, part, Y, Q, W, Q1, GP, R, Rinv, Ut, Mv, sigma, shift, sign, amax_val, amax_idx, H, Qw,
+    size_t counters, flags, part, Y, Q, W, GP, R, Rinv, Ut, Mv, sigma, shift, sign, amax_val, amax_idx, H, Qw,
         work, res_part, res;
     // Low-precision A: format, prepared operand (L x ldt) and its scales.
     int afmt = 0;
@@ -138,11 +138,13 @@ bool make_plan(int adtype, int64_t m, int64_t n, int64_t k, int64_t p, int64_t q
         plp = std::max(lp_partials_elems(m, n, P.L, &P.splits_lp_nn), lp_partials_elems(n, m, P.L, &P.splits_lp_tn));
         P.ldt = round_up(mx, 64);
     }
-    P.part = c.take(es * std::max<size_t>({pn, pt, pn16, pt16, plp, 1}));
+    // The split-K partials are idle during an orthonormalisation, so the
+    // Householder fallback's tree levels share their space.
+    P.part = c.take(std::max(es * std::max<size_t>({pn, pt, pn16, pt16, plp, 1}),
+                             sizeof(double) * householder_scratch_doubles(mx, P.L)));
     P.Y = c.take(es * (size_t)mx * P.L);
     P.Q = c.take(es * (size_t)m * P.L);
     P.W = c.take(es * (size_t)n * P.L);
-    P.Q1 = c.take(es * (size_t)mx * P.L);
     P.GP = c.take(sizeof(double) * std::max(gram_partials_elems(mx, P.L),
                                             spectral ? gram_partials_elems(m, P.L + kSpecBlock) : 0));
     P.R = c.take(sizeof(double) * (size_t)P.L * P.L);
@@ -191,32 +193,44 @@ T* at(void* base, size_t off) {
         if (e_ != hipSuccess) return RSVD_ERR_DEVICE;      \
     } while (0)
 
+// The second CholeskyQR pass is switched off when the first one is already
+// orthonormal to within 2^-24 (FP32 panels; see chol_finish_orth): a second
+// pass could then only move Q by less than its storage precision.  FP64
+// panels always take it.
+constexpr double kPass2SkipTauF32 = 0x1.0p-24;
+
 // orth(Y) -> Q for an internal rows x L buffer (ld = L, l valid columns,
 // zero padding), with the outcome in `flags`.  Qout must not alias Y.
+// CholeskyQR2: Q1 = Y R1^{-1} is written to Qout, and the second pass
+// multiplies Qout by R2^{-1} in place.
 rsvd_status run_orth_cols(const Plan& P, void* ws, DevFlags* flags, int dtype, int64_t rows, int l, int L,
-                          const void* Y, void* Qout, int force_hh, hipStream_t s) {
+                          const void* Y, void* Qout, int orth_mode, hipStream_t s) {
     double* R = at<double>(ws, P.R);
     double* Rinv = at<double>(ws, P.Rinv);
     double* GP = at<double>(ws, P.GP);
     double* work = at<double>(ws, P.work);
-    void* Q1 = at<char>(ws, P.Q1);
-    if (!force_hh) {
+    if (orth_mode != RSVD_ORTH_HOUSEHOLDER) {
+        const int report = orth_mode == RSVD_ORTH_CHOLQR2;
+        const double skip_tau = dtype == RSVD_F32 ? kPass2SkipTauF32 : 0.0;
         RSVD_TRY(launch_gram(dtype, Y, L, rows, L, GP, nullptr, s));
-        RSVD_TRY(launch_chol(GP, rows, l, L, R, Rinv, flags, 0, nullptr, work, 0.0, s));
-        RSVD_TRY(launch_apply(dtype, Y, L, rows, L, Rinv, L, L, Q1, L, 0, nullptr, flags, nullptr, nullptr, 1, s));
-        RSVD_TRY(launch_gram(dtype, Q1, L, rows, L, GP, flags, s));
+        RSVD_TRY(launch_chol(GP, rows, l, L, R, Rinv, flags, 0, nullptr, work, 0.0, s, skip_tau, report));
+        RSVD_TRY(launch_apply(dtype, Y, L, rows, L, Rinv, L, L, Qout, L, 0, nullptr, &flags->orth_fail, nullptr,
+                              nullptr, 1, s));
+        RSVD_TRY(launch_gram(dtype, Qout, L, rows, L, GP, &flags->pass2_off, s));
         RSVD_TRY(launch_chol(GP, rows, l, L, R, Rinv, flags, 1, nullptr, work,
-                             dtype == RSVD_F64 ? 0x1.0p-26 : 0x1.0p-13, s));
-        RSVD_TRY(launch_apply(dtype, Q1, L, rows, L, Rinv, L, L, Qout, L, 0, nullptr, flags, nullptr, nullptr, 1, s));
+                             dtype == RSVD_F64 ? 0x1.0p-26 : 0x1.0p-13, s, 0.0, report));
+        RSVD_TRY(launch_apply(dtype, Qout, L, rows, L, Rinv, L, L, Qout, L, 0, nullptr, &flags->pass2_off, nullptr,
+                              nullptr, 1, s));
+        if (orth_mode == RSVD_ORTH_CHOLQR2) return RSVD_OK;
     }
-    RSVD_TRY(launch_householder(dtype, Y, L, rows, l, L, Qout, L, at<double>(ws, P.H), at<double>(ws, P.Qw), flags,
-                                force_hh, s));
+    RSVD_TRY(launch_householder(dtype, Y, L, rows, l, L, Qout, L, at<double>(ws, P.H), at<double>(ws, P.Qw),
+                                at<double>(ws, P.part), flags, orth_mode == RSVD_ORTH_HOUSEHOLDER, s));
     return RSVD_OK;
 }
 
-rsvd_status run_orth(const Plan& P, void* ws, int dtype, int64_t rows, const void* Y, void* Qout, int force_hh,
+rsvd_status run_orth(const Plan& P, void* ws, int dtype, int64_t rows, const void* Y, void* Qout, int orth_mode,
                      hipStream_t s) {
-    return run_orth_cols(P, ws, at<DevFlags>(ws, P.flags), dtype, rows, (int)P.l, P.L, Y, Qout, force_hh, s);
+    return run_orth_cols(P, ws, at<DevFlags>(ws, P.flags), dtype, rows, (int)P.l, P.L, Y, Qout, orth_mode, s);
 }
 
 // Product of A with a skinny block: Yout (ldy) = A X or A^T X, X with ldx
@@ -393,6 +407,9 @@ rsvd_status check_params(const rsvd_matrix* A, const rsvd_params* p) {
     if (p->residual < 0 || p->residual > 3 || p->residual_iters < 0 || p->residual_iters > 1000)
         return RSVD_ERR_INVALID_ARG;
     if (p->extra_power_pass < -1 || p->extra_power_pass > 8) return RSVD_ERR_INVALID_ARG;
+    if (p->orth < RSVD_ORTH_AUTO || p->orth > RSVD_ORTH_HOUSEHOLDER) return RSVD_ERR_INVALID_ARG;
+    if (p->algorithm != 0 && p->algorithm != 3 && p->algorithm != 4) return RSVD_ERR_INVALID_ARG;
+    if (p->jacobi_max_sweeps < 0 || p->jacobi_max_sweeps > 1000) return RSVD_ERR_INVALID_ARG;
     if (is_lowp(A->dtype) && p->residual && !A->master) return RSVD_ERR_INVALID_ARG;
     if (round_up(std::min<int64_t>(p->k + p->p, mn), 16) > kMaxL) return RSVD_ERR_UNSUPPORTED;
     return RSVD_OK;
@@ -521,7 +538,7 @@ rsvd_status solve_impl(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* 
     void* Y = at<char>(ws, P.Y);
     void* Q = at<char>(ws, P.Q);
     void* W = at<char>(ws, P.W);
-    const int hh = params->force_householder;
+    const int om = params->orth;
 
     RSVD_TRY(launch_init(cnt, P.ncounters, flags, s));
     rsvd_handle* hp = profile && h->profiling ? h : nullptr;   // product timing on
@@ -533,15 +550,26 @@ rsvd_status solve_impl(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* 
         RSVD_TRY(hipEventRecord(stage1.start, s));
     }
     if (A->dtype == RSVD_FP8_E4M3) RSVD_TRY(launch_vec_max(A->col_scale, A->cols, at<float>(ws, P.smax), s));
-    // Stage 1: steps 1-3, sketch with the generated test matrix, then orth.
-    if ((st = run_gemm(hp, P, ws, A, 0, nullptr, params->seed, Y, s)) != RSVD_OK) return st;
-    if ((st = run_orth(P, ws, dt, P.m, Y, Q, hh, s)) != RSVD_OK) return st;
-    // Steps 4-5: q power iterations, each product re-orthonormalised.
-    for (int64_t t = 0; t < qeff; ++t) {
-        if ((st = run_gemm(hp, P, ws, A, 1, Q, 0, Y, s)) != RSVD_OK) return st;
-        if ((st = run_orth(P, ws, dt, P.n, Y, W, hh, s)) != RSVD_OK) return st;
-        if ((st = run_gemm(hp, P, ws, A, 0, W, 0, Y, s)) != RSVD_OK) return st;
-        if ((st = run_orth(P, ws, dt, P.m, Y, Q, hh, s)) != RSVD_OK) return st;
+    if (params->algorithm == 3) {
+        // Algorithm 3 (Section 3.2): Y = A Omega, then q times Z = A^T Y,
+        // Y = A Z with no orthonormalisation in between; orth once at the end.
+        if ((st = run_gemm(hp, P, ws, A, 0, nullptr, params->seed, Y, s)) != RSVD_OK) return st;
+        for (int64_t t = 0; t < qeff; ++t) {
+            if ((st = run_gemm(hp, P, ws, A, 1, Y, 0, W, s)) != RSVD_OK) return st;
+            if ((st = run_gemm(hp, P, ws, A, 0, W, 0, Y, s)) != RSVD_OK) return st;
+        }
+        if ((st = run_orth(P, ws, dt, P.m, Y, Q, om, s)) != RSVD_OK) return st;
+    } else {
+        // Stage 1: steps 1-3, sketch with the generated test matrix, then orth.
+        if ((st = run_gemm(hp, P, ws, A, 0, nullptr, params->seed, Y, s)) != RSVD_OK) return st;
+        if ((st = run_orth(P, ws, dt, P.m, Y, Q, om, s)) != RSVD_OK) return st;
+        // Steps 4-5: q power iterations, each product re-orthonormalised.
+        for (int64_t t = 0; t < qeff; ++t) {
+            if ((st = run_gemm(hp, P, ws, A, 1, Q, 0, Y, s)) != RSVD_OK) return st;
+            if ((st = run_orth(P, ws, dt, P.n, Y, W, om, s)) != RSVD_OK) return st;
+            if ((st = run_gemm(hp, P, ws, A, 0, W, 0, Y, s)) != RSVD_OK) return st;
+            if ((st = run_orth(P, ws, dt, P.m, Y, Q, om, s)) != RSVD_OK) return st;
+        }
     }
     if (hp) {
         RSVD_TRY(hipEventRecord(stage1.stop, s));
@@ -563,7 +591,8 @@ rsvd_status solve_impl(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* 
     RSVD_TRY(launch_gram(dt, Bt, L, P.n, L, at<double>(ws, P.GP), nullptr, s));
     RSVD_TRY(launch_chol(at<double>(ws, P.GP), P.n, (int)P.l, L, R, at<double>(ws, P.Rinv), flags, 2, shift,
                          at<double>(ws, P.work), 0.0, s));
-    RSVD_TRY(launch_jacobi(R, (int)P.l, L, shift, sigma, Ut, Mv, flags, at<double>(ws, P.work), s));
+    RSVD_TRY(launch_jacobi(R, (int)P.l, L, shift, sigma, Ut, Mv, flags, at<double>(ws, P.work), s,
+                           params->jacobi_max_sweeps));
     // V = B^T U~ Sigma^{-1}, written transposed into Vt, with column argmax partials.
     RSVD_TRY(launch_apply(dt, Bt, L, P.n, L, Mv, L, r, out->Vt, out->ldvt, 1, nullptr, nullptr, av, ai, 0, s));
     RSVD_TRY(launch_signs(av, ai, apply_blocks(P.n), r, sigma, out->S, sign, s));
@@ -730,8 +759,9 @@ rsvd_status rsvd_orth_workspace_size(int32_t dtype, int64_t rows, int64_t l, siz
 }
 
 rsvd_status rsvd_orth(rsvd_handle* h, int32_t dtype, int64_t rows, int64_t l, const void* Y, int64_t ldy, void* Qo,
-                      int64_t ldq, int32_t force_householder, int32_t* info, void* ws, size_t ws_bytes, void* stream) {
+                      int64_t ldq, int32_t orth_mode, int32_t* info, void* ws, size_t ws_bytes, void* stream) {
     if (!h || !Y || !Qo || !info || ldy < l || ldq < l) return RSVD_ERR_INVALID_ARG;
+    if (orth_mode < RSVD_ORTH_AUTO || orth_mode > RSVD_ORTH_HOUSEHOLDER) return RSVD_ERR_INVALID_ARG;
     size_t need = 0;
     rsvd_status st = rsvd_orth_workspace_size(dtype, rows, l, &need);
     if (st != RSVD_OK) return st;
@@ -746,7 +776,7 @@ rsvd_status rsvd_orth(rsvd_handle* h, int32_t dtype, int64_t rows, int64_t l, co
     void* Yi = at<char>(ws, P.Y);
     void* Qi = at<char>(ws, P.Q);
     RSVD_TRY(launch_copy2d(dtype, Y, ldy, rows, (int)l, Yi, P.L, P.L, s));
-    if ((st = run_orth(P, ws, dtype, rows, Yi, Qi, force_householder, s)) != RSVD_OK) return st;
+    if ((st = run_orth(P, ws, dtype, rows, Yi, Qi, orth_mode, s)) != RSVD_OK) return st;
     RSVD_TRY(launch_copy2d(dtype, Qi, P.L, rows, (int)l, Qo, ldq, (int)l, s));
     RSVD_TRY(launch_export_info(flags, info, s));
     return RSVD_OK;

@@ -86,9 +86,9 @@ private:
 
 // Everything about a request that decides which kernels rsvd_solve launches.
 struct BucketKey {
-    int64_t v[14];
+    int64_t v[16];
     bool operator==(const BucketKey& o) const {
-        for (int i = 0; i < 14; ++i)
+        for (int i = 0; i < 16; ++i)
             if (v[i] != o.v[i]) return false;
         return true;
     }
@@ -156,8 +156,8 @@ BucketKey bucket_of(const Request* r) {
     const rsvd_params& p = r->params;
     return BucketKey{{(int64_t)r->A.dtype, r->A.rows, r->A.cols, p.k, p.p, p.q, (int64_t)p.extra_power_pass,
                       (int64_t)p.residual, (int64_t)p.residual_iters, (int64_t)p.return_full_l,
-                      (int64_t)p.force_householder, r->out.Q != nullptr, r->A.master != nullptr,
-                      r->A.col_scale != nullptr}};
+                      (int64_t)p.orth, r->out.Q != nullptr, r->A.master != nullptr,
+                      r->A.col_scale != nullptr, (int64_t)p.algorithm, (int64_t)p.jacobi_max_sweeps}};
 }
 
 }  // namespace

@@ -159,7 +159,7 @@ template <int R>
 __global__ __launch_bounds__(512) void jacobi_oe_kernel(const double* __restrict__ Rm, int l, int L,
                                                         const double* __restrict__ shift_p,
                                                         double* __restrict__ sigma, double* __restrict__ Ut,
-                                                        double* __restrict__ Mv, DevFlags* flags) {
+                                                        double* __restrict__ Mv, DevFlags* flags, int max_sweeps) {
     constexpr int LPP = 8, GMAX = kJacobiRegMax / 2;
     constexpr int BUF = 2 * R * GMAX * LPP;                 // exchange buffer [side][k][group][lane]
     static_assert(LPP * R <= kJacobiRegMax, "rows per column");
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(512) void jacobi_oe_kernel(const double* __restrict
     const int sr = hasR ? 0 : 1, gr = hasR ? gi + 1 : gi;
     const int sl = hasL ? 1 : 0, gl = hasL ? gi - 1 : gi;
     bool converged = (l < 2), small = false;
-    for (int sweep = 0; sweep < kJacobiMaxSweeps && !converged; ++sweep) {
+    for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             x0[k] *= c0.sc;
@@ -505,14 +505,15 @@ __global__ __launch_bounds__(kBlkLpp * kBlkGroups) void jacobi_blk_pair_kernel(d
 __global__ __launch_bounds__(512) void jacobi_blk_finish_kernel(const double* __restrict__ work, int l, int L,
                                                                 const double* __restrict__ shift_p,
                                                                 double* __restrict__ sigma, double* __restrict__ Ut,
-                                                                double* __restrict__ Mv, DevFlags* flags) {
+                                                                double* __restrict__ Mv, DevFlags* flags,
+                                                                int sweeps) {
     __shared__ double nrm2[kMaxL];
     __shared__ int rank_of[kMaxL];
     const double* X = work;
     const int* rotw = reinterpret_cast<const int*>(work + (size_t)kMaxL * kMaxL);
     const double sc4 = work[(size_t)kMaxL * kMaxL + kJacobiBlockSweeps / 2 + 2];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    if (tid == 0 && rotw[kJacobiBlockSweeps - 1] != 0) atomicOr(&flags->info, RSVD_INFO_JACOBI_NOT_CONVERGED);
+    if (tid == 0 && rotw[sweeps - 1] != 0) atomicOr(&flags->info, RSVD_INFO_JACOBI_NOT_CONVERGED);
     for (int c = wid; c < l; c += 8) {
         double s2 = 0.0;
         for (int r = lane; r < l; r += 64) s2 = fma(X[(int64_t)c * kMaxL + r], X[(int64_t)c * kMaxL + r], s2);
@@ -541,52 +542,56 @@ __global__ __launch_bounds__(512) void jacobi_blk_finish_kernel(const double* __
 
 template <int R>
 static void launch_jacobi_blk(const double* Rm, int l, int L, const double* shift, double* sigma, double* Ut,
-                              double* Mv, DevFlags* flags, double* work, hipStream_t s) {
+                              double* Mv, DevFlags* flags, double* work, hipStream_t s, int sweeps) {
     const int nb = (l + 15) / 16, nb2 = nb + (nb & 1);
     hipLaunchKernelGGL(jacobi_blk_prep_kernel, dim3(1), dim3(1024), 0, s, Rm, l, L, work);
-    for (int sweep = 0; sweep < kJacobiBlockSweeps; ++sweep)
+    for (int sweep = 0; sweep < sweeps; ++sweep)
         for (int r = 0; r < nb2 - 1; ++r)
             hipLaunchKernelGGL(jacobi_blk_pair_kernel<R>, dim3(nb2 / 2), dim3(kBlkLpp * kBlkGroups), 0, s, work, nb2,
                                r, sweep);
-    hipLaunchKernelGGL(jacobi_blk_finish_kernel, dim3(1), dim3(512), 0, s, work, l, L, shift, sigma, Ut, Mv, flags);
+    hipLaunchKernelGGL(jacobi_blk_finish_kernel, dim3(1), dim3(512), 0, s, work, l, L, shift, sigma, Ut, Mv, flags,
+                       sweeps);
 }
 
 template <int R>
 static void launch_jacobi_oe(const double* Rm, int l, int L, const double* shift, double* sigma, double* Ut,
-                             double* Mv, DevFlags* flags, hipStream_t s) {
+                             double* Mv, DevFlags* flags, hipStream_t s, int sweeps) {
     const int groups = ((l + 1) & ~1) / 2;
     const int threads = (int)round_up(groups * 8, kWave);
-    hipLaunchKernelGGL(jacobi_oe_kernel<R>, dim3(1), dim3(threads), 0, s, Rm, l, L, shift, sigma, Ut, Mv, flags);
+    hipLaunchKernelGGL(jacobi_oe_kernel<R>, dim3(1), dim3(threads), 0, s, Rm, l, L, shift, sigma, Ut, Mv, flags,
+                       sweeps);
 }
 
 hipError_t launch_jacobi(const double* R, int l, int L, const double* shift, double* sigma, double* Ut, double* Mv,
-                         DevFlags* flags, double* work, hipStream_t s) {
-    if (l < 1 || l > kMaxL || L < l) return hipErrorInvalidValue;
+                         DevFlags* flags, double* work, hipStream_t s, int max_sweeps) {
+    if (l < 1 || l > kMaxL || L < l || max_sweeps < 0) return hipErrorInvalidValue;
+    const int oe_sweeps = max_sweeps ? max_sweeps : kJacobiMaxSweeps;
+    const int blk_sweeps = max_sweeps ? std::min(max_sweeps, kJacobiBlockSweeps) : kJacobiBlockSweeps;
     if (l <= kJacobiRegMax) {
         // rows per lane and column: 2 ceil(l / 16), so 8 lanes cover ceil(l / 16) * 16 >= l rows
         switch ((l + 15) / 16) {
-            case 1: launch_jacobi_oe<2>(R, l, L, shift, sigma, Ut, Mv, flags, s); break;
-            case 2: launch_jacobi_oe<4>(R, l, L, shift, sigma, Ut, Mv, flags, s); break;
-            case 3: launch_jacobi_oe<6>(R, l, L, shift, sigma, Ut, Mv, flags, s); break;
-            case 4: launch_jacobi_oe<8>(R, l, L, shift, sigma, Ut, Mv, flags, s); break;
-            case 5: launch_jacobi_oe<10>(R, l, L, shift, sigma, Ut, Mv, flags, s); break;
-            case 6: launch_jacobi_oe<12>(R, l, L, shift, sigma, Ut, Mv, flags, s); break;
-            case 7: launch_jacobi_oe<14>(R, l, L, shift, sigma, Ut, Mv, flags, s); break;
-            default: launch_jacobi_oe<16>(R, l, L, shift, sigma, Ut, Mv, flags, s); break;
+            case 1: launch_jacobi_oe<2>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps); break;
+            case 2: launch_jacobi_oe<4>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps); break;
+            case 3: launch_jacobi_oe<6>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps); break;
+            case 4: launch_jacobi_oe<8>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps); break;
+            case 5: launch_jacobi_oe<10>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps); break;
+            case 6: launch_jacobi_oe<12>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps); break;
+            case 7: launch_jacobi_oe<14>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps); break;
+            default: launch_jacobi_oe<16>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps); break;
         }
     } else {
         // rows per lane and column: ceil(l / 16), 16 lanes per column pair
         switch ((l + 15) / 16) {
-            case 9: launch_jacobi_blk<9>(R, l, L, shift, sigma, Ut, Mv, flags, work, s); break;
-            case 10: launch_jacobi_blk<10>(R, l, L, shift, sigma, Ut, Mv, flags, work, s); break;
-            case 11: launch_jacobi_blk<11>(R, l, L, shift, sigma, Ut, Mv, flags, work, s); break;
-            case 12: launch_jacobi_blk<12>(R, l, L, shift, sigma, Ut, Mv, flags, work, s); break;
-            case 13: launch_jacobi_blk<13>(R, l, L, shift, sigma, Ut, Mv, flags, work, s); break;
-            case 14: launch_jacobi_blk<14>(R, l, L, shift, sigma, Ut, Mv, flags, work, s); break;
-            case 15: launch_jacobi_blk<15>(R, l, L, shift, sigma, Ut, Mv, flags, work, s); break;
-            case 16: launch_jacobi_blk<16>(R, l, L, shift, sigma, Ut, Mv, flags, work, s); break;
-            case 17: launch_jacobi_blk<17>(R, l, L, shift, sigma, Ut, Mv, flags, work, s); break;
-            default: launch_jacobi_blk<18>(R, l, L, shift, sigma, Ut, Mv, flags, work, s); break;
+            case 9: launch_jacobi_blk<9>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps); break;
+            case 10: launch_jacobi_blk<10>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps); break;
+            case 11: launch_jacobi_blk<11>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps); break;
+            case 12: launch_jacobi_blk<12>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps); break;
+            case 13: launch_jacobi_blk<13>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps); break;
+            case 14: launch_jacobi_blk<14>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps); break;
+            case 15: launch_jacobi_blk<15>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps); break;
+            case 16: launch_jacobi_blk<16>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps); break;
+            case 17: launch_jacobi_blk<17>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps); break;
+            default: launch_jacobi_blk<18>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps); break;
         }
     }
     return hipGetLastError();

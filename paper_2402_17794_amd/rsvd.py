@@ -50,11 +50,23 @@ class LowPrecisionMatrix:
         return m
 
 
+ORTH_AUTO, ORTH_CHOLQR2, ORTH_HOUSEHOLDER = 0, 1, 2
+INFO_ORTH_BREAKDOWN = 16
+INFO_FALLBACK_TIMEOUT = 32
+
+
 class rsvd_params(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int64), ("p", ctypes.c_int64), ("q", ctypes.c_int64), ("seed", ctypes.c_uint64),
                 ("residual", ctypes.c_int32), ("return_full_l", ctypes.c_int32),
-                ("force_householder", ctypes.c_int32), ("residual_iters", ctypes.c_int32),
-                ("extra_power_pass", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+                ("orth", ctypes.c_int32), ("residual_iters", ctypes.c_int32),
+                ("extra_power_pass", ctypes.c_int32), ("algorithm", ctypes.c_int32),
+                ("jacobi_max_sweeps", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+
+
+def make_params(k, p=10, q=0, seed=0, residual=0, return_full_l=False, orth=ORTH_AUTO, residual_iters=0,
+                extra_power_pass=-1, algorithm=4, jacobi_max_sweeps=0):
+    return rsvd_params(k, p, q, seed, residual, int(return_full_l), int(orth), int(residual_iters),
+                       int(extra_power_pass), int(algorithm), int(jacobi_max_sweeps), 0, 0)
 
 
 class rsvd_result(ctypes.Structure):
@@ -196,7 +208,7 @@ def l_used(m, n, k, p):
 def workspace_size(A, k, p=10, q=0, return_full_l=False):
     lib = load_library()
     M = _as_matrix(A)
-    prm = rsvd_params(k, p, q, 0, 0, int(return_full_l), 0, 0, -1, 0)
+    prm = make_params(k, p, q, return_full_l=return_full_l)
     nb = ctypes.c_size_t()
     _check(lib.rsvd_workspace_size(_handle(A.device), ctypes.byref(M), ctypes.byref(prm), ctypes.byref(nb)))
     return nb.value
@@ -225,10 +237,14 @@ class Solver:
     Frobenius, 3 both); residual_iters: power iterations of the spectral
     estimate (0 = library default).  noalloc: call rsvd_solve_noalloc, which
     uses the library's fixed device scratch instead of a workspace (no
-    workspace tensor is made)."""
+    workspace tensor is made).  orth: ORTH_AUTO, ORTH_CHOLQR2 or
+    ORTH_HOUSEHOLDER (force_householder=True is ORTH_HOUSEHOLDER);
+    algorithm: 4 (default) or 3 (no orth between the power products);
+    jacobi_max_sweeps: sweep cap of the small SVD (0 = default)."""
 
     def __init__(self, A, k, p=10, q=0, seed=0, residual=False, return_full_l=False, force_householder=False,
-                 return_q=False, stream=None, residual_iters=0, extra_power_pass=-1, noalloc=False):
+                 return_q=False, stream=None, residual_iters=0, extra_power_pass=-1, noalloc=False, orth=ORTH_AUTO,
+                 algorithm=4, jacobi_max_sweeps=0):
         self.lib = load_library()
         self.A = A
         self.M = _as_matrix(A)
@@ -237,8 +253,9 @@ class Solver:
         r = self.l if return_full_l else k
         dev = A.device
         residual = _residual_mode(residual)
-        self.params = rsvd_params(k, p, q, seed, residual, int(return_full_l), int(force_householder),
-                                  int(residual_iters), int(extra_power_pass), 0)
+        self.params = make_params(k, p, q, seed, residual, return_full_l,
+                                  ORTH_HOUSEHOLDER if force_householder else orth, residual_iters, extra_power_pass,
+                                  algorithm, jacobi_max_sweeps)
         self.U = torch.empty((m, r), dtype=A.dtype, device=dev)
         self.S = torch.empty((r,), dtype=torch.float64, device=dev)
         self.Vt = torch.empty((r, n), dtype=A.dtype, device=dev)
@@ -271,13 +288,15 @@ class Solver:
 
 
 def solve(A, k, p=10, q=0, seed=0, residual=False, return_full_l=False, force_householder=False, return_q=False,
-          stream=None, residual_iters=0, extra_power_pass=-1, noalloc=False):
-    """Randomized SVD (Algorithm 4) of a CUDA tensor A.  Returns a dict with
-    U (m x r), S (r, float64), Vt (r x n), info (int), l, and optionally
-    residual_t ([spectral estimate, Frobenius norm] of A - QQ^T A, float64
-    tensor) and Q (m x l).  noalloc: use rsvd_solve_noalloc."""
+          stream=None, residual_iters=0, extra_power_pass=-1, noalloc=False, orth=ORTH_AUTO, algorithm=4,
+          jacobi_max_sweeps=0):
+    """Randomized SVD (Algorithm 4, or Algorithm 3 with algorithm=3) of a
+    CUDA tensor A.  Returns a dict with U (m x r), S (r, float64), Vt
+    (r x n), info (int), l, and optionally residual_t ([spectral estimate,
+    Frobenius norm] of A - QQ^T A, float64 tensor) and Q (m x l).
+    noalloc: use rsvd_solve_noalloc."""
     s = Solver(A, k, p, q, seed, residual, return_full_l, force_householder, return_q, stream, residual_iters,
-               extra_power_pass, noalloc)()
+               extra_power_pass, noalloc, orth, algorithm, jacobi_max_sweeps)()
     out = dict(U=s.U, S=s.S, Vt=s.Vt, l=s.l, info_tensor=s.info)
     if residual:
         out["residual_t"] = s.res
@@ -300,7 +319,7 @@ class Request:
         self.Vt = torch.empty((r, n), dtype=A.dtype, device=dev)
         self.info = torch.zeros((1,), dtype=torch.int32, device=dev)
         self._M = _as_matrix(A)
-        self._params = rsvd_params(k, p, q, seed, 0, int(return_full_l), 0, 0, int(extra_power_pass), 0)
+        self._params = make_params(k, p, q, seed, 0, return_full_l, extra_power_pass=extra_power_pass)
         self._result = rsvd_result(self.U.data_ptr(), r, self.S.data_ptr(), self.Vt.data_ptr(), n, None,
                                    self.info.data_ptr(), None, self.l)
         t = ctypes.c_uint64()
@@ -422,9 +441,12 @@ def gemm(A, X=None, trans=False, seed=0, ncols=None):
     return Y
 
 
-def orth(Y, force_householder=False):
-    """Orthonormal basis of range(Y) (CholeskyQR2 with Householder fallback).
-    Returns (Q, info)."""
+def orth(Y, force_householder=False, mode=None):
+    """Orthonormal basis of range(Y) (CholeskyQR2 with Householder fallback;
+    mode: ORTH_AUTO, ORTH_CHOLQR2 or ORTH_HOUSEHOLDER, force_householder=True
+    is ORTH_HOUSEHOLDER).  Returns (Q, info)."""
+    if mode is None:
+        mode = ORTH_HOUSEHOLDER if force_householder else ORTH_AUTO
     lib = load_library()
     if Y.dtype not in _DTYPES or Y.stride(1) != 1:
         raise ValueError("Y must be a row-major float32/float64 CUDA tensor")
@@ -435,6 +457,6 @@ def orth(Y, force_householder=False):
     Q = torch.empty_like(Y)
     info = torch.zeros((1,), dtype=torch.int32, device=Y.device)
     _check(lib.rsvd_orth(_handle(Y.device), _DTYPES[Y.dtype], rows, l, ctypes.c_void_p(Y.data_ptr()), Y.stride(0),
-                         ctypes.c_void_p(Q.data_ptr()), l, int(force_householder), ctypes.c_void_p(info.data_ptr()),
+                         ctypes.c_void_p(Q.data_ptr()), l, int(mode), ctypes.c_void_p(info.data_ptr()),
                          ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(None, Y.device)))
     return Q, info

@@ -44,13 +44,13 @@ def test_host_only_entry_points(lib):
     assert lib.rsvd_status_string(4) == b"workspace too small"
     A = rsvd.rsvd_matrix(0x1000, rsvd.RSVD_F32, 0, 8192, 8192, 8192)
     nb = ctypes.c_size_t()
-    good = rsvd.rsvd_params(100, 10, 2, 0, 0, 0, 0, 0)
+    good = rsvd.make_params(100, 10, 2)
     assert lib.rsvd_workspace_size(None, ctypes.byref(A), ctypes.byref(good), ctypes.byref(nb)) == 0
     assert nb.value > 8192 * 112 * 4 * 3
     for k, p, q in [(0, 10, 0), (8193, 0, 0), (10, -1, 0), (10, 5, -2)]:
-        bad = rsvd.rsvd_params(k, p, q, 0, 0, 0, 0, 0)
+        bad = rsvd.make_params(k, p, q)
         assert lib.rsvd_workspace_size(None, ctypes.byref(A), ctypes.byref(bad), ctypes.byref(nb)) == 1
-    wide = rsvd.rsvd_params(400, 10, 0, 0, 0, 0, 0, 0)          # l = 410 > 288
+    wide = rsvd.make_params(400, 10, 0)          # l = 410 > 288
     assert lib.rsvd_workspace_size(None, ctypes.byref(A), ctypes.byref(wide), ctypes.byref(nb)) == 2
     badld = rsvd.rsvd_matrix(0x1000, rsvd.RSVD_F32, 0, 10, 20, 19)
     assert lib.rsvd_workspace_size(None, ctypes.byref(badld), ctypes.byref(good), ctypes.byref(nb)) == 1
@@ -66,7 +66,7 @@ def test_workspace_grows_with_the_block_jacobi_scratch(lib):
     from paper_2402_17794_amd import rsvd
     A = rsvd.rsvd_matrix(0x1000, rsvd.RSVD_F32, 0, 4096, 2048, 2048)
     nb = ctypes.c_size_t()
-    p = rsvd.rsvd_params(256, 16, 1, 0, 0, 0, 0, 0)            # l = 272
+    p = rsvd.make_params(256, 16, 1)            # l = 272
     assert lib.rsvd_workspace_size(None, ctypes.byref(A), ctypes.byref(p), ctypes.byref(nb)) == 0
     assert nb.value >= 288 * 288 * 8 + 4096 * 272 * 4
 

@@ -100,12 +100,13 @@ def test_integer_products_bit_exact(R, dtype, m, n, nc):
     A = rng.integers(-4, 5, size=(m, n), dtype=np.int64)
     X = rng.integers(-4, 5, size=(n, nc), dtype=np.int64)
     Wm = rng.integers(-4, 5, size=(m, nc), dtype=np.int64)
-    Ad = _cuda(A.astype(np.float64), dtype)
-    Y = R.gemm(Ad, _cuda(X.astype(np.float64), dtype)).cpu().numpy()
-    assert np.array_equal(Y.astype(np.int64), A @ X)
-    assert np.all(Y == (A @ X).astype(Y.dtype))
-    Z = R.gemm(Ad, _cuda(Wm.astype(np.float64), dtype), trans=True).cpu().numpy()
-    assert np.all(Z == (A.T @ Wm).astype(Z.dtype))
+    # the reference products in FP64 BLAS are exact too (integers below 2^53)
+    Af, Xf, Wf = A.astype(np.float64), X.astype(np.float64), Wm.astype(np.float64)
+    Ad = _cuda(Af, dtype)
+    Y = R.gemm(Ad, _cuda(Xf, dtype)).cpu().numpy()
+    assert np.all(Y == (Af @ Xf).astype(Y.dtype))
+    Z = R.gemm(Ad, _cuda(Wf, dtype), trans=True).cpu().numpy()
+    assert np.all(Z == (Af.T @ Wf).astype(Z.dtype))
 
 
 def test_products_strided_and_unaligned(R):
@@ -126,8 +127,6 @@ def _orth_err(Q):
 @pytest.mark.parametrize("rows,l", [(1000, 30), (8192, 110), (300, 288), (17, 17), (5000, 1)])
 @pytest.mark.parametrize("force_hh", [False, True])
 def test_orth_matches_householder_oracle(R, dtype, rows, l, force_hh):
-    if force_hh and rows * l > 300 * 288:
-        pytest.skip("single-workgroup fallback: exercised at the smaller shapes")
     rng = np.random.default_rng(rows + l)
     Y = rng.standard_normal((rows, l)) * np.logspace(0, -2, l)[None, :]     # kappa ~ 1e2
     if dtype == torch.float32:
@@ -142,6 +141,23 @@ def test_orth_matches_householder_oracle(R, dtype, rows, l, force_hh):
     assert fell_back == force_hh
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_orth_cholqr2_only_reports_breakdown(R, dtype):
+    """RSVD_ORTH_CHOLQR2 enqueues no fallback: a rank-deficient Y is reported
+    as RSVD_INFO_ORTH_BREAKDOWN, and a full-rank Y gives the same Q as the
+    default mode."""
+    rng = np.random.default_rng(12)
+    Yd = _cuda(rng.standard_normal((600, 5)) @ rng.standard_normal((5, 20)), dtype)
+    _, info = R.orth(Yd, mode=R.ORTH_CHOLQR2)
+    assert info.item() & R.INFO_ORTH_BREAKDOWN
+    assert not info.item() & R.INFO_QR_FALLBACK
+    Yf = _cuda(rng.standard_normal((3000, 40)), dtype)
+    Qa, ia = R.orth(Yf)
+    Qc, ic = R.orth(Yf, mode=R.ORTH_CHOLQR2)
+    assert ia.item() == 0 and ic.item() == 0
+    assert torch.equal(Qa, Qc)
+
+
 def test_orth_ill_conditioned_fp64(R):
     """kappa(Y) = 1e6: the second CholeskyQR pass is far from the identity
     and takes the exact factorisation."""
@@ -154,6 +170,25 @@ def test_orth_ill_conditioned_fp64(R):
     assert info.item() == 0
     assert _orth_err(Qg) <= 1e-13
     assert np.max(np.abs(Qg - OL.householder_qr(Y)[0])) <= 1e-8
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("rows,l,rank", [(8192, 110, 40), (1000, 288, 100), (100000, 16, 3)])
+def test_orth_fallback_tree_rank_deficient(R, dtype, rows, l, rank):
+    """The Householder fallback at full size (a TSQR tree over up to 64
+    workgroups, two or three levels): a rank-deficient Y breaks CholeskyQR,
+    and the fallback returns an orthonormal Q whose range holds range(Y)."""
+    rng = np.random.default_rng(rows + rank)
+    Y = rng.standard_normal((rows, rank)) @ rng.standard_normal((rank, l))
+    Yd = _cuda(Y, dtype)
+    Q, info = R.orth(Yd)
+    assert info.item() & R.INFO_QR_FALLBACK
+    assert not info.item() & R.INFO_FALLBACK_TIMEOUT
+    Qg = Q.cpu().numpy().astype(np.float64)
+    Yr = Yd.cpu().numpy().astype(np.float64)
+    tol_o = 2e-6 if dtype == torch.float32 else 1e-13
+    assert _orth_err(Qg) <= tol_o
+    assert np.linalg.norm(Yr - Qg @ (Qg.T @ Yr)) <= (1e-5 if dtype == torch.float32 else 1e-12) * np.linalg.norm(Yr)
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])

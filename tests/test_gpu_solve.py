@@ -174,6 +174,32 @@ def test_rank_deficient_block_jacobi(R):
     assert np.all(np.diff(S) <= 0.0)
 
 
+def test_exact_rank_full_size_takes_the_fallback(R):
+    """8192 x 8192 FP32 of exact rank 50 with k = 100, p = 10, q = 2: every
+    Y of the power scheme has rank 50 < l = 110, so every orthonormalisation
+    takes the Householder fallback at full size; the 50 singular values are
+    recovered to FP32 accuracy, the other 50 returned ones are at the
+    rounding level, and U, V are orthonormal."""
+    m = n = 8192
+    r = 50
+    sig = 0.8 ** np.arange(r)
+    U = W.haar(m, r, 31)
+    V = W.haar(n, r, 32)
+    A = ((U * sig[None, :]) @ V.T).astype(np.float32)
+    out = R.solve(torch.from_numpy(A).cuda(), k=100, p=10, q=2, seed=0)
+    torch.cuda.synchronize()
+    info = out["info_tensor"].item()
+    assert info & R.INFO_QR_FALLBACK and not info & R.INFO_FALLBACK_TIMEOUT
+    S = _np(out["S"])
+    assert np.max(np.abs(S[:r] - sig)) <= 1e-5 * sig[0]
+    assert np.max(S[r:]) <= 1e-5 * sig[0]
+    Ug, Vt = _np(out["U"]), _np(out["Vt"])
+    assert np.max(np.abs(Ug.T @ Ug - np.eye(100))) <= 1e-5
+    assert np.max(np.abs(Vt[:r] @ Vt[:r].T - np.eye(r))) <= 1e-5
+    # the leading singular subspace is recovered
+    assert np.linalg.norm(U[:, :10] - Ug[:, :10] @ (Ug[:, :10].T @ U[:, :10]), 2) <= 1e-4
+
+
 def test_exact_rank_fp64(R):
     A, sig = W.exact_rank(700, 300, 12, 5, 6)
     out = R.solve(torch.from_numpy(A).cuda(), k=12, p=8, q=1, seed=4, residual=True)
@@ -220,6 +246,20 @@ def test_nonfinite_input_is_reported(R, dtype):
     out = R.solve(torch.from_numpy(A).to(dtype).cuda(), k=20, p=10, q=1, seed=0)
     torch.cuda.synchronize()
     assert out["info_tensor"].item() & R.INFO_NONFINITE
+
+
+@pytest.mark.parametrize("m,n,k", [(500, 300, 40), (700, 400, 190)])
+def test_jacobi_sweep_cap_is_reported(R, m, n, k):
+    """A sweep cap of 1 stops the small SVD's Jacobi iteration before it
+    converges (both forms: l <= 128 in registers, l > 128 block pairs) and
+    sets RSVD_INFO_JACOBI_NOT_CONVERGED; the default cap does not."""
+    sig = W.spectrum_geometric(n, 0.97)
+    Ad = torch.from_numpy(W.known_spectrum(m, n, sig, 5, 6)).cuda()
+    capped = R.solve(Ad, k=k, p=10, q=0, seed=1, jacobi_max_sweeps=1)
+    full = R.solve(Ad, k=k, p=10, q=0, seed=1)
+    torch.cuda.synchronize()
+    assert capped["info_tensor"].item() & R.INFO_JACOBI_NOT_CONVERGED
+    assert full["info_tensor"].item() == 0
 
 
 def test_invalid_arguments_raise(R):

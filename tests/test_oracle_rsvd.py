@@ -212,3 +212,18 @@ def test_spectral_estimator_converges_and_bounds():
             est = spectral_norm_power(G, iters=iters, block=16, seed=t)
             assert est <= s1 * (1 + 1e-13)
             assert est >= 0.5 * s1
+
+
+def test_alg4_beats_alg3_at_large_q():
+    """Section 3.3: without orthonormalisation between the products of the
+    power scheme, round-off erases the information of the smaller singular
+    values as q grows, which Algorithm 4 avoids.  Eq. (4.1) stand-in with a
+    gap of 10 after sigma_15, k = 20, p = 5, FP64: the two agree at q = 1;
+    Algorithm 4's error keeps decreasing with q, while Algorithm 3's grows
+    from q = 3 on and is several times larger at q = 8."""
+    A = W.eq41_matrix(10.0, 1, 2)
+    e3 = {q: residual_norms(A, rsvd_alg3(A, 20, 5, q, seed=0)["Q"])[0] for q in (1, 2, 4, 8)}
+    e4 = {q: residual_norms(A, rsvd_alg4(A, 20, 5, q, seed=0)["Q"])[0] for q in (1, 2, 4, 8)}
+    assert abs(e3[1] - e4[1]) <= 1e-8 * e4[1]
+    assert e4[8] <= e4[4] <= e4[2] <= e4[1]
+    assert e3[4] > e3[2] and e3[8] > 3.0 * e4[8]

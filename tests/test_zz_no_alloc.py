@@ -69,7 +69,7 @@ def test_noalloc_refuses_a_problem_beyond_the_scratch(R):
     lib = R.load_library()
     h = R._handle("cuda:0")
     M = R.rsvd_matrix(0x100000, R.RSVD_F32, 0, 32768, 16384, 16384)
-    prm = R.rsvd_params(256, 16, 2, 0, 0, 0, 0, 0, -1, 0)
+    prm = R.make_params(256, 16, 2)
     nb = ctypes.c_size_t()
     assert lib.rsvd_workspace_size(h, ctypes.byref(M), ctypes.byref(prm), ctypes.byref(nb)) == 0
     assert nb.value > R.NOALLOC_SCRATCH_BYTES
