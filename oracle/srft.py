@@ -64,11 +64,15 @@ def srft_columns(seed, n, l):
 
 
 def dct2_column(n, c):
-    """Column c of the orthonormal DCT-II matrix F (length n)."""
-    i = np.arange(n, dtype=np.float64)
+    """Column c of the orthonormal DCT-II matrix F (length n).  The cosine's
+    argument pi (2 i + 1) c / (2 n) is reduced modulo 2 pi in exact integer
+    arithmetic first (the same function, evaluated without the rounding of
+    a large argument)."""
     if c == 0:
         return np.full(n, np.sqrt(1.0 / n))
-    return np.sqrt(2.0 / n) * np.cos(np.pi * (2.0 * i + 1.0) * c / (2.0 * n))
+    i = np.arange(n, dtype=np.int64)
+    m = ((2 * i + 1) * int(c)) % (4 * n)
+    return np.sqrt(2.0 / n) * np.cos(np.pi * m.astype(np.float64) / (2.0 * n))
 
 
 def srft_omega(seed, n, l):
