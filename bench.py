@@ -27,6 +27,7 @@ if ROOT not in sys.path:
 
 METRIC = "RSVD solves/s + MFMA TFLOP/s at fixed rel. error vs FP64; p50/p99 latency"
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}      # MI355X dense MFMA peaks
+PEAK_VALU_TFLOPS = {"f32": 157.3, "f64": 78.6}  # MI355X vector peaks
 HBM_PEAK_GBS = 8000.0                          # MI355X HBM3E
 LP_KIND_NAMES = {0: "sketch A*Omega (lp_gemm_kernel<AB,false,true,LT>)",
                  1: "A*W (lp_gemm_kernel<AB,false,false,LT>)",
@@ -46,6 +47,49 @@ def _describe(name, cfg):
         spec = "60 Gaussian bumps + N(0,0.05^2) noise"
     return (f"{name}: A {cfg['m']}x{cfg['n']} {cfg['dtype']}, {spec}, Haar U,V (numpy PCG64 seeds 1,2); "
             f"k={cfg['k']} p={cfg['p']} q={cfg['q']}; Philox Omega seed 0")
+
+
+def _cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo) for the oracle baseline."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([d.get("num_threads", 1) for d in threadpool_info()] or [1]))
+    except Exception:
+        return len(os.sched_getaffinity(0))
+
+
+def _oracle_single_thread(Ah, k, p, q, budget_s=10.0):
+    """Whole FP64 oracle solves with one BLAS thread, for the small
+    configurations: solves/s and the number of solves timed."""
+    from threadpoolctl import threadpool_limits
+    from oracle.rsvd import rsvd_alg4
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        n = 0
+        while True:
+            rsvd_alg4(Ah, k, p, q, seed=0)
+            n += 1
+            if time.perf_counter() - t0 >= budget_s or n >= 200:
+                break
+        return n / (time.perf_counter() - t0), n
+
+
+def _jacobi_flops(l, sweeps):
+    """Algorithmic work of the small SVD's one-sided Jacobi iteration on the
+    l x l factor: per pair and sweep one inner product (2 l flops) and the
+    update of the two columns (4 l flops), l (l - 1) / 2 pairs per sweep."""
+    return float(sweeps) * l * (l - 1) / 2.0 * 6.0 * l
 
 
 def _time_solver(torch, solver, steps, warmup):
@@ -72,8 +116,11 @@ def bench_lowp(args, cfg, A, torch, rsvd, workloads):
     m, n, k, p, q = cfg["m"], cfg["n"], cfg["k"], cfg["p"], cfg["q"]
     dev = A.device
     forms = {}
+    stored = {}                                   # the low-precision copies, for the oracle leg
     for name in ("f32", "bf16", "fp8"):
         M = A if name == "f32" else rsvd.quantize(A, rsvd.RSVD_BF16 if name == "bf16" else rsvd.RSVD_FP8_E4M3)
+        if name != "f32" and not args.no_cpu_baseline:
+            stored[name] = (M.data.cpu().numpy(), M.col_scale.cpu().numpy() if M.col_scale is not None else None)
         solver = rsvd.Solver(M, k, p, q, seed=0)
         l = solver.l
         dt, lat = _time_solver(torch, solver, args.steps, args.warmup)
@@ -127,25 +174,38 @@ def bench_lowp(args, cfg, A, torch, rsvd, workloads):
         "roofline": forms["bf16"]["roofline"],
     }
     if not args.no_cpu_baseline:
+        # Errors against the FP64 oracle, per form: on the FP32 master (cast to
+        # FP64) with the form's own number of power iterations, and for BF16
+        # and FP8 also on the dequantized stored matrix.
+        from oracle.quant import dequantize_bf16, dequantize_fp8
         from oracle.rsvd import rsvd_alg4
+
+        def errs(S, ref):
+            return {"sigma_normwise_max": float(np.max(np.abs(S - ref["S"])) / ref["S"][0]),
+                    "sigma_relative_max": float(np.max(np.abs(S - ref["S"]) / ref["S"]))}
+
         Ah = A.double().cpu().numpy()
-        print("bench: running the FP64 CPU oracle on the FP32 matrix ...", file=sys.stderr, flush=True)
+        print("bench: FP64 CPU oracle on the FP32 matrix ...", file=sys.stderr, flush=True)
         tc = time.perf_counter()
         ref = rsvd_alg4(Ah, k, p, q, seed=0)
         tcpu = time.perf_counter() - tc
-        del Ah
-        try:
-            from threadpoolctl import threadpool_info
-            threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-        except Exception:
-            threads = len(os.sched_getaffinity(0))
-        out["cpu_baseline"] = {"value": 1.0 / tcpu, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+        out["cpu_baseline"] = {"value": 1.0 / tcpu, "unit": "solves/s", "cores": _blas_threads(), "kind": "oracle",
                                "sample": f"1 full FP64 solve of the same workload ({m}x{n}, k={k}, p={p}, q={q}), "
-                                         f"{tcpu:.1f} s wall clock incl. Omega generation"}
-        for f in forms.values():
-            f["rel_err_vs_fp64_oracle"] = {
-                "sigma_normwise_max": float(np.max(np.abs(f["S"] - ref["S"])) / ref["S"][0]),
-                "sigma_relative_max": float(np.max(np.abs(f["S"] - ref["S"]) / ref["S"]))}
+                                         f"{tcpu:.1f} s wall clock incl. Omega generation",
+                               "cpu_model": _cpu_model()}
+        forms["f32"]["rel_err_vs_fp64_oracle"] = errs(forms["f32"]["S"], ref)
+        print(f"bench: oracle {tcpu:.1f} s; with q = {q + 1} ...", file=sys.stderr, flush=True)
+        ref1 = rsvd_alg4(Ah, k, p, q + 1, seed=0)
+        del Ah
+        for name in ("bf16", "fp8"):
+            data, scale = stored.pop(name)
+            print(f"bench: FP64 CPU oracle on the dequantized {name} matrix ...", file=sys.stderr, flush=True)
+            Ad = dequantize_bf16(data.view(np.uint16)) if name == "bf16" else dequantize_fp8(data, scale)
+            del data
+            refd = rsvd_alg4(Ad, k, p, q + 1, seed=0)
+            del Ad
+            forms[name]["rel_err_vs_fp64_oracle_master"] = errs(forms[name]["S"], ref1)
+            forms[name]["rel_err_vs_fp64_oracle_dequantized"] = errs(forms[name]["S"], refd)
     for f in forms.values():
         del f["S"]
     out["forms"] = forms
@@ -254,6 +314,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="c2_fp32_8192")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c4", action="store_true", help="skip the mixed-precision forms after the default workload")
     ap.add_argument("--input", choices=("workload", "gaussian"), default="workload",
                     help="gaussian: i.i.d. N(0,1)/sqrt(n) matrix of the same shape, drawn on the device without a "
                          "QR; for hardware-counter runs, where the products' traffic does not depend on the values")
@@ -335,6 +396,8 @@ def main():
         if cnt:
             kinds[kind] = (tot, cnt)
     st1_tot, st1_cnt = rsvd.profile_read(dev, rsvd.PROFILE_STAGE1)
+    jac_tot, jac_cnt = rsvd.profile_read(dev, rsvd.PROFILE_JACOBI)
+    sweeps = int(solver.sweeps.item())
     dom = max(kinds, key=lambda kk: kinds[kk][0])
     dom_ms = kinds[dom][0] / kinds[dom][1]
     flops_launch = 2.0 * m * n * l
@@ -342,6 +405,7 @@ def main():
     peak = PEAK_TFLOPS[cfg["dtype"]]
     gemm_ms = sum(v[0] for v in kinds.values()) / args.steps
     flops_solve = (2 * q + 2) * 2.0 * m * n * l
+    jac_ms = jac_tot / max(1, jac_cnt)
 
     # The residual ||A - QQ^T A|| (spectral estimate, t = 4, and Frobenius
     # norm), optional in a solve and timed separately: ms per solve with it
@@ -395,7 +459,7 @@ def main():
         "info": info,
         "residual": {"spectral_estimate_t4": float(res_gpu[0]), "frobenius": float(res_gpu[1]),
                      "ms_per_solve": res_ms},
-        "roofline": {
+        "roofline_contraction": {
             "bound": "mfma",
             "kernel": KIND_NAMES[dom].replace("float", "double") if cfg["dtype"] == "f64" else KIND_NAMES[dom],
             "achieved": achieved,
@@ -407,16 +471,27 @@ def main():
             "avg_launch_ms": dom_ms,
             "flops_per_launch": flops_launch,
             "launches_per_solve": kinds[dom][1] / args.steps,
+            "ms_per_solve": kinds[dom][0] / args.steps,
         },
+        "small_svd_jacobi": {"ms": jac_ms, "sweeps": sweeps, "l": l},
     }
+    # The roofline of the kernel that takes the most time per solve: the
+    # product kind above, or the small SVD's Jacobi iteration (FP64 vector
+    # work on one compute unit, against the FP64 vector peak).
+    jflops = _jacobi_flops(l, sweeps)
+    if jac_ms > kinds[dom][0] / args.steps:
+        ja = jflops / (jac_ms * 1e-3) / 1e12
+        out["roofline"] = {"bound": "alu", "kernel": "small SVD one-sided Jacobi (jacobi_oe_kernel<R> / jacobi_blk_*)",
+                           "achieved": ja, "peak": PEAK_VALU_TFLOPS["f64"], "unit": "TFLOP/s",
+                           "frac": ja / PEAK_VALU_TFLOPS["f64"], "traffic": None, "avg_launch_ms": jac_ms,
+                           "flops_per_launch": jflops, "launches_per_solve": 1.0,
+                           "note": "Jacobi span of one solve; flops = sweeps * l(l-1)/2 * 6 l"}
+    else:
+        out["roofline"] = dict(out["roofline_contraction"])
 
     if not args.no_cpu_baseline and args.input == "workload":
         from oracle.rsvd import rsvd_alg4
-        try:
-            from threadpoolctl import threadpool_info
-            threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-        except Exception:
-            threads = len(os.sched_getaffinity(0))
+        threads = _blas_threads()
         Ah = A.double().cpu().numpy()
         print("bench: running the FP64 CPU oracle on the same matrix ...", file=sys.stderr, flush=True)
         # Whole solves of the same workload until about 10 s of CPU work (at most 5).
@@ -430,7 +505,11 @@ def main():
                 break
         out["cpu_baseline"] = {"value": nsol / tcpu, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
                                "sample": f"{nsol} full solve(s) of the same workload ({m}x{n}, k={k}, p={p}, "
-                                         f"q={q}) in float64, {tcpu:.1f} s wall clock incl. Omega generation"}
+                                         f"q={q}) in float64, {tcpu:.1f} s wall clock incl. Omega generation",
+                               "cpu_model": _cpu_model()}
+        if m * n <= 2048 * 2048:
+            st_rate, st_n = _oracle_single_thread(Ah, k, p, q)
+            out["cpu_baseline"]["single_thread"] = {"value": st_rate, "unit": "solves/s", "solves": st_n}
         S_ref = ref["S"]
         from oracle.rsvd import spectral_norm_power
         E = Ah - ref["Q"] @ (ref["Q"].T @ Ah)
@@ -444,6 +523,22 @@ def main():
     sig = workloads.config_sigma(args.config)
     if sig is not None and args.input == "workload":
         out["err_vs_true_spectrum_normwise"] = float(np.max(np.abs(S_gpu - sig[:k])) / sig[0])
+    if args.config == "c2_fp32_8192" and args.input == "workload" and not args.no_c4:
+        # The largest configuration, timed in the same run: the mixed-precision
+        # workload in its three storage forms (5 timed solves each, no oracle
+        # leg here; its errors against the FP64 oracle come from
+        # `--config c4_mixed_32768x16384`).
+        del solver, A
+        torch.cuda.empty_cache()
+        c4 = "c4_mixed_32768x16384"
+        print(f"bench: generating {c4} ...", file=sys.stderr, flush=True)
+        A4 = workloads.config_matrix(c4, device=dev).float().contiguous()
+        torch.cuda.synchronize()
+        a4 = argparse.Namespace(steps=5, warmup=2, no_cpu_baseline=True, config=c4)
+        r4 = bench_lowp(a4, workloads.CONFIGS[c4], A4, torch, rsvd, workloads)
+        out[c4] = {"workload": r4["config"]["workload"], "forms": r4["forms"]}
+        del A4
+        torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
 

@@ -132,9 +132,15 @@ typedef struct {
                                       stay inside the float range. */
     int32_t jacobi_max_sweeps;     /* sweep cap of the small SVD's Jacobi iteration, 0 = default
                                       (60; 30 for l > 128); reaching it sets RSVD_INFO_JACOBI_NOT_CONVERGED */
-    int32_t reserved0;
+    int32_t test_matrix;           /* RSVD_TEST_GAUSSIAN (0): Omega standard Gaussian (rsvd_omega);
+                                      RSVD_TEST_SRFT (1): the subsampled randomized trigonometric test
+                                      matrix of FastRandRF (Appendix A; see rsvd_srft_omega), generated
+                                      in the sketch kernel like the Gaussian one.  F32 / F64 A only. */
     int32_t reserved1;
 } rsvd_params;
+
+#define RSVD_TEST_GAUSSIAN 0
+#define RSVD_TEST_SRFT 1
 
 #define RSVD_ORTH_AUTO 0
 #define RSVD_ORTH_CHOLQR2 1
@@ -151,6 +157,8 @@ typedef struct {
                                       [1] = Frobenius norm (an entry not requested is 0) */
     int32_t* info;                 /* required; RSVD_INFO_* bit flags */
     void* Q;  int64_t ldq;         /* nullable; m x l, row-major, ldq >= l */
+    int32_t* jacobi_sweeps;        /* nullable, device: sweeps run by the small SVD's one-sided Jacobi
+                                      iteration (Algorithm 4 step 7), the last of which rotates nothing */
 } rsvd_result;
 
 /* Create a handle bound to HIP device `device` (host memory only; the
@@ -211,7 +219,9 @@ const char* rsvd_status_string(rsvd_status s);
  * number of launches, and forgets those records (kind 3 forgets all product
  * records).  Kind 5 is the range finder of each solve (Stage 1 of Algorithm
  * 4: the sketch, the power iterations and every orthonormalisation, from the
- * first kernel after the flag reset to the last orth), one record per solve. */
+ * first kernel after the flag reset to the last orth), one record per solve.
+ * Kind 6 is the one-sided Jacobi iteration of the small SVD (Algorithm 4
+ * step 7: every kernel of it), one record per solve. */
 rsvd_status rsvd_profile_enable(rsvd_handle* h, int32_t enable);
 rsvd_status rsvd_profile_read(rsvd_handle* h, int32_t kind, double* total_ms, int64_t* launches);
 
@@ -279,6 +289,19 @@ rsvd_status rsvd_server_destroy(rsvd_server* s);
  * `dtype`.  out: n x l row-major, ld >= l. */
 rsvd_status rsvd_omega(int32_t dtype, uint64_t seed, uint32_t stream_id, int64_t n, int64_t l,
                        void* out, int64_t ld, void* stream);
+
+/* The SRFT test matrix of FastRandRF (Appendix A: Omega = sqrt(n / l) D F R),
+ * materialised (a solve generates it inside the sketch kernel).  Real form:
+ * D = diag(d_i), d_i = -1 if bit 0 of word (i mod 4) of the Philox4x32-10
+ * block (i / 4, 0, 4, 0) under key (seed) is set, else +1; F the orthonormal
+ * DCT-II, F[i][c] = sqrt(2 / n) cos(pi (2 i + 1) c / (2 n)) (sqrt(1 / n) for
+ * c = 0); R the l columns c_0 .. c_{l-1} drawn by Floyd's algorithm: step t
+ * (j = n - l + t) takes x = floor(w (j + 1) / 2^32), w word 0 of block
+ * (t, 1, 4, 0), unless an earlier step took x, else j.  Omega^T Omega =
+ * (n / l) I.  out: n x l row-major (ld >= l) of `dtype` (F32 / F64); cols
+ * (device, l int32) receives c_0 .. c_{l-1}.  1 <= l <= min(n, 288). */
+rsvd_status rsvd_srft_omega(int32_t dtype, uint64_t seed, int64_t n, int64_t l, void* out, int64_t ld,
+                            int32_t* cols, void* stream);
 
 /* Raw Philox4x32-10 words: for each of `count` counter pairs (g, j) in
  * ctr (device, 2*count uint32), writes the 4 words of block

@@ -119,6 +119,7 @@ __global__ __launch_bounds__(256) void skinny_gemm_kernel(GemmArgs g) {
     V ra[NVA];
     V rb[OMEGA ? 1 : NVB];
     T ro[OMEGA ? NOB : 1][4];
+    const T srft_sc0 = (T)sqrt(1.0 / (double)g.ncols), srft_sc1 = (T)sqrt(2.0 / (double)g.ncols);
 
     // Tiles wholly inside A (and the slice) take unguarded 16-byte loads.
     const bool rows_full = avec && (row0 + BM <= g.M);
@@ -169,7 +170,10 @@ __global__ __launch_bounds__(256) void skinny_gemm_kernel(GemmArgs g) {
                 const int gi = idx / L, j = idx % L;
                 const int64_t r = k0 + 4 * gi;
                 if (idx < BK / 4 * L && j < g.ncols && r < kend) {
-                    omega_block<T>(g.seed, 0u, (uint32_t)(r >> 2), (uint32_t)j, ro[it]);
+                    if (g.omega_kind == kOmegaSrft)
+                        srft_block<T>(g.seed, (uint32_t)(r >> 2), g.srft_cols[j], g.K, srft_sc0, srft_sc1, ro[it]);
+                    else
+                        omega_block<T>(g.seed, 0u, (uint32_t)(r >> 2), (uint32_t)j, ro[it]);
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
                         if (r + e >= kend) ro[it][e] = T(0);
@@ -402,6 +406,62 @@ hipError_t launch_splitk_reduce_f32(const float* partials, int64_t M, int L, int
     const int64_t nvec = M * (L / 4);
     hipLaunchKernelGGL((splitk_reduce_kernel<float, kMaxSplits>), dim3((unsigned)ceil_div(nvec, 256)), dim3(256), 0, s,
                        partials, M, L, splits, Y, ldy, wcols);
+    return hipGetLastError();
+}
+
+// ---- SRFT test matrix: sampled columns (Floyd's algorithm) ----
+// One wavefront; step t (j = n - l + t) draws x = floor(w (j + 1) / 2^32)
+// from word 0 of block (t, 1, 4, 0) and takes x unless an earlier step took
+// it, else j.  The membership test is spread over the lanes.
+__global__ __launch_bounds__(64) void srft_columns_kernel(uint64_t seed, int64_t n, int l, int* cols) {
+    __shared__ int taken[kMaxL];
+    const int lane = threadIdx.x;
+    for (int t = 0; t < l; ++t) {
+        const int64_t j = n - l + t;
+        const Philox4 w = philox4x32_10((uint32_t)t, 1u, kSrftStream, 0u, (uint32_t)seed, (uint32_t)(seed >> 32));
+        const int x = (int)(((uint64_t)w.x[0] * (uint64_t)(j + 1)) >> 32);
+        bool dup = false;
+        for (int u = lane; u < t; u += 64) dup |= taken[u] == x;
+        const bool any = __any(dup);
+        const int pick = any ? (int)j : x;
+        if (lane == 0) {
+            taken[t] = pick;
+            cols[t] = pick;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_srft_columns(uint64_t seed, int64_t n, int l, int* cols, hipStream_t s) {
+    if (l < 1 || l > kMaxL || n < l || n > ((int64_t)1 << 31)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(srft_columns_kernel, dim3(1), dim3(64), 0, s, seed, n, l, cols);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void srft_omega_kernel(uint64_t seed, int64_t n, int l, const int* cols, T* out, int64_t ld) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t groups = ceil_div(n, 4);
+    if (idx >= groups * l) return;
+    const int64_t gidx = idx / l;
+    const int j = (int)(idx % l);
+    const T sc0 = (T)sqrt(1.0 / (double)l), sc1 = (T)sqrt(2.0 / (double)l);
+    T z[4];
+    srft_block<T>(seed, (uint32_t)gidx, cols[j], n, sc0, sc1, z);
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        if (4 * gidx + e < n) out[(4 * gidx + e) * ld + j] = z[e];
+}
+
+hipError_t launch_srft_omega(int dtype, uint64_t seed, int64_t n, int l, const int* cols, void* out, int64_t ld,
+                             hipStream_t s) {
+    const int64_t total = ceil_div(n, 4) * l;
+    if (total == 0) return hipSuccess;
+    dim3 grid((unsigned)ceil_div(total, 256));
+    if (dtype == 0)
+        hipLaunchKernelGGL(srft_omega_kernel<double>, grid, dim3(256), 0, s, seed, n, l, cols, (double*)out, ld);
+    else
+        hipLaunchKernelGGL(srft_omega_kernel<float>, grid, dim3(256), 0, s, seed, n, l, cols, (float*)out, ld);
     return hipGetLastError();
 }
 

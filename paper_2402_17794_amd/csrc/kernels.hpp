@@ -18,7 +18,8 @@ struct DevFlags {
     int pass2_off;      // the second CholeskyQR pass of the current orth does not run
     int fb_count;       // grid barrier of the Householder fallback: arrivals (0 between barriers)
     int fb_gen;         // and its generation
-    int pad[59];
+    int jacobi_sweeps;  // sweeps the small SVD's Jacobi iteration ran (the last one rotates nothing)
+    int pad[58];
 };
 
 // ---- skinny products with A (gemm.hip) ----
@@ -33,7 +34,10 @@ struct GemmArgs {
     void* Y; int64_t ldy;
     void* partials;            // splits * M * L elements (splits > 1)
     int splits;
+    int omega_kind;            // X == NULL: kOmegaGaussian (default) or kOmegaSrft
+    const int* srft_cols;      // kOmegaSrft: the ncols sampled DCT columns (device)
 };
+constexpr int kOmegaGaussian = 0, kOmegaSrft = 1;
 size_t gemm_partials_elems(int dtype, int64_t M, int64_t K, int ncols, int* splits_out);
 int gemm_row_tiles(int dtype, int64_t M, int ncols);
 // product_done (optional) is recorded on s right after the product kernel,
@@ -152,8 +156,14 @@ hipError_t launch_copy2d(int dtype, const void* src, int64_t lds, int64_t rows, 
 // Zero `count` ints and the flags block.
 hipError_t launch_init(int* counters, int count, DevFlags* flags, hipStream_t s);
 // Copy the flags' info word into the caller's info (OR-ed).
-hipError_t launch_export_info(const DevFlags* flags, int* info, hipStream_t s);
+// sweeps (nullable): also the Jacobi sweep count of the small SVD.
+hipError_t launch_export_info(const DevFlags* flags, int* info, hipStream_t s, int* sweeps = nullptr);
 
+// SRFT test matrix: the l sampled columns of the DCT-II (Floyd's algorithm
+// on Philox stream 4), one wavefront; and the matrix materialised.
+hipError_t launch_srft_columns(uint64_t seed, int64_t n, int l, int* cols, hipStream_t s);
+hipError_t launch_srft_omega(int dtype, uint64_t seed, int64_t n, int l, const int* cols, void* out, int64_t ld,
+                             hipStream_t s);
 // Omega materialised / raw Philox words (test entry points).
 hipError_t launch_omega(int dtype, uint64_t seed, uint32_t stream, int64_t n, int64_t l, void* out, int64_t ld,
                         hipStream_t s);

@@ -94,7 +94,7 @@ struct Plan {
     int ncounters = 0;
     int splits_nn = 1, splits_tn = 1;
     size_t counters, flags, part, Y, Q, W, GP, R, Rinv, Ut, Mv, sigma, shift, sign, amax_val, amax_idx, H, Qw,
-        work, res_part, res;
+        work, res_part, res, cols;
     // Low-precision A: format, prepared operand (L x ldt) and its scales.
     int afmt = 0;
     int splits_lp_nn = 1, splits_lp_tn = 1;
@@ -161,6 +161,7 @@ bool make_plan(int adtype, int64_t m, int64_t n, int64_t k, int64_t p, int64_t q
     P.work = c.take(sizeof(double) * kJacobiWorkDoubles);
     P.res_part = c.take(sizeof(double) * residual_partials(m, n));
     P.res = c.take(sizeof(double) * 2);
+    P.cols = c.take(sizeof(int) * (size_t)P.L);
     if (is_lowp(adtype)) {
         P.Xt = c.take((size_t)lowp_bytes(adtype) * (size_t)P.L * (size_t)P.ldt);
         P.tsc = c.take(sizeof(float) * (size_t)P.L);
@@ -238,8 +239,10 @@ rsvd_status run_orth(const Plan& P, void* ws, int dtype, int64_t rows, const voi
 // Timed (rsvd_profile_*) when h is not NULL and profiling is on.
 rsvd_status run_product(rsvd_handle* h, const Plan& P, void* ws, const rsvd_matrix* A, int trans, const void* X,
                         int64_t ldx, uint64_t seed, int cols, int wcols, int splits, void* Yout, int64_t ldy,
-                        hipStream_t s, int kind = -1) {
+                        hipStream_t s, int kind = -1, const int* srft_cols = nullptr) {
     GemmArgs g{};
+    g.omega_kind = srft_cols ? kOmegaSrft : kOmegaGaussian;
+    g.srft_cols = srft_cols;
     g.A = A->data;
     g.lda = A->ld;
     g.trans = trans;
@@ -312,12 +315,13 @@ rsvd_status run_product_lowp(rsvd_handle* h, const Plan& P, void* ws, const rsvd
 }
 
 // The products of Algorithm 4 on the solve's L-column buffers.
+// srft_cols: the sketch uses the SRFT test matrix with these sampled columns.
 rsvd_status run_gemm(rsvd_handle* h, const Plan& P, void* ws, const rsvd_matrix* A, int trans, const void* X,
-                     uint64_t seed, void* Yout, hipStream_t s, int kind = -1) {
+                     uint64_t seed, void* Yout, hipStream_t s, int kind = -1, const int* srft_cols = nullptr) {
     if (is_lowp(A->dtype)) return run_product_lowp(h, P, ws, A, trans, X, seed, Yout, s);
     const int cols = trans ? P.L : (X ? P.L : (int)P.l);
     return run_product(h, P, ws, A, trans, X, P.L, seed, cols, P.L, trans ? P.splits_tn : P.splits_nn, Yout, P.L, s,
-                       kind);
+                       kind, X ? nullptr : srft_cols);
 }
 
 // The FP32 copy of a low-precision A (for the Rayleigh-Ritz projection and
@@ -410,6 +414,8 @@ rsvd_status check_params(const rsvd_matrix* A, const rsvd_params* p) {
     if (p->orth < RSVD_ORTH_AUTO || p->orth > RSVD_ORTH_HOUSEHOLDER) return RSVD_ERR_INVALID_ARG;
     if (p->algorithm != 0 && p->algorithm != 3 && p->algorithm != 4) return RSVD_ERR_INVALID_ARG;
     if (p->jacobi_max_sweeps < 0 || p->jacobi_max_sweeps > 1000) return RSVD_ERR_INVALID_ARG;
+    if (p->test_matrix != RSVD_TEST_GAUSSIAN && p->test_matrix != RSVD_TEST_SRFT) return RSVD_ERR_INVALID_ARG;
+    if (p->test_matrix == RSVD_TEST_SRFT && is_lowp(A->dtype)) return RSVD_ERR_UNSUPPORTED;
     if (is_lowp(A->dtype) && p->residual && !A->master) return RSVD_ERR_INVALID_ARG;
     if (round_up(std::min<int64_t>(p->k + p->p, mn), 16) > kMaxL) return RSVD_ERR_UNSUPPORTED;
     return RSVD_OK;
@@ -467,12 +473,12 @@ rsvd_status rsvd_profile_enable(rsvd_handle* h, int32_t enable) {
 }
 
 rsvd_status rsvd_profile_read(rsvd_handle* h, int32_t kind, double* total_ms, int64_t* launches) {
-    if (!h || !total_ms || !launches || kind < 0 || kind > 5) return RSVD_ERR_INVALID_ARG;
+    if (!h || !total_ms || !launches || kind < 0 || kind > 6) return RSVD_ERR_INVALID_ARG;
     double tot = 0.0;
     int64_t cnt = 0;
     std::vector<rsvd_handle::Rec> keep;
     for (auto& r : h->recs) {
-        const bool match = kind == 3 ? r.kind != 5 : r.kind == kind;    // kind 3: every product kind
+        const bool match = kind == 3 ? (r.kind <= 2 || r.kind == 4) : r.kind == kind;   // kind 3: every product
         if (!match) { keep.push_back(r); continue; }
         if (hipEventSynchronize(r.stop) != hipSuccess) return RSVD_ERR_DEVICE;
         float ms = 0.0f;
@@ -550,10 +556,15 @@ rsvd_status solve_impl(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* 
         RSVD_TRY(hipEventRecord(stage1.start, s));
     }
     if (A->dtype == RSVD_FP8_E4M3) RSVD_TRY(launch_vec_max(A->col_scale, A->cols, at<float>(ws, P.smax), s));
+    const int* srft = nullptr;
+    if (params->test_matrix == RSVD_TEST_SRFT) {
+        RSVD_TRY(launch_srft_columns(params->seed, P.n, (int)P.l, at<int>(ws, P.cols), s));
+        srft = at<int>(ws, P.cols);
+    }
     if (params->algorithm == 3) {
         // Algorithm 3 (Section 3.2): Y = A Omega, then q times Z = A^T Y,
         // Y = A Z with no orthonormalisation in between; orth once at the end.
-        if ((st = run_gemm(hp, P, ws, A, 0, nullptr, params->seed, Y, s)) != RSVD_OK) return st;
+        if ((st = run_gemm(hp, P, ws, A, 0, nullptr, params->seed, Y, s, -1, srft)) != RSVD_OK) return st;
         for (int64_t t = 0; t < qeff; ++t) {
             if ((st = run_gemm(hp, P, ws, A, 1, Y, 0, W, s)) != RSVD_OK) return st;
             if ((st = run_gemm(hp, P, ws, A, 0, W, 0, Y, s)) != RSVD_OK) return st;
@@ -561,7 +572,7 @@ rsvd_status solve_impl(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* 
         if ((st = run_orth(P, ws, dt, P.m, Y, Q, om, s)) != RSVD_OK) return st;
     } else {
         // Stage 1: steps 1-3, sketch with the generated test matrix, then orth.
-        if ((st = run_gemm(hp, P, ws, A, 0, nullptr, params->seed, Y, s)) != RSVD_OK) return st;
+        if ((st = run_gemm(hp, P, ws, A, 0, nullptr, params->seed, Y, s, -1, srft)) != RSVD_OK) return st;
         if ((st = run_orth(P, ws, dt, P.m, Y, Q, om, s)) != RSVD_OK) return st;
         // Steps 4-5: q power iterations, each product re-orthonormalised.
         for (int64_t t = 0; t < qeff; ++t) {
@@ -591,8 +602,19 @@ rsvd_status solve_impl(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* 
     RSVD_TRY(launch_gram(dt, Bt, L, P.n, L, at<double>(ws, P.GP), nullptr, s));
     RSVD_TRY(launch_chol(at<double>(ws, P.GP), P.n, (int)P.l, L, R, at<double>(ws, P.Rinv), flags, 2, shift,
                          at<double>(ws, P.work), 0.0, s));
+    rsvd_handle::Rec jac{6, nullptr, nullptr};
+    if (hp) {
+        jac.start = h->get_event();
+        jac.stop = h->get_event();
+        if (!jac.start || !jac.stop) return RSVD_ERR_DEVICE;
+        RSVD_TRY(hipEventRecord(jac.start, s));
+    }
     RSVD_TRY(launch_jacobi(R, (int)P.l, L, shift, sigma, Ut, Mv, flags, at<double>(ws, P.work), s,
                            params->jacobi_max_sweeps));
+    if (hp) {
+        RSVD_TRY(hipEventRecord(jac.stop, s));
+        h->recs.push_back(jac);
+    }
     // V = B^T U~ Sigma^{-1}, written transposed into Vt, with column argmax partials.
     RSVD_TRY(launch_apply(dt, Bt, L, P.n, L, Mv, L, r, out->Vt, out->ldvt, 1, nullptr, nullptr, av, ai, 0, s));
     RSVD_TRY(launch_signs(av, ai, apply_blocks(P.n), r, sigma, out->S, sign, s));
@@ -608,7 +630,7 @@ rsvd_status solve_impl(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* 
         if ((st = run_spectral(P, ws, &Am, Q, params->seed, iters, out->residual, params->residual & 2, s)) != RSVD_OK)
             return st;
     }
-    RSVD_TRY(launch_export_info(flags, out->info, s));
+    RSVD_TRY(launch_export_info(flags, out->info, s, out->jacobi_sweeps));
     return RSVD_OK;
 }
 
@@ -638,6 +660,15 @@ rsvd_status rsvd_omega(int32_t dtype, uint64_t seed, uint32_t stream_id, int64_t
     if (dtype != RSVD_F32 && dtype != RSVD_F64) return RSVD_ERR_INVALID_ARG;
     if (n < 0 || l < 0 || (n * l > 0 && (!out || ld < l)) || n > ((int64_t)1 << 33)) return RSVD_ERR_INVALID_ARG;
     RSVD_TRY(launch_omega(dtype, seed, stream_id, n, l, out, ld, as_stream(stream)));
+    return RSVD_OK;
+}
+
+rsvd_status rsvd_srft_omega(int32_t dtype, uint64_t seed, int64_t n, int64_t l, void* out, int64_t ld, int32_t* cols,
+                            void* stream) {
+    if (dtype != RSVD_F32 && dtype != RSVD_F64) return RSVD_ERR_INVALID_ARG;
+    if (l < 1 || l > kMaxL || n < l || n > ((int64_t)1 << 31) || !out || !cols || ld < l) return RSVD_ERR_INVALID_ARG;
+    RSVD_TRY(launch_srft_columns(seed, n, (int)l, cols, as_stream(stream)));
+    RSVD_TRY(launch_srft_omega(dtype, seed, n, (int)l, cols, out, ld, as_stream(stream)));
     return RSVD_OK;
 }
 

@@ -86,9 +86,9 @@ private:
 
 // Everything about a request that decides which kernels rsvd_solve launches.
 struct BucketKey {
-    int64_t v[16];
+    int64_t v[17];
     bool operator==(const BucketKey& o) const {
-        for (int i = 0; i < 16; ++i)
+        for (int i = 0; i < 17; ++i)
             if (v[i] != o.v[i]) return false;
         return true;
     }
@@ -157,7 +157,8 @@ BucketKey bucket_of(const Request* r) {
     return BucketKey{{(int64_t)r->A.dtype, r->A.rows, r->A.cols, p.k, p.p, p.q, (int64_t)p.extra_power_pass,
                       (int64_t)p.residual, (int64_t)p.residual_iters, (int64_t)p.return_full_l,
                       (int64_t)p.orth, r->out.Q != nullptr, r->A.master != nullptr,
-                      r->A.col_scale != nullptr, (int64_t)p.algorithm, (int64_t)p.jacobi_max_sweeps}};
+                      r->A.col_scale != nullptr, (int64_t)p.algorithm, (int64_t)p.jacobi_max_sweeps,
+                      (int64_t)p.test_matrix}};
 }
 
 }  // namespace

@@ -204,6 +204,7 @@ __global__ __launch_bounds__(512) void jacobi_oe_kernel(const double* __restrict
     const int sr = hasR ? 0 : 1, gr = hasR ? gi + 1 : gi;
     const int sl = hasL ? 1 : 0, gl = hasL ? gi - 1 : gi;
     bool converged = (l < 2), small = false;
+    int sweeps_run = 0;
     for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
@@ -257,6 +258,7 @@ __global__ __launch_bounds__(512) void jacobi_oe_kernel(const double* __restrict
                 break;
             }
         }
+        ++sweeps_run;
         int rot = 0, big = 0;
         for (int h = 0; h < G; ++h) {
             {   // even round: pair (2g, 2g + 1); position 2g takes the rotated second column
@@ -314,6 +316,7 @@ __global__ __launch_bounds__(512) void jacobi_oe_kernel(const double* __restrict
         small = !__syncthreads_or(big);
     }
     if (!converged && tid == 0) atomicOr(&flags->info, RSVD_INFO_JACOBI_NOT_CONVERGED);
+    if (tid == 0) flags->jacobi_sweeps = sweeps_run;
 
 #pragma unroll
     for (int k = 0; k < R; ++k) {
@@ -513,7 +516,12 @@ __global__ __launch_bounds__(512) void jacobi_blk_finish_kernel(const double* __
     const int* rotw = reinterpret_cast<const int*>(work + (size_t)kMaxL * kMaxL);
     const double sc4 = work[(size_t)kMaxL * kMaxL + kJacobiBlockSweeps / 2 + 2];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    if (tid == 0 && rotw[sweeps - 1] != 0) atomicOr(&flags->info, RSVD_INFO_JACOBI_NOT_CONVERGED);
+    if (tid == 0) {
+        if (rotw[sweeps - 1] != 0) atomicOr(&flags->info, RSVD_INFO_JACOBI_NOT_CONVERGED);
+        int run = 0;                  // sweeps until (and with) the first one that rotated nothing
+        while (run < sweeps && rotw[run] != 0) ++run;
+        flags->jacobi_sweeps = min(run + 1, sweeps);
+    }
     for (int c = wid; c < l; c += 8) {
         double s2 = 0.0;
         for (int r = lane; r < l; r += 64) s2 = fma(X[(int64_t)c * kMaxL + r], X[(int64_t)c * kMaxL + r], s2);
@@ -666,10 +674,13 @@ hipError_t launch_init(int* counters, int count, DevFlags* flags, hipStream_t s)
     return hipGetLastError();
 }
 
-__global__ void export_info_kernel(const DevFlags* flags, int* info) { *info = flags->info; }
+__global__ void export_info_kernel(const DevFlags* flags, int* info, int* sweeps) {
+    *info = flags->info;
+    if (sweeps) *sweeps = flags->jacobi_sweeps;
+}
 
-hipError_t launch_export_info(const DevFlags* flags, int* info, hipStream_t s) {
-    hipLaunchKernelGGL(export_info_kernel, dim3(1), dim3(1), 0, s, flags, info);
+hipError_t launch_export_info(const DevFlags* flags, int* info, hipStream_t s, int* sweeps) {
+    hipLaunchKernelGGL(export_info_kernel, dim3(1), dim3(1), 0, s, flags, info, sweeps);
     return hipGetLastError();
 }
 

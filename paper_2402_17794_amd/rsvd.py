@@ -60,22 +60,27 @@ class rsvd_params(ctypes.Structure):
                 ("residual", ctypes.c_int32), ("return_full_l", ctypes.c_int32),
                 ("orth", ctypes.c_int32), ("residual_iters", ctypes.c_int32),
                 ("extra_power_pass", ctypes.c_int32), ("algorithm", ctypes.c_int32),
-                ("jacobi_max_sweeps", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+                ("jacobi_max_sweeps", ctypes.c_int32), ("test_matrix", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+
+
+TEST_GAUSSIAN, TEST_SRFT = 0, 1
 
 
 def make_params(k, p=10, q=0, seed=0, residual=0, return_full_l=False, orth=ORTH_AUTO, residual_iters=0,
-                extra_power_pass=-1, algorithm=4, jacobi_max_sweeps=0):
+                extra_power_pass=-1, algorithm=4, jacobi_max_sweeps=0, test_matrix=TEST_GAUSSIAN):
     return rsvd_params(k, p, q, seed, residual, int(return_full_l), int(orth), int(residual_iters),
-                       int(extra_power_pass), int(algorithm), int(jacobi_max_sweeps), 0, 0)
+                       int(extra_power_pass), int(algorithm), int(jacobi_max_sweeps), int(test_matrix), 0)
 
 
 class rsvd_result(ctypes.Structure):
     _fields_ = [("U", ctypes.c_void_p), ("ldu", ctypes.c_int64), ("S", ctypes.c_void_p),
                 ("Vt", ctypes.c_void_p), ("ldvt", ctypes.c_int64), ("residual", ctypes.c_void_p),
-                ("info", ctypes.c_void_p), ("Q", ctypes.c_void_p), ("ldq", ctypes.c_int64)]
+                ("info", ctypes.c_void_p), ("Q", ctypes.c_void_p), ("ldq", ctypes.c_int64),
+                ("jacobi_sweeps", ctypes.c_void_p)]
 
 
 EXPORTS = ["rsvd_create", "rsvd_destroy", "rsvd_l_used", "rsvd_workspace_size", "rsvd_solve", "rsvd_solve_noalloc",
+           "rsvd_srft_omega",
            "rsvd_status_string", "rsvd_profile_enable", "rsvd_profile_read", "rsvd_quantize", "rsvd_omega",
            "rsvd_philox_words", "rsvd_gemm_workspace_size", "rsvd_gemm", "rsvd_orth_workspace_size", "rsvd_orth",
            "rsvd_server_create", "rsvd_server_submit", "rsvd_server_poll", "rsvd_server_wait", "rsvd_server_drain",
@@ -120,6 +125,7 @@ def load_library(path=LIB_PATH):
         "rsvd_server_graph_stats": ([P, ctypes.POINTER(I64), ctypes.POINTER(I64)], I32),
         "rsvd_omega": ([I32, U64, ctypes.c_uint32, I64, I64, P, I64, P], I32),
         "rsvd_philox_words": ([U64, ctypes.c_uint32, P, I64, P, P], I32),
+        "rsvd_srft_omega": ([I32, U64, I64, I64, P, I64, P, P], I32),
         "rsvd_gemm_workspace_size": ([ctypes.POINTER(rsvd_matrix), I32, I64, ctypes.POINTER(SZ)], I32),
         "rsvd_gemm": ([P, ctypes.POINTER(rsvd_matrix), I32, P, I64, U64, I64, P, I64, P, SZ, P], I32),
         "rsvd_orth_workspace_size": ([I32, I64, I64, ctypes.POINTER(SZ)], I32),
@@ -244,7 +250,7 @@ class Solver:
 
     def __init__(self, A, k, p=10, q=0, seed=0, residual=False, return_full_l=False, force_householder=False,
                  return_q=False, stream=None, residual_iters=0, extra_power_pass=-1, noalloc=False, orth=ORTH_AUTO,
-                 algorithm=4, jacobi_max_sweeps=0):
+                 algorithm=4, jacobi_max_sweeps=0, test_matrix=TEST_GAUSSIAN):
         self.lib = load_library()
         self.A = A
         self.M = _as_matrix(A)
@@ -255,11 +261,12 @@ class Solver:
         residual = _residual_mode(residual)
         self.params = make_params(k, p, q, seed, residual, return_full_l,
                                   ORTH_HOUSEHOLDER if force_householder else orth, residual_iters, extra_power_pass,
-                                  algorithm, jacobi_max_sweeps)
+                                  algorithm, jacobi_max_sweeps, test_matrix)
         self.U = torch.empty((m, r), dtype=A.dtype, device=dev)
         self.S = torch.empty((r,), dtype=torch.float64, device=dev)
         self.Vt = torch.empty((r, n), dtype=A.dtype, device=dev)
-        self.info = torch.zeros((1,), dtype=torch.int32, device=dev)
+        self._words = torch.empty((2,), dtype=torch.int32, device=dev)
+        self.info, self.sweeps = self._words[:1], self._words[1:]        # RSVD_INFO_* bits, Jacobi sweeps
         self.res = torch.zeros((2,), dtype=torch.float64, device=dev) if residual else None
         self.Q = torch.empty((m, self.l), dtype=A.dtype, device=dev) if return_q else None
         nb = ctypes.c_size_t()
@@ -270,7 +277,7 @@ class Solver:
         self.ws = None if self.noalloc else _workspace(nb.value, dev)
         self.result = rsvd_result(self.U.data_ptr(), r, self.S.data_ptr(), self.Vt.data_ptr(), n,
                                   self.res.data_ptr() if residual else None, self.info.data_ptr(),
-                                  self.Q.data_ptr() if return_q else None, self.l)
+                                  self.Q.data_ptr() if return_q else None, self.l, self.sweeps.data_ptr())
         self.stream = stream
 
     def set_seed(self, seed):
@@ -289,15 +296,15 @@ class Solver:
 
 def solve(A, k, p=10, q=0, seed=0, residual=False, return_full_l=False, force_householder=False, return_q=False,
           stream=None, residual_iters=0, extra_power_pass=-1, noalloc=False, orth=ORTH_AUTO, algorithm=4,
-          jacobi_max_sweeps=0):
+          jacobi_max_sweeps=0, test_matrix=TEST_GAUSSIAN):
     """Randomized SVD (Algorithm 4, or Algorithm 3 with algorithm=3) of a
     CUDA tensor A.  Returns a dict with U (m x r), S (r, float64), Vt
     (r x n), info (int), l, and optionally residual_t ([spectral estimate,
     Frobenius norm] of A - QQ^T A, float64 tensor) and Q (m x l).
     noalloc: use rsvd_solve_noalloc."""
     s = Solver(A, k, p, q, seed, residual, return_full_l, force_householder, return_q, stream, residual_iters,
-               extra_power_pass, noalloc, orth, algorithm, jacobi_max_sweeps)()
-    out = dict(U=s.U, S=s.S, Vt=s.Vt, l=s.l, info_tensor=s.info)
+               extra_power_pass, noalloc, orth, algorithm, jacobi_max_sweeps, test_matrix)()
+    out = dict(U=s.U, S=s.S, Vt=s.Vt, l=s.l, info_tensor=s.info, jacobi_sweeps_tensor=s.sweeps)
     if residual:
         out["residual_t"] = s.res
     if return_q:
@@ -317,7 +324,7 @@ class Request:
         self.U = torch.empty((m, r), dtype=A.dtype, device=dev)
         self.S = torch.empty((r,), dtype=torch.float64, device=dev)
         self.Vt = torch.empty((r, n), dtype=A.dtype, device=dev)
-        self.info = torch.zeros((1,), dtype=torch.int32, device=dev)
+        self.info = torch.empty((1,), dtype=torch.int32, device=dev)    # assigned by the solve
         self._M = _as_matrix(A)
         self._params = make_params(k, p, q, seed, 0, return_full_l, extra_power_pass=extra_power_pass)
         self._result = rsvd_result(self.U.data_ptr(), r, self.S.data_ptr(), self.Vt.data_ptr(), n, None,
@@ -386,7 +393,7 @@ class Server:
             pass
 
 
-PROFILE_SKETCH, PROFILE_NN, PROFILE_TN, PROFILE_ALL, PROFILE_PROJ32, PROFILE_STAGE1 = 0, 1, 2, 3, 4, 5
+PROFILE_SKETCH, PROFILE_NN, PROFILE_TN, PROFILE_ALL, PROFILE_PROJ32, PROFILE_STAGE1, PROFILE_JACOBI = 0, 1, 2, 3, 4, 5, 6
 
 
 def profile_enable(device, enable=True):
@@ -409,6 +416,16 @@ def omega(n, l, seed, dtype=torch.float32, stream_id=0, device="cuda"):
     _check(load_library().rsvd_omega(_DTYPES[dtype], seed, stream_id, n, l, ctypes.c_void_p(out.data_ptr()), l,
                                      _stream_ptr(None, out.device)))
     return out
+
+
+def srft_omega(n, l, seed, dtype=torch.float32, device="cuda"):
+    """The SRFT test matrix (FastRandRF), materialised: (Omega n x l, the l
+    sampled DCT columns as an int32 tensor)."""
+    out = torch.empty((n, l), dtype=dtype, device=device)
+    cols = torch.empty((l,), dtype=torch.int32, device=device)
+    _check(load_library().rsvd_srft_omega(_DTYPES[dtype], seed, n, l, ctypes.c_void_p(out.data_ptr()), l,
+                                          ctypes.c_void_p(cols.data_ptr()), _stream_ptr(None, out.device)))
+    return out, cols
 
 
 def philox_words(seed, ctr, stream_id=0):

@@ -6,7 +6,8 @@ Tolerances:
   well-separated singular values within 1e-9, residual within 1e-9 relative.
 * FP32 solve: top-k singular values within 1e-5 sigma_1 (normwise; FP32
   rounding perturbs every singular value by about u ||A||) and within 1e-5
-  relative where sigma_k stays well above u ||A||, the Frobenius residual
+  relative where sigma_i >= 1e-2 sigma_1 (below it the rounding floor u ||A||
+  approaches 1e-5 sigma_i), the Frobenius residual
   within 1% of the oracle's (plus the FP32 floor 16 u ||A||_F, which matters
   only when the exact residual vanishes), and every singular vector whose
   gap to its neighbours exceeds 1e-4 sigma_1 within 8 u sigma_1 / gap_i
@@ -101,8 +102,11 @@ def test_fp32_solve_matches_oracle(R, m, n, k, p, q, seed):
     ref = rsvd_alg4(Ad, k, p, q, seed=seed)
     S = _np(out["S"])
     assert np.max(np.abs(S - ref["S"])) <= 1e-5 * ref["S"][0]
-    # top-k relative error too (these spectra stay above the FP32 floor here)
-    assert np.max(np.abs(S - ref["S"]) / ref["S"]) <= 1e-5
+    # top-k relative error too, where sigma_i >= 1e-2 sigma_1: below that the
+    # FP32 rounding of the products (about u ||A||, u = 2^-24) is itself near
+    # 1e-5 sigma_i and only the normwise bound above holds
+    big = ref["S"] >= 1e-2 * ref["S"][0]
+    assert np.max(np.abs(S - ref["S"])[big] / ref["S"][big]) <= 1e-5
     _, fro = residual_norms(Ad, ref["Q"])
     # 1% of the oracle's residual, above the FP32 rounding floor u ||A||_F
     # (when l = min(m, n) the exact residual is zero).
