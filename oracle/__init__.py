@@ -13,12 +13,16 @@ Modules
            one-sided Jacobi SVD (the "standard algorithm" of Stage 2).
   rsvd     Algorithm 4 end to end (Algorithm 2 is q = 0), the residual
            norms of the error measure, Algorithm 3 for comparison.
-  bounds   the expected-error bounds of Theorems 2, 3, 6 and eq. (3.5), and
-           the Eckart-Young floor of eq. (3.1).
+  bounds   the expected-error bounds of Theorems 2, 3, 6 and eq. (3.5), the
+           canonical-angle bounds of Theorem 5, and the Eckart-Young floor
+           of eq. (3.1).
+  angles   canonical angles between subspaces (Section 4.3).
+  adaptive the adaptive randomized range finder (Appendix A, blocked).
+  srft     the SRFT test matrix and FastRandRF (Appendix A).
 
 Everything is real (the paper's conjugate transpose becomes a transpose) and
 computed in float64.
 """
 
-from . import philox, linalg, rsvd, bounds, quant  # noqa: F401
+from . import philox, linalg, rsvd, bounds, quant, angles, adaptive, srft  # noqa: F401
 from .rsvd import rsvd_alg4, rsvd_alg3, residual_norms  # noqa: F401

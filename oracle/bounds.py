@@ -51,3 +51,29 @@ def eq35(sigma_k1, k, p, q, m, n):
     + e sqrt(k+p)/p sqrt(min(m,n) - k)]^(1/(2q+1)) sigma_{k+1}."""
     c = (1.0 + math.sqrt(k / (p - 1))) + math.e * math.sqrt(k + p) / p * math.sqrt(min(m, n) - k)
     return c ** (1.0 / (2 * q + 1)) * sigma_k1
+
+
+def thm5(sigma, k, q, Omega, V):
+    """Theorem 5 (under Assumption 4): bounds on the sines of the canonical
+    angles theta_j between range(U_k) and the left space of the power-scheme
+    sketch, and v_j between range(V_k) and the right space, j = 1..k:
+
+      sin theta_j <= g_j^(2q+1) c / sqrt(1 + g_j^(4q+2) c^2),
+      sin v_j     <= g_j^(2q+2) c / sqrt(1 + g_j^(4q+4) c^2),
+
+    with g_j = sigma_{k+1} / sigma_j (gamma_j, the reading of gamma for index
+    j) and c = ||Omega_2 Omega_1^+||_2, where V^T Omega = [Omega_1; Omega_2]
+    splits the test matrix along the first k right singular vectors (V: all
+    right singular vectors of A, n x min(m, n) or n x n).  Returns (bounds
+    for theta, bounds for v), each of length k."""
+    sigma = np.asarray(sigma, dtype=np.float64)
+    V = np.asarray(V, dtype=np.float64)
+    Om = np.asarray(Omega, dtype=np.float64)
+    O1 = V[:, :k].T @ Om
+    O2 = V[:, k:].T @ Om
+    c = float(np.linalg.norm(O2 @ np.linalg.pinv(O1), 2))
+    g = np.array([_s(sigma, k + 1) / _s(sigma, j) for j in range(1, k + 1)])
+    e1, e2 = 2 * q + 1, 2 * q + 2
+    bt = g ** e1 * c / np.sqrt(1.0 + g ** (2 * e1) * c * c)
+    bv = g ** e2 * c / np.sqrt(1.0 + g ** (2 * e2) * c * c)
+    return bt, bv
