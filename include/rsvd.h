@@ -277,6 +277,41 @@ rsvd_status rsvd_server_graph_stats(rsvd_server* s, int64_t* launches, int64_t* 
 /* Drains, then releases the arena, streams, graphs and thread. */
 rsvd_status rsvd_server_destroy(rsvd_server* s);
 
+/* ---- Subspace diagnostics and the adaptive range finder ---- */
+
+/* Sines of the canonical angles theta_1 <= ... <= theta_k between range(U1)
+ * (rows x k, ld1) and range(U2) (rows x l, ld2), both with orthonormal
+ * columns, k <= l <= rows, round16(k) + round16(l) <= 288 (the measure of
+ * Section 4.3, eq. (4.3), and of Theorem 5): the singular values of
+ * E = (I - U2 U2^T) U1, ascending, written to `sines` (device, k doubles).
+ * E is formed from the FP64 Gram of [U2 | U1] (projected twice) and its
+ * singular values come from its FP64 Gram, so sines far below
+ * sqrt(2^-53) ||E|| (FP64) or the FP32 rounding of U1, U2 (FP32) are not
+ * resolved.  dtype F32 or F64; asynchronous on `stream`. */
+rsvd_status rsvd_canonical_sines_workspace_size(int32_t dtype, int64_t rows, int64_t k, int64_t l, size_t* bytes);
+rsvd_status rsvd_canonical_sines(rsvd_handle* h, int32_t dtype, int64_t rows, int64_t k, const void* U1, int64_t ld1,
+                                 int64_t l, const void* U2, int64_t ld2, double* sines, void* workspace,
+                                 size_t workspace_bytes, void* stream);
+
+/* Adaptive randomized range finder (Appendix A, Adaptive_randRF), blocked:
+ * blocks of `block` (1..32) Gaussian test vectors (columns t*block.. of the
+ * test matrix on Philox stream 3, key seed) are drawn until the estimate
+ * est = 10 sqrt(2/pi) max_i ||(I - Q Q^T) A w_i|| of the last block is <= tol
+ * (then ||(I - Q Q^T) A||_2 <= tol except with probability at most
+ * min(m, n) 10^-block).  Each block is projected against Q twice; its left
+ * singular vectors with singular value above tol / (10 sqrt(2/pi)) are
+ * projected once more, orthonormalised (CholeskyQR2, Householder fallback)
+ * and appended.  At most max_l columns (max_l <= min(m, n), round16(max_l) +
+ * round16(block) <= 288).  Q (device, m x max_l, ldq >= max_l) receives the
+ * l_out columns; est_out the last estimate; converged_out 1 if the
+ * tolerance was met, 0 if max_l stopped it.  F32 / F64 A.  Unlike the other
+ * calls this one synchronises `stream` once per block (the block count
+ * depends on the data) and returns when Q is complete. */
+rsvd_status rsvd_adaptive_range_workspace_size(const rsvd_matrix* A, int32_t block, int64_t max_l, size_t* bytes);
+rsvd_status rsvd_adaptive_range(rsvd_handle* h, const rsvd_matrix* A, double tol, int32_t block, int64_t max_l,
+                                uint64_t seed, void* Q, int64_t ldq, int64_t* l_out, double* est_out,
+                                int32_t* converged_out, void* workspace, size_t workspace_bytes, void* stream);
+
 /* ---- Single steps of the path, for testing each kernel on its own. ---- */
 
 /* The test matrix of Algorithm 4 step 1, materialised (the solve never does

@@ -173,7 +173,7 @@ __global__ __launch_bounds__(256) void skinny_gemm_kernel(GemmArgs g) {
                     if (g.omega_kind == kOmegaSrft)
                         srft_block<T>(g.seed, (uint32_t)(r >> 2), g.srft_cols[j], g.K, srft_sc0, srft_sc1, ro[it]);
                     else
-                        omega_block<T>(g.seed, 0u, (uint32_t)(r >> 2), (uint32_t)j, ro[it]);
+                        omega_block<T>(g.seed, g.omega_stream, (uint32_t)(r >> 2), (uint32_t)(g.omega_col0 + j), ro[it]);
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
                         if (r + e >= kend) ro[it][e] = T(0);

@@ -36,6 +36,8 @@ struct GemmArgs {
     int splits;
     int omega_kind;            // X == NULL: kOmegaGaussian (default) or kOmegaSrft
     const int* srft_cols;      // kOmegaSrft: the ncols sampled DCT columns (device)
+    uint32_t omega_stream;     // kOmegaGaussian: Philox stream id (0 = the solve's test matrix)
+    int64_t omega_col0;        // kOmegaGaussian: column j of the product uses test-matrix column col0 + j
 };
 constexpr int kOmegaGaussian = 0, kOmegaSrft = 1;
 size_t gemm_partials_elems(int dtype, int64_t M, int64_t K, int ncols, int* splits_out);
@@ -179,6 +181,16 @@ size_t residual_partials(int64_t m, int64_t n);
 // Spectral-norm estimator of A - Q Q^T A: M = [-Q^T W; I_b] ((L + 16) x 16,
 // FP64) from the Gram partials of [Q | W] (rows x (L + 16)).
 hipError_t launch_proj_coef(const double* partials, int64_t rows, int L, int b, double* M, hipStream_t s);
+// Wide form of launch_proj_coef: M = [-Q^T W; I_b] ((L + B) x B, ld B) from
+// the Gram partials of [Q | W] (rows x (L + B)); columns >= b zero.
+hipError_t launch_proj_coef_w(const double* partials, int64_t rows, int L, int B, int b, double* M, hipStream_t s);
+// sines[j] = min(1, sigma[k-1-j]) (ascending).
+hipError_t launch_sines(const double* sigma, int k, double* sines, hipStream_t s);
+// Adaptive range finder block statistics: out[0] = factor * largest column
+// norm of the block (from the diagonal of its Gram partials, B wide),
+// out[1] = number of the b sorted sigma above thr.
+hipError_t launch_adaptive_stats(const double* partials, int64_t rows, int B, int b, const double* sigma,
+                                 double factor, double thr, double* out, hipStream_t s);
 // out[0] = sigma[0]; out[1] = 0 unless the Frobenius norm was requested.
 hipError_t launch_residual_spec_final(const double* sigma, double* out, int fro_requested, hipStream_t s);
 

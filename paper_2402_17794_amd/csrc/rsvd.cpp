@@ -814,3 +814,225 @@ rsvd_status rsvd_orth(rsvd_handle* h, int32_t dtype, int64_t rows, int64_t l, co
 }
 
 }  // extern "C"
+
+// ---- canonical angles (Section 4.3, Theorem 5) and the adaptive range finder ----
+namespace {
+
+// Workspace of rsvd_canonical_sines: the panel [U2 | U1] (rows x (L2 + K1)),
+// Gram partials of it, the projection coefficients, and the small-SVD
+// buffers of the K1-column residual.
+struct SinesLayout {
+    int K1 = 0, L2 = 0, LW = 0;
+    size_t flags = 0, panel = 0, GP = 0, M = 0, R = 0, Rinv = 0, Ut = 0, Mv = 0, sigma = 0, shift = 0, work = 0,
+           total = 0;
+};
+
+SinesLayout sines_layout(int dtype, int64_t rows, int64_t k, int64_t l) {
+    SinesLayout W;
+    W.K1 = (int)round_up(k, 16);
+    W.L2 = (int)round_up(l, 16);
+    W.LW = W.L2 + W.K1;
+    Carver c;
+    W.flags = c.take(sizeof(DevFlags));
+    W.panel = c.take(esize(dtype) * (size_t)rows * W.LW);
+    W.GP = c.take(sizeof(double) * gram_partials_elems(rows, W.LW));
+    W.M = c.take(sizeof(double) * (size_t)W.LW * W.K1);
+    W.R = c.take(sizeof(double) * (size_t)W.K1 * W.K1);
+    W.Rinv = c.take(sizeof(double) * (size_t)W.K1 * W.K1);
+    W.Ut = c.take(sizeof(double) * (size_t)W.K1 * W.K1);
+    W.Mv = c.take(sizeof(double) * (size_t)W.K1 * W.K1);
+    W.sigma = c.take(sizeof(double) * (size_t)W.K1);
+    W.shift = c.take(sizeof(double));
+    W.work = c.take(sizeof(double) * kJacobiWorkDoubles);
+    W.total = c.off;
+    return W;
+}
+
+// The projection of the block at column `off` of the panel (K1 wide)
+// against the panel's first Lq columns, in place: Y <- Y - Q (Q^T Y) with
+// the coefficients from the FP64 Gram of [Q | Y].
+rsvd_status project_block(int dtype, void* panel, int64_t ldp, int64_t rows, int Lq, int B, int b, double* GP,
+                          double* M, hipStream_t s) {
+    if (Lq == 0) return RSVD_OK;
+    RSVD_TRY(launch_gram(dtype, panel, ldp, rows, Lq + B, GP, nullptr, s));
+    RSVD_TRY(launch_proj_coef_w(GP, rows, Lq, B, b, M, s));
+    void* out = static_cast<char*>(panel) + esize(dtype) * (size_t)Lq;
+    RSVD_TRY(launch_apply(dtype, panel, ldp, rows, Lq + B, M, B, B, out, ldp, 0, nullptr, nullptr, nullptr, nullptr, 0,
+                          s));
+    return RSVD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rsvd_status rsvd_canonical_sines_workspace_size(int32_t dtype, int64_t rows, int64_t k, int64_t l, size_t* bytes) {
+    if (!bytes || (dtype != RSVD_F32 && dtype != RSVD_F64) || k < 1 || l < k || rows < l) return RSVD_ERR_INVALID_ARG;
+    if (round_up(k, 16) + round_up(l, 16) > kMaxL) return RSVD_ERR_UNSUPPORTED;
+    *bytes = sines_layout(dtype, rows, k, l).total;
+    return RSVD_OK;
+}
+
+rsvd_status rsvd_canonical_sines(rsvd_handle* h, int32_t dtype, int64_t rows, int64_t k, const void* U1, int64_t ld1,
+                                 int64_t l, const void* U2, int64_t ld2, double* sines, void* ws, size_t ws_bytes,
+                                 void* stream) {
+    if (!h || !U1 || !U2 || !sines || ld1 < k || ld2 < l) return RSVD_ERR_INVALID_ARG;
+    size_t need = 0;
+    rsvd_status st = rsvd_canonical_sines_workspace_size(dtype, rows, k, l, &need);
+    if (st != RSVD_OK) return st;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return RSVD_ERR_INVALID_ARG;
+    if (ws_bytes < need) return RSVD_ERR_WORKSPACE_TOO_SMALL;
+    if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_DEVICE;
+    const SinesLayout W = sines_layout(dtype, rows, k, l);
+    hipStream_t s = as_stream(stream);
+    DevFlags* flags = at<DevFlags>(ws, W.flags);
+    char* panel = at<char>(ws, W.panel);
+    double* GP = at<double>(ws, W.GP);
+    double* M = at<double>(ws, W.M);
+    RSVD_TRY(launch_init(nullptr, 0, flags, s));
+    RSVD_TRY(launch_copy2d(dtype, U2, ld2, rows, (int)l, panel, W.LW, W.L2, s));
+    RSVD_TRY(launch_copy2d(dtype, U1, ld1, rows, (int)k, panel + esize(dtype) * W.L2, W.LW, W.K1, s));
+    // E = (I - U2 U2^T) U1, projected twice, in place of U1 in the panel.
+    for (int pass = 0; pass < 2; ++pass)
+        if ((st = project_block(dtype, panel, W.LW, rows, W.L2, W.K1, (int)k, GP, M, s)) != RSVD_OK) return st;
+    // Singular values of E: FP64 Gram, Cholesky (shifted when E is singular), Jacobi.
+    const void* E = panel + esize(dtype) * W.L2;
+    RSVD_TRY(launch_gram(dtype, E, W.LW, rows, W.K1, GP, nullptr, s));
+    RSVD_TRY(launch_chol(GP, rows, (int)k, W.K1, at<double>(ws, W.R), at<double>(ws, W.Rinv), flags, 2,
+                         at<double>(ws, W.shift), at<double>(ws, W.work), 0.0, s));
+    RSVD_TRY(launch_jacobi(at<double>(ws, W.R), (int)k, W.K1, at<double>(ws, W.shift), at<double>(ws, W.sigma),
+                           at<double>(ws, W.Ut), at<double>(ws, W.Mv), flags, at<double>(ws, W.work), s));
+    RSVD_TRY(launch_sines(at<double>(ws, W.sigma), (int)k, sines, s));
+    return RSVD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+constexpr uint32_t kAdaptiveStream = 3;
+constexpr double kEstFactor = 7.978845608028654;    // 10 sqrt(2 / pi)
+
+// Workspace of rsvd_adaptive_range: the orth plan of one block (B columns),
+// the panel [Q | block] (rows x PW, PW = round16(max_l) + B), the wide Gram
+// partials and projection coefficients, a block buffer and the statistics.
+struct AdaptLayout {
+    int B = 0, PW = 0;
+    Plan orth;
+    int splits = 1;
+    size_t orth_bytes = 0, part = 0, panel = 0, GP = 0, M = 0, T = 0, T2 = 0, stats = 0, total = 0;
+};
+
+AdaptLayout adapt_layout(int dtype, int64_t rows, int64_t cols, int b, int max_l) {
+    AdaptLayout W;
+    W.B = (int)round_up(b, 16);
+    W.PW = (int)round_up(max_l, 16) + W.B;
+    make_plan(dtype, rows, W.B, W.B, 0, 0, 0, W.orth);
+    Carver c;
+    W.orth_bytes = c.take(W.orth.total);
+    W.part = c.take(esize(dtype) * std::max<size_t>(1, gemm_partials_elems(dtype, rows, cols, W.B, &W.splits)));
+    W.panel = c.take(esize(dtype) * (size_t)rows * W.PW);
+    W.GP = c.take(sizeof(double) * gram_partials_elems(rows, W.PW));
+    W.M = c.take(sizeof(double) * (size_t)W.PW * W.B);
+    W.T = c.take(esize(dtype) * (size_t)rows * W.B);
+    W.T2 = c.take(esize(dtype) * (size_t)rows * W.B);
+    W.stats = c.take(sizeof(double) * 2);
+    W.total = c.off;
+    return W;
+}
+
+}  // namespace
+
+extern "C" {
+
+rsvd_status rsvd_adaptive_range_workspace_size(const rsvd_matrix* A, int32_t block, int64_t max_l, size_t* bytes) {
+    rsvd_status st = check_matrix(A);
+    if (st != RSVD_OK) return st;
+    if (!bytes || block < 1 || block > 32 || max_l < 1) return RSVD_ERR_INVALID_ARG;
+    if (A->dtype != RSVD_F32 && A->dtype != RSVD_F64) return RSVD_ERR_UNSUPPORTED;
+    const int64_t cap = std::min<int64_t>(max_l, std::min(A->rows, A->cols));
+    if (round_up(cap, 16) + round_up(block, 16) > kMaxL) return RSVD_ERR_UNSUPPORTED;
+    *bytes = adapt_layout(A->dtype, A->rows, A->cols, block, (int)cap).total;
+    return RSVD_OK;
+}
+
+rsvd_status rsvd_adaptive_range(rsvd_handle* h, const rsvd_matrix* A, double tol, int32_t block, int64_t max_l,
+                                uint64_t seed, void* Q, int64_t ldq, int64_t* l_out, double* est_out,
+                                int32_t* converged_out, void* ws, size_t ws_bytes, void* stream) {
+    if (!h || !Q || !l_out || !est_out || !converged_out || !(tol >= 0.0)) return RSVD_ERR_INVALID_ARG;
+    size_t need = 0;
+    rsvd_status st = rsvd_adaptive_range_workspace_size(A, block, max_l, &need);
+    if (st != RSVD_OK) return st;
+    const int64_t m = A->rows, n = A->cols;
+    const int cap = (int)std::min<int64_t>(max_l, std::min(m, n));
+    if (ldq < cap) return RSVD_ERR_INVALID_ARG;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return RSVD_ERR_INVALID_ARG;
+    if (ws_bytes < need) return RSVD_ERR_WORKSPACE_TOO_SMALL;
+    if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_DEVICE;
+    const int dt = A->dtype;
+    const size_t es = esize(dt);
+    const AdaptLayout W = adapt_layout(dt, m, n, block, cap);
+    const Plan& OP = W.orth;
+    void* ows = at<char>(ws, W.orth_bytes);           // the orth plan's own region
+    char* panel = at<char>(ws, W.panel);
+    double* GP = at<double>(ws, W.GP);
+    double* M = at<double>(ws, W.M);
+    char* T = at<char>(ws, W.T);
+    char* T2 = at<char>(ws, W.T2);
+    double* dstats = at<double>(ws, W.stats);
+    DevFlags* flags = at<DevFlags>(ows, OP.flags);
+    hipStream_t s = as_stream(stream);
+    const int B = W.B, b = block;
+    const double thr = tol / kEstFactor;
+    RSVD_TRY(launch_init(at<int>(ows, OP.counters), OP.ncounters, flags, s));
+    int lc = 0;                                         // columns of Q so far
+    double est = 0.0;
+    int converged = 0;
+    for (int64_t t = 0;; ++t) {
+        const int Lq = (int)round_up(lc, 16);
+        char* Yb = panel + es * (size_t)Lq;
+        // Y = A Omega_t (columns t b .. t b + b - 1 of the stream-3 test matrix), B wide, zero padded.
+        GemmArgs g{};
+        g.A = A->data; g.lda = A->ld; g.trans = 0; g.M = m; g.K = n; g.X = nullptr; g.ldx = 0; g.seed = seed;
+        g.ncols = b; g.wcols = B; g.Y = Yb; g.ldy = W.PW; g.partials = at<char>(ws, W.part);
+        g.splits = W.splits;
+        g.omega_stream = kAdaptiveStream;
+        g.omega_col0 = t * b;
+        RSVD_TRY(launch_gemm(dt, g, s));
+        for (int pass = 0; pass < 2; ++pass)
+            if ((st = project_block(dt, panel, W.PW, m, Lq, B, b, GP, M, s)) != RSVD_OK) return st;
+        // Column norms and the singular values of the projected block.
+        RSVD_TRY(launch_gram(dt, Yb, W.PW, m, B, GP, nullptr, s));
+        RSVD_TRY(launch_chol(GP, m, b, B, at<double>(ows, OP.R), at<double>(ows, OP.Rinv), flags, 2,
+                             at<double>(ows, OP.shift), at<double>(ows, OP.work), 0.0, s));
+        RSVD_TRY(launch_jacobi(at<double>(ows, OP.R), b, B, at<double>(ows, OP.shift), at<double>(ows, OP.sigma),
+                               at<double>(ows, OP.Ut), at<double>(ows, OP.Mv), flags, at<double>(ows, OP.work), s));
+        RSVD_TRY(launch_adaptive_stats(GP, m, B, b, at<double>(ows, OP.sigma), kEstFactor, thr, dstats, s));
+        double hst[2] = {0.0, 0.0};
+        RSVD_TRY(hipMemcpyAsync(hst, dstats, sizeof(hst), hipMemcpyDeviceToHost, s));
+        RSVD_TRY(hipStreamSynchronize(s));
+        est = hst[0];
+        const int keep = (int)hst[1];
+        if (est <= tol) { converged = 1; break; }
+        if (keep < 1 || lc + keep > cap) break;
+        // W = Y Z_keep S_keep^-1 (the kept left singular vectors), projected against Q once more, orthonormalised.
+        const int Kp = (int)round_up(keep, 16);
+        RSVD_TRY(launch_apply(dt, Yb, W.PW, m, B, at<double>(ows, OP.Mv), B, keep, T, B, 0, nullptr, nullptr, nullptr,
+                              nullptr, 0, s));
+        RSVD_TRY(launch_copy2d(dt, T, B, m, keep, Yb, W.PW, Kp, s));
+        if ((st = project_block(dt, panel, W.PW, m, Lq, Kp, keep, GP, M, s)) != RSVD_OK) return st;
+        RSVD_TRY(launch_copy2d(dt, Yb, W.PW, m, keep, T, Kp, Kp, s));
+        if ((st = run_orth_cols(OP, ows, flags, dt, m, keep, Kp, T, T2, RSVD_ORTH_AUTO, s)) != RSVD_OK) return st;
+        // Append: the new columns go right after the last one of Q, zero padding after them.
+        RSVD_TRY(launch_copy2d(dt, T2, Kp, m, keep, panel + es * (size_t)lc, W.PW,
+                               (int)round_up(lc + keep, 16) - lc, s));
+        lc += keep;
+    }
+    if (lc > 0) RSVD_TRY(launch_copy2d(dt, panel, W.PW, m, lc, Q, ldq, lc, s));
+    RSVD_TRY(hipStreamSynchronize(s));
+    *l_out = lc;
+    *est_out = est;
+    *converged_out = converged;
+    return RSVD_OK;
+}
+}  // extern "C"

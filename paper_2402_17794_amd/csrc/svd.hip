@@ -833,6 +833,85 @@ hipError_t launch_proj_coef(const double* partials, int64_t rows, int L, int b, 
     return hipGetLastError();
 }
 
+// Wide form: M = [-Q^T W; I_b] ((L + B) x B, ld B) from the Gram partials of
+// [Q | W] (rows x (L + B), L and B multiples of 16); columns c >= b of M are
+// zero.
+__global__ __launch_bounds__(256) void proj_coef_w_kernel(const double* __restrict__ part, int nchunks, int L, int B,
+                                                          int b, double* __restrict__ M) {
+    const int nt = (L + B) / 16, npairs = nt * (nt + 1) / 2;
+    for (int idx = blockIdx.x * 256 + threadIdx.x; idx < (L + B) * B; idx += 256 * gridDim.x) {
+        const int a = idx / B, c = idx % B;
+        double v = 0.0;
+        if (c < b) {
+            if (a < L) {
+                const int ta = a >> 4, tb = (L + c) >> 4;
+                const int pr = ta * nt - ta * (ta - 1) / 2 + (tb - ta);   // row-major upper-triangle index
+                const int e = (a & 15) * 16 + ((L + c) & 15);
+                double sum = 0.0;
+                for (int ch = 0; ch < nchunks; ++ch) sum += part[((size_t)ch * npairs + pr) * 256 + e];
+                v = -sum;
+            } else {
+                v = (a - L == c) ? 1.0 : 0.0;
+            }
+        }
+        M[idx] = v;
+    }
+}
+
+hipError_t launch_proj_coef_w(const double* partials, int64_t rows, int L, int B, int b, double* M, hipStream_t s) {
+    if (L % 16 || B % 16 || L + B > kMaxL || b > B) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(proj_coef_w_kernel, dim3((unsigned)ceil_div((L + B) * B, 256)), dim3(256), 0, s, partials,
+                       gram_chunks(rows), L, B, b, M);
+    return hipGetLastError();
+}
+
+// sines[j] = min(1, sigma[k - 1 - j]): the singular values of the projection
+// residual, ascending.
+__global__ void sines_kernel(const double* sigma, int k, double* sines) {
+    for (int j = threadIdx.x; j < k; j += blockDim.x) sines[j] = fmin(1.0, sigma[k - 1 - j]);
+}
+
+hipError_t launch_sines(const double* sigma, int k, double* sines, hipStream_t s) {
+    hipLaunchKernelGGL(sines_kernel, dim3(1), dim3(256), 0, s, sigma, k, sines);
+    return hipGetLastError();
+}
+
+// Adaptive range finder, per block: est = factor * max_i ||y_i|| (column
+// norms from the diagonal of the Gram partials of the block, B wide) and
+// keep = #{sigma_i > thr} over the block's b sorted singular values.
+// out[0] = est, out[1] = keep.
+__global__ __launch_bounds__(64) void adaptive_stats_kernel(const double* __restrict__ part, int nchunks, int B, int b,
+                                                            const double* __restrict__ sigma, double factor, double thr,
+                                                            double* out) {
+    const int nt = B / 16, npairs = nt * (nt + 1) / 2;
+    double mx = 0.0;
+    int keep = 0;
+    for (int c = threadIdx.x; c < b; c += 64) {
+        const int t = c >> 4;
+        const int pr = t * nt - t * (t - 1) / 2;                   // diagonal tile (t, t)
+        const int e = (c & 15) * 16 + (c & 15);
+        double sq = 0.0;
+        for (int ch = 0; ch < nchunks; ++ch) sq += part[((size_t)ch * npairs + pr) * 256 + e];
+        mx = fmax(mx, sqrt(fmax(sq, 0.0)));
+        keep += sigma[c] > thr ? 1 : 0;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        mx = fmax(mx, __shfl_xor(mx, o));
+        keep += __shfl_xor(keep, o);
+    }
+    if (threadIdx.x == 0) {
+        out[0] = factor * mx;
+        out[1] = (double)keep;
+    }
+}
+
+hipError_t launch_adaptive_stats(const double* partials, int64_t rows, int B, int b, const double* sigma,
+                                 double factor, double thr, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(adaptive_stats_kernel, dim3(1), dim3(64), 0, s, partials, gram_chunks(rows), B, b, sigma, factor,
+                       thr, out);
+    return hipGetLastError();
+}
+
 // residual[0] = largest Ritz value of the estimator; residual[1] = 0 when the
 // Frobenius norm was not requested.
 __global__ void residual_spec_final_kernel(const double* sigma, double* out, int fro_requested) {

@@ -80,7 +80,8 @@ class rsvd_result(ctypes.Structure):
 
 
 EXPORTS = ["rsvd_create", "rsvd_destroy", "rsvd_l_used", "rsvd_workspace_size", "rsvd_solve", "rsvd_solve_noalloc",
-           "rsvd_srft_omega",
+           "rsvd_srft_omega", "rsvd_canonical_sines_workspace_size", "rsvd_canonical_sines",
+           "rsvd_adaptive_range_workspace_size", "rsvd_adaptive_range",
            "rsvd_status_string", "rsvd_profile_enable", "rsvd_profile_read", "rsvd_quantize", "rsvd_omega",
            "rsvd_philox_words", "rsvd_gemm_workspace_size", "rsvd_gemm", "rsvd_orth_workspace_size", "rsvd_orth",
            "rsvd_server_create", "rsvd_server_submit", "rsvd_server_poll", "rsvd_server_wait", "rsvd_server_drain",
@@ -126,6 +127,12 @@ def load_library(path=LIB_PATH):
         "rsvd_omega": ([I32, U64, ctypes.c_uint32, I64, I64, P, I64, P], I32),
         "rsvd_philox_words": ([U64, ctypes.c_uint32, P, I64, P, P], I32),
         "rsvd_srft_omega": ([I32, U64, I64, I64, P, I64, P, P], I32),
+        "rsvd_canonical_sines_workspace_size": ([I32, I64, I64, I64, ctypes.POINTER(SZ)], I32),
+        "rsvd_canonical_sines": ([P, I32, I64, I64, P, I64, I64, P, I64, P, P, SZ, P], I32),
+        "rsvd_adaptive_range_workspace_size": ([ctypes.POINTER(rsvd_matrix), I32, I64, ctypes.POINTER(SZ)], I32),
+        "rsvd_adaptive_range": ([P, ctypes.POINTER(rsvd_matrix), ctypes.c_double, I32, I64, U64, P, I64,
+                                 ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I32), P, SZ, P],
+                                I32),
         "rsvd_gemm_workspace_size": ([ctypes.POINTER(rsvd_matrix), I32, I64, ctypes.POINTER(SZ)], I32),
         "rsvd_gemm": ([P, ctypes.POINTER(rsvd_matrix), I32, P, I64, U64, I64, P, I64, P, SZ, P], I32),
         "rsvd_orth_workspace_size": ([I32, I64, I64, ctypes.POINTER(SZ)], I32),
@@ -426,6 +433,48 @@ def srft_omega(n, l, seed, dtype=torch.float32, device="cuda"):
     _check(load_library().rsvd_srft_omega(_DTYPES[dtype], seed, n, l, ctypes.c_void_p(out.data_ptr()), l,
                                           ctypes.c_void_p(cols.data_ptr()), _stream_ptr(None, out.device)))
     return out, cols
+
+
+def canonical_sines(U1, U2):
+    """Sines of the canonical angles between range(U1) and range(U2) (both
+    with orthonormal columns, U1 no wider than U2), ascending, float64."""
+    lib = load_library()
+    if U1.dtype != U2.dtype or U1.dtype not in _DTYPES or U1.stride(1) != 1 or U2.stride(1) != 1:
+        raise ValueError("U1, U2: row-major CUDA tensors of one float dtype")
+    rows, k = U1.shape
+    l = U2.shape[1]
+    nb = ctypes.c_size_t()
+    _check(lib.rsvd_canonical_sines_workspace_size(_DTYPES[U1.dtype], rows, k, l, ctypes.byref(nb)))
+    ws = _workspace(nb.value, U1.device)
+    out = torch.empty((k,), dtype=torch.float64, device=U1.device)
+    _check(lib.rsvd_canonical_sines(_handle(U1.device), _DTYPES[U1.dtype], rows, k, ctypes.c_void_p(U1.data_ptr()),
+                                    U1.stride(0), l, ctypes.c_void_p(U2.data_ptr()), U2.stride(0),
+                                    ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                    _stream_ptr(None, U1.device)))
+    return out
+
+
+def adaptive_range(A, tol, block=16, max_l=None, seed=0):
+    """Adaptive randomized range finder: (Q m x l, estimate, converged).
+    max_l defaults to the largest basis the library handles for this block
+    (288 - round16(block)), or min(m, n) if smaller."""
+    lib = load_library()
+    M = _as_matrix(A)
+    m, n = A.shape
+    if max_l is None:
+        max_l = min(m, n, 288 - (int(block) + 15) // 16 * 16)
+    max_l = int(max_l)
+    nb = ctypes.c_size_t()
+    _check(lib.rsvd_adaptive_range_workspace_size(ctypes.byref(M), int(block), max_l, ctypes.byref(nb)))
+    ws = _workspace(nb.value, A.device)
+    cap = min(max_l, m, n)
+    Q = torch.empty((m, cap), dtype=A.dtype, device=A.device)
+    l, est, conv = ctypes.c_int64(), ctypes.c_double(), ctypes.c_int32()
+    _check(lib.rsvd_adaptive_range(_handle(A.device), ctypes.byref(M), float(tol), int(block), max_l, seed,
+                                   ctypes.c_void_p(Q.data_ptr()), cap, ctypes.byref(l), ctypes.byref(est),
+                                   ctypes.byref(conv), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                   _stream_ptr(None, A.device)))
+    return Q[:, :l.value], est.value, bool(conv.value)
 
 
 def philox_words(seed, ctr, stream_id=0):
