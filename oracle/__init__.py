@@ -19,10 +19,12 @@ Modules
   angles   canonical angles between subspaces (Section 4.3).
   adaptive the adaptive randomized range finder (Appendix A, blocked).
   srft     the SRFT test matrix and FastRandRF (Appendix A).
+  single_pass  the single-pass Algorithms 5 (Hermitian) and 6 (general) of
+           Section 3.4.
 
 Everything is real (the paper's conjugate transpose becomes a transpose) and
 computed in float64.
 """
 
-from . import philox, linalg, rsvd, bounds, quant, angles, adaptive, srft  # noqa: F401
+from . import philox, linalg, rsvd, bounds, quant, angles, adaptive, srft, single_pass  # noqa: F401
 from .rsvd import rsvd_alg4, rsvd_alg3, residual_norms  # noqa: F401

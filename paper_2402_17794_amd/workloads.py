@@ -24,6 +24,9 @@ Families
                   separable Gaussian bumps, min-max normalised to [0, 1], plus
                   i.i.d. N(0, 0.05^2) noise.
   exact_rank      A = U diag(sigma_1..r) V^T of exact rank r.
+  symmetric_spectrum  symmetric A = U diag(lambda) U^T with Haar U (the
+                  Hermitian inputs of the single-pass Algorithm 5), with
+                  alternating_signs for indefinite spectra.
 """
 
 import numpy as np
@@ -68,6 +71,30 @@ def known_spectrum(m, n, sigma, seed_u=1, seed_v=2, device=None):
     import torch
     s = torch.from_numpy(sigma).to(U.device)
     return (U * s[None, :]) @ V.T
+
+
+def symmetric_spectrum(n, lam, seed=1, device=None):
+    """Symmetric A = U diag(lam) U^T (float64) with Haar U (n x n); lam has n
+    entries (signed: A may be indefinite).  On a torch device, returns a
+    float64 tensor there, symmetrised exactly."""
+    lam = np.asarray(lam, dtype=np.float64)
+    if lam.shape != (n,):
+        raise ValueError("lam must have n entries")
+    U = haar(n, n, seed, device)
+    if device is None:
+        A = (U * lam[None, :]) @ U.T
+        return 0.5 * (A + A.T)
+    import torch
+    s = torch.from_numpy(lam).to(U.device)
+    A = (U * s[None, :]) @ U.T
+    return 0.5 * (A + A.T)
+
+
+def alternating_signs(values):
+    """values with signs + - + - ... (an indefinite spectrum of the same
+    magnitudes)."""
+    v = np.asarray(values, dtype=np.float64)
+    return v * np.where(np.arange(v.size) % 2 == 0, 1.0, -1.0)
 
 
 def spectrum_geometric(d, ratio, floor=0.0):
