@@ -79,6 +79,9 @@ typedef enum {
 #define RSVD_INFO_FALLBACK_TIMEOUT  32  /* a grid barrier of the Householder fallback did not
                                            complete within its wait limit (device oversubscribed);
                                            the basis of that orthonormalisation is not valid */
+#define RSVD_INFO_SINGULAR_SYSTEM   64  /* Algorithm 5: the square system of eq. (3.13) has no
+                                           usable pivot (Q^T Omega singular or not finite); the
+                                           outputs are not valid */
 
 typedef struct rsvd_handle rsvd_handle;
 
@@ -129,7 +132,26 @@ typedef struct {
     int32_t algorithm;             /* 0 or 4: Algorithm 4 (orth after every product of the power scheme);
                                       3: Algorithm 3 (Section 3.2): Y = A Omega, q times Y = A (A^T Y), and
                                       orth only once, after the last product.  In FP32, sigma_1^(2q+1) must
-                                      stay inside the float range. */
+                                      stay inside the float range.
+                                      5: Algorithm 5 (Section 3.4.1), single pass, for a symmetric n x n A:
+                                      Y = A Omega, Q = orth(Y), C (l x l) from C (Q^T Omega) = Q^T Y
+                                      (eq. (3.13), Gauss-Jordan with partial pivoting), the
+                                      eigendecomposition of (C + C^T) / 2; S receives the k eigenvalues of
+                                      largest magnitude (signed, |S| descending; ties: larger value first),
+                                      U their eigenvectors (each column's largest-magnitude entry positive)
+                                      and Vt = U^T, so A ~ U diag(S) Vt.  A is read once; its symmetry is
+                                      not checked.
+                                      6: Algorithm 6 (Section 3.4.2), single pass: Y_c = A Omega_c and
+                                      Y_r = A^T Omega_r (Omega_c: the test matrix above, n x l; Omega_r:
+                                      the same generator on stream 1, m x l) from one read of A; Q_c, Q_r
+                                      the k dominant left singular vectors of Y_c, Y_r; C (k x k) the
+                                      least-squares solution of (Omega_r^T Q_c) C = Y_r^T Q_r and
+                                      C (Q_r^T Omega_c) = Q_c^T Y_c (eqs. (3.15)-(3.16), equal weights);
+                                      U = Q_c U^, V = Q_r V^ from the SVD of C, signs as for Algorithm 4.
+                                      Algorithms 5 and 6 need F32 / F64 A, q = 0, l <= 128, the Gaussian
+                                      test matrix, return_full_l = 0 and residual = 0
+                                      (RSVD_ERR_UNSUPPORTED otherwise); Q, if given, receives orth(Y)
+                                      (Algorithm 5) or orth(Y_c) (Algorithm 6), m x l. */
     int32_t jacobi_max_sweeps;     /* sweep cap of the small SVD's Jacobi iteration, 0 = default
                                       (60; 30 for l > 128); reaching it sets RSVD_INFO_JACOBI_NOT_CONVERGED */
     int32_t test_matrix;           /* RSVD_TEST_GAUSSIAN (0): Omega standard Gaussian (rsvd_omega);
@@ -221,7 +243,12 @@ const char* rsvd_status_string(rsvd_status s);
  * 4: the sketch, the power iterations and every orthonormalisation, from the
  * first kernel after the flag reset to the last orth), one record per solve.
  * Kind 6 is the one-sided Jacobi iteration of the small SVD (Algorithm 4
- * step 7: every kernel of it), one record per solve. */
+ * step 7: every kernel of it), one record per solve.  Kind 7 is the
+ * two-sided sketch kernel of Algorithm 6 (Y_c = A Omega_c and
+ * Y_r = A^T Omega_r from one read of A; the reductions of its partials are
+ * outside the events), and it is also counted by kind 3.  For Algorithms 5
+ * and 6, kind 5 spans the sketch(es) and their orthonormalisations and
+ * kind 6 every small SVD / eigendecomposition of Stage 2. */
 rsvd_status rsvd_profile_enable(rsvd_handle* h, int32_t enable);
 rsvd_status rsvd_profile_read(rsvd_handle* h, int32_t kind, double* total_ms, int64_t* launches);
 
@@ -355,6 +382,18 @@ rsvd_status rsvd_gemm_workspace_size(const rsvd_matrix* A, int32_t trans, int64_
 rsvd_status rsvd_gemm(rsvd_handle* h, const rsvd_matrix* A, int32_t trans, const void* X, int64_t ldx,
                       uint64_t seed, int64_t ncols, void* Y, int64_t ldy,
                       void* workspace, size_t workspace_bytes, void* stream);
+
+/* Two-sided sketch of the single-pass Algorithm 6 (step 2): Y_c = A Omega_c
+ * (m x l, ldyc >= l) and Y_r = A^T Omega_r (n x l, ldyr >= l) from one read
+ * of A (F32 / F64), with the kernel of the solve.  Omega_c is the test
+ * matrix of rsvd_omega(seed, stream 0) (n x l), Omega_r that of stream 1
+ * (m x l).  omega_c (n x l, ldoc >= l) and omega_r (m x l, ldor >= l), when
+ * not NULL, receive the two test matrices as the kernel generated them.
+ * 1 <= l <= 128.  Uses `workspace` (rsvd_dual_sketch_workspace_size). */
+rsvd_status rsvd_dual_sketch_workspace_size(const rsvd_matrix* A, int64_t l, size_t* bytes);
+rsvd_status rsvd_dual_sketch(rsvd_handle* h, const rsvd_matrix* A, uint64_t seed, int64_t l, void* Yc,
+                             int64_t ldyc, void* Yr, int64_t ldyr, void* omega_c, int64_t ldoc, void* omega_r,
+                             int64_t ldor, void* workspace, size_t workspace_bytes, void* stream);
 
 /* orth of Algorithms 1-4: Q (rows x l, ldq) = orthonormal basis of range(Y)
  * (rows x l, ldy), l <= rows, by CholeskyQR2 (FP64 Gram and Cholesky) with a

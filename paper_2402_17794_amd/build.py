@@ -21,7 +21,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "librsvd.so")
 ARCH = os.environ.get("RSVD_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["gemm.hip", "gemm_lp.hip", "orth.hip", "svd.hip", "rsvd.cpp", "server.cpp"]
+SOURCES = ["gemm.hip", "gemm_lp.hip", "orth.hip", "svd.hip", "single_pass.hip", "rsvd.cpp", "server.cpp"]
 
 COMMON_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

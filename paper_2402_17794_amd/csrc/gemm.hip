@@ -409,6 +409,359 @@ hipError_t launch_splitk_reduce_f32(const float* partials, int64_t M, int L, int
     return hipGetLastError();
 }
 
+// ---- two-sided sketch of the single-pass Algorithm 6 (begin) ----
+// Y_c = A Omega_c (M x l) and Y_r = A^T Omega_r (K x l) from one read of A.
+// A workgroup owns BM rows of A and one slice of its K columns, like the
+// products above, and keeps the BM x L block of Omega_r in LDS for the whole
+// slice.  Each K tile of A is staged once in LDS and feeds both products:
+// the A Omega_c MFMAs read it row-wise, the A^T Omega_r MFMAs column-wise.
+// The row-dependent XOR-free rotation of each LDS row (dual_swz) makes both
+// fragment reads conflict-free.  Y_c accumulates in registers over the
+// slice (split-K partials as above); the A^T Omega_r block of a K tile is
+// complete over the workgroup's rows only, so it is written as the row
+// tile's partial and a second kernel sums the row tiles in order.
+template <typename T> struct DualTile;
+template <> struct DualTile<float> { static constexpr int BM = 128, BK = 64, SW = 64; };
+template <> struct DualTile<double> { static constexpr int BM = 64, BK = 32, SW = 32; };
+
+// Column offset of row r inside an LDS row of SW elements (bank rotation).
+// FP32 (64 banks): lanes (li, lk) of a row-wise fragment read rows li,
+// columns lk; of a column-wise read rows lk, columns li; both hit 64
+// distinct banks.  FP64 (32 two-bank slots): the same for each half-wave.
+template <typename T> __device__ __forceinline__ int dual_swz(int r);
+template <> __device__ __forceinline__ int dual_swz<float>(int r) { return 16 * (r & 3) + 4 * ((r >> 2) & 3); }
+template <> __device__ __forceinline__ int dual_swz<double>(int r) { return 16 * (r & 1) + 2 * ((r >> 1) & 7); }
+template <typename T> __device__ __forceinline__ int dual_pos(int r, int c) {
+    constexpr int SW = DualTile<T>::SW;
+    return r * SW + ((c + dual_swz<T>(r)) & (SW - 1));
+}
+
+template <typename T, int L> struct DualStride {
+    static constexpr int SB = (sizeof(T) == 4) ? ((L % 32 == 16) ? L : L + 16) : L + 8;
+};
+
+template <typename T, int LT>
+__global__ __launch_bounds__(256) void dual_sketch_kernel(DualArgs g) {
+    using DT = DualTile<T>;
+    constexpr int BM = DT::BM, BK = DT::BK;
+    constexpr int RT = BM / 64;                      // 16-row tiles per wavefront in A Omega_c
+    constexpr int L = 16 * LT;
+    constexpr int CT = BK / 16;                      // 16-column tiles per K tile
+    constexpr int H = 4 / CT;                        // wavefronts per column tile in A^T Omega_r
+    constexpr int LTH = (LT + H - 1) / H;            // l tiles per wavefront in A^T Omega_r
+    constexpr int VEC = Vec16<T>::n;
+    using V = typename Vec16<T>::type;
+    constexpr int SB = DualStride<T, L>::SB;
+    constexpr int NVA = BM * BK / VEC / 256;
+    constexpr int NOB = (BK / 4 * L + 255) / 256;
+    constexpr int NOR = (BM / 4 * L + 255) / 256;
+
+    __shared__ __attribute__((aligned(16))) T As[BM * DT::SW];
+    __shared__ __attribute__((aligned(16))) T Bs[BK * SB];     // Omega_c rows of the K tile
+    __shared__ __attribute__((aligned(16))) T Os[BM * SB];     // Omega_r rows of the row tile
+
+    const T* __restrict__ A = static_cast<const T*>(g.A);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int splits = g.splits;
+    const int split = blockIdx.x % splits;
+    const int tile = blockIdx.x / splits;
+    const int64_t row0 = (int64_t)tile * BM;
+    const int64_t kchunk = round_up(ceil_div(g.K, splits), BK);
+    const int64_t kbeg = (int64_t)split * kchunk;
+    const int64_t kend = min(g.K, kbeg + kchunk);
+    const bool avec = ((g.lda % VEC) == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+    const bool rows_full = avec && (row0 + BM <= g.M);
+
+    // Omega_r rows [row0, row0 + BM) into LDS (zero past M and past l), and
+    // into the caller's copy from the first slice.
+    T* omr = static_cast<T*>(g.omega_r_out);
+#pragma unroll
+    for (int it = 0; it < NOR; ++it) {
+        const int idx = tid + 256 * it;
+        if (idx < BM / 4 * L) {
+            const int gi = idx / L, j = idx % L;
+            const int64_t r = row0 + 4 * gi;
+            T z[4];
+            if (j < g.ncols && r < g.M) {
+                omega_block<T>(g.seed, g.stream_r, (uint32_t)(r >> 2), (uint32_t)j, z);
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (r + e >= g.M) z[e] = T(0);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) z[e] = T(0);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                Os[(4 * gi + e) * SB + j] = z[e];
+                if (omr && split == 0 && r + e < g.M && j < g.wcols) omr[(r + e) * g.ldor + j] = z[e];
+            }
+        }
+    }
+
+    using Acc = typename Acc4<T>::type;
+    Acc acc[RT][LT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int t = 0; t < LT; ++t) acc[r][t] = Acc{0, 0, 0, 0};
+
+    V ra[NVA];
+    T ro[NOB][4];
+    auto load_a = [&](int64_t k0) {
+#pragma unroll
+        for (int it = 0; it < NVA; ++it) {
+            const int idx = tid + 256 * it;
+            const int64_t row = row0 + idx / (BK / VEC), col = k0 + (idx % (BK / VEC)) * VEC;
+            if (rows_full && k0 + BK <= kend) {
+                ra[it] = *reinterpret_cast<const V*>(A + row * g.lda + col);
+                continue;
+            }
+            V v;
+            if (row < g.M && avec && col + VEC <= kend) {
+                v = *reinterpret_cast<const V*>(A + row * g.lda + col);
+            } else {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e)
+                    vset<T>(v, e, (row < g.M && col + e < kend) ? A[row * g.lda + col + e] : T(0));
+            }
+            ra[it] = v;
+        }
+    };
+    auto load_b = [&](int64_t k0) {
+#pragma unroll
+        for (int it = 0; it < NOB; ++it) {
+            const int idx = tid + 256 * it;
+            const int gi = idx / L, j = idx % L;
+            const int64_t r = k0 + 4 * gi;
+            if (idx < BK / 4 * L && j < g.ncols && r < kend) {
+                omega_block<T>(g.seed, g.stream_c, (uint32_t)(r >> 2), (uint32_t)j, ro[it]);
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (r + e >= kend) ro[it][e] = T(0);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) ro[it][e] = T(0);
+            }
+        }
+    };
+    T* omc = static_cast<T*>(g.omega_c_out);
+    auto store_tiles = [&](int64_t k0) {
+#pragma unroll
+        for (int it = 0; it < NVA; ++it) {
+            const int idx = tid + 256 * it;
+            const int r = idx / (BK / VEC), c = (idx % (BK / VEC)) * VEC;
+            vec_store<T>(&As[dual_pos<T>(r, c)], ra[it]);
+        }
+#pragma unroll
+        for (int it = 0; it < NOB; ++it) {
+            const int idx = tid + 256 * it;
+            if (idx < BK / 4 * L) {
+                const int gi = idx / L, j = idx % L;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    Bs[(4 * gi + e) * SB + j] = ro[it][e];
+                    const int64_t r = k0 + 4 * gi + e;
+                    if (omc && tile == 0 && r < kend && j < g.wcols) omc[r * g.ldoc + j] = ro[it][e];
+                }
+            }
+        }
+    };
+
+    const int wm = wave * 16 * RT;
+    const int ct = wave % CT, h = wave / CT;
+    T* __restrict__ Pr = static_cast<T*>(g.part_r) + (size_t)tile * (size_t)g.K * L;
+    if (kbeg < kend) {
+        load_a(kbeg);
+        load_b(kbeg);
+        for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+            __syncthreads();
+            store_tiles(k0);
+            __syncthreads();
+            if (k0 + BK < kend) {
+                load_a(k0 + BK);
+                load_b(k0 + BK);
+            }
+            // Y_c += A(tile rows, K tile) Omega_c(K tile): row-wise fragments.
+            {
+                T fa[2][RT], fb[2][LT];
+                auto frags = [&](int kk, T (&a)[RT], T (&b)[LT]) {
+#pragma unroll
+                    for (int r = 0; r < RT; ++r) a[r] = As[dual_pos<T>(wm + 16 * r + li, kk + lk)];
+#pragma unroll
+                    for (int t = 0; t < LT; ++t) b[t] = Bs[(kk + lk) * SB + 16 * t + li];
+                };
+                frags(0, fa[0], fb[0]);
+#pragma unroll
+                for (int st = 0; st < BK / 4; ++st) {
+                    const int cur = st & 1;
+                    if (st + 1 < BK / 4) frags(4 * (st + 1), fa[cur ^ 1], fb[cur ^ 1]);
+#pragma unroll
+                    for (int t = 0; t < LT; ++t)
+#pragma unroll
+                        for (int r = 0; r < RT; ++r) acc[r][t] = mfma16x16x4(fa[cur][r], fb[cur][t], acc[r][t]);
+                    if (st + 1 < BK / 4) __builtin_amdgcn_sched_group_barrier(0x100, RT + LT, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x008, RT * LT, 0);
+                }
+            }
+            // Y_r(K tile) partial = A(tile rows, K tile)^T Omega_r(tile rows):
+            // column-wise fragments, contraction over the BM rows.
+            {
+                Acc accr[LTH];
+#pragma unroll
+                for (int t = 0; t < LTH; ++t) accr[t] = Acc{0, 0, 0, 0};
+                T fa[2], fb[2][LTH];
+                auto frags = [&](int kk, T& a, T (&b)[LTH]) {
+                    a = As[dual_pos<T>(kk + lk, 16 * ct + li)];
+#pragma unroll
+                    for (int t = 0; t < LTH; ++t) {
+                        const int tt = h * LTH + t;
+                        b[t] = tt < LT ? Os[(kk + lk) * SB + 16 * tt + li] : T(0);
+                    }
+                };
+                frags(0, fa[0], fb[0]);
+#pragma unroll 8
+                for (int st = 0; st < BM / 4; ++st) {
+                    const int cur = st & 1;
+                    if (st + 1 < BM / 4) frags(4 * (st + 1), fa[cur ^ 1], fb[cur ^ 1]);
+#pragma unroll
+                    for (int t = 0; t < LTH; ++t) accr[t] = mfma16x16x4(fa[cur], fb[cur][t], accr[t]);
+                }
+#pragma unroll
+                for (int t = 0; t < LTH; ++t) {
+                    const int tt = h * LTH + t;
+                    if (tt >= LT) continue;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int64_t col = k0 + 16 * ct + acc_row<T>(lk, v);
+                        if (col < kend) Pr[col * L + 16 * tt + li] = accr[t][v];
+                    }
+                }
+            }
+        }
+    }
+
+    // Y_c epilogue, as in the products above.
+    if (splits == 1) {
+        T* __restrict__ Y = static_cast<T*>(g.Yc);
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int t = 0; t < LT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t row = row0 + wm + 16 * r + acc_row<T>(lk, v);
+                    const int col = 16 * t + li;
+                    if (row < g.M && col < g.wcols) Y[row * g.ldyc + col] = acc[r][t][v];
+                }
+        return;
+    }
+    T* __restrict__ P = static_cast<T*>(g.part_c);
+    const int64_t pstride = g.M * L;
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int t = 0; t < LT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = row0 + wm + 16 * r + acc_row<T>(lk, v);
+                if (row < g.M) P[split * pstride + row * L + 16 * t + li] = acc[r][t][v];
+            }
+}
+
+// Y (rows x wcols, ldy) = sum of `slices` partials of rows x L, in slice
+// order.  One thread per 16-byte vector; loads are issued 8 slices at a time.
+template <typename T>
+__global__ __launch_bounds__(256) void slices_reduce_kernel(const T* __restrict__ P, int64_t rows, int L, int slices,
+                                                            T* __restrict__ Y, int64_t ldy, int wcols) {
+    using V = typename Vec16<T>::type;
+    constexpr int VEC = Vec16<T>::n;
+    const int64_t nvec = rows * (L / VEC);
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= nvec) return;
+    const int64_t pstride = rows * L;
+    V sum;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) vset<T>(sum, e, T(0));
+    for (int s0 = 0; s0 < slices; s0 += 8) {
+        V x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (s0 + u < slices) x[u] = *reinterpret_cast<const V*>(P + (s0 + u) * pstride + idx * VEC);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (s0 + u < slices)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) vset<T>(sum, e, vget<T>(sum, e) + vget<T>(x[u], e));
+    }
+    const int64_t row = idx / (L / VEC);
+    const int c = (int)(idx % (L / VEC)) * VEC;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e)
+        if (c + e < wcols) Y[row * ldy + c + e] = vget<T>(sum, e);
+}
+
+static int dual_bm(int dtype) { return dtype == 0 ? DualTile<double>::BM : DualTile<float>::BM; }
+static int dual_bk(int dtype) { return dtype == 0 ? DualTile<double>::BK : DualTile<float>::BK; }
+
+int dual_row_tiles(int dtype, int64_t M) { return (int)ceil_div(M, dual_bm(dtype)); }
+
+int dual_splits(int dtype, int64_t M, int64_t K) {
+    const int tiles = dual_row_tiles(dtype, M);
+    const int64_t ktiles = ceil_div(K, dual_bk(dtype));
+    int s = (int)ceil_div(512, tiles);
+    s = (int)std::min<int64_t>(s, std::max<int64_t>(1, ktiles / 4));
+    s = std::max(1, std::min(s, kMaxSplits));
+    if (s > 1 && s < 8 && 8 <= ktiles / 4) s = 8;
+    return s;
+}
+
+hipError_t launch_dual_sketch(int dtype, DualArgs a, void* Yr, int64_t ldyr, hipStream_t s, hipEvent_t product_done) {
+    if (a.ncols < 1 || a.ncols > kMaxDualL || a.M < 1 || a.K < 1) return hipErrorInvalidValue;
+    if (a.splits < 1 || a.splits > kMaxSplits) return hipErrorInvalidValue;
+    const int LT = (int)ceil_div(a.ncols, 16);
+    const int tiles = dual_row_tiles(dtype, a.M);
+    dim3 grid(tiles * a.splits);
+#define RSVD_DUAL_CASE(N)                                                                                  \
+    case N:                                                                                                \
+        if (dtype == 0) hipLaunchKernelGGL((dual_sketch_kernel<double, N>), grid, dim3(256), 0, s, a);     \
+        else hipLaunchKernelGGL((dual_sketch_kernel<float, N>), grid, dim3(256), 0, s, a);                 \
+        break;
+    switch (LT) {
+        RSVD_DUAL_CASE(1) RSVD_DUAL_CASE(2) RSVD_DUAL_CASE(3) RSVD_DUAL_CASE(4) RSVD_DUAL_CASE(5)
+        RSVD_DUAL_CASE(6) RSVD_DUAL_CASE(7) RSVD_DUAL_CASE(8) RSVD_DUAL_CASE(9)
+        default: return hipErrorInvalidValue;
+    }
+#undef RSVD_DUAL_CASE
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (product_done && (e = hipEventRecord(product_done, s)) != hipSuccess) return e;
+    const int L = 16 * LT;
+    const int vec = dtype == 0 ? 2 : 4;
+    if (a.splits > 1) {
+        const int64_t nvec = a.M * (L / vec);
+        dim3 rgrid((unsigned)ceil_div(nvec, 256));
+        if (dtype == 0)
+            hipLaunchKernelGGL((splitk_reduce_kernel<double, kMaxSplits>), rgrid, dim3(256), 0, s,
+                               (const double*)a.part_c, a.M, L, a.splits, (double*)a.Yc, a.ldyc, a.wcols);
+        else
+            hipLaunchKernelGGL((splitk_reduce_kernel<float, kMaxSplits>), rgrid, dim3(256), 0, s,
+                               (const float*)a.part_c, a.M, L, a.splits, (float*)a.Yc, a.ldyc, a.wcols);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    const int64_t nvec = a.K * (L / vec);
+    dim3 rgrid((unsigned)ceil_div(nvec, 256));
+    if (dtype == 0)
+        hipLaunchKernelGGL(slices_reduce_kernel<double>, rgrid, dim3(256), 0, s, (const double*)a.part_r, a.K, L,
+                           tiles, (double*)Yr, ldyr, a.wcols);
+    else
+        hipLaunchKernelGGL(slices_reduce_kernel<float>, rgrid, dim3(256), 0, s, (const float*)a.part_r, a.K, L,
+                           tiles, (float*)Yr, ldyr, a.wcols);
+    return hipGetLastError();
+}
+// ---- two-sided sketch (end) ----
+
 // ---- SRFT test matrix: sampled columns (Floyd's algorithm) ----
 // One wavefront; step t (j = n - l + t) draws x = floor(w (j + 1) / 2^32)
 // from word 0 of block (t, 1, 4, 0) and takes x unless an earlier step took

@@ -51,6 +51,53 @@ hipError_t launch_gemm(int dtype, GemmArgs a, hipStream_t s, hipEvent_t product_
 hipError_t launch_splitk_reduce_f32(const float* partials, int64_t M, int L, int splits, float* Y, int64_t ldy,
                                     int wcols, hipStream_t s);
 
+// ---- two-sided sketch of the single-pass Algorithm 6 (gemm.hip) ----
+// Y_c = A Omega_c (M x l, Philox stream stream_c over the K rows of Omega_c)
+// and Y_r = A^T Omega_r (K x l, stream stream_r over the M rows of Omega_r)
+// from one read of A (M x K, FP32 or FP64).  l <= kMaxDualL.
+constexpr int kMaxDualL = 144;
+struct DualArgs {
+    const void* A; int64_t lda;
+    int64_t M, K;
+    uint64_t seed;
+    int ncols;                 // l
+    int wcols;                 // columns of Y_c / Y_r to write (l or L)
+    uint32_t stream_c, stream_r;
+    void* Yc; int64_t ldyc;    // M x wcols
+    void* part_c;              // splits * M * L (splits > 1)
+    int splits;
+    void* part_r;              // dual_row_tiles * K * L: per row tile partials of Y_r
+    void* omega_c_out; int64_t ldoc;   // nullable: Omega_c (K x L, zero past l)
+    void* omega_r_out; int64_t ldor;   // nullable: Omega_r (M x L, zero past l)
+};
+int dual_row_tiles(int dtype, int64_t M);
+int dual_splits(int dtype, int64_t M, int64_t K);
+// Launches the product kernel (product_done, optional, is recorded right
+// after it), the split-K reduction of Y_c and the row-tile reduction of Y_r
+// into Yr (K x wcols, ld ldyr).
+hipError_t launch_dual_sketch(int dtype, DualArgs a, void* Yr, int64_t ldyr, hipStream_t s,
+                              hipEvent_t product_done = nullptr);
+
+// ---- Stage 2 of the single-pass algorithms (single_pass.hip) ----
+// out (LX x LZ FP64, ld ldo) = X^T Z for X rows x LX, Z rows x LZ (dtype,
+// LX, LZ multiples of 16); partials: cross_partials_elems doubles.
+size_t cross_partials_elems(int64_t rows, int LX, int LZ);
+hipError_t launch_cross(int dtype, const void* X, int64_t ldx, const void* Z, int64_t ldz, int64_t rows, int LX,
+                        int LZ, double* partials, double* out, int ldo, hipStream_t s);
+// C (Mw x Nw, ldc) = op(A) op(B) on the leading M x N block, zero elsewhere;
+// with dr, dc: each element divided by dr[i]^2 + dc[j]^2.
+hipError_t launch_small_gemm(int M, int N, int K, const double* A, int lda, int ta, const double* B, int ldb, int tb,
+                             double* C, int ldc, int Mw, int Nw, hipStream_t s, const double* dr = nullptr,
+                             const double* dc = nullptr);
+// X (l x l, ldx) with W^T X = Z^T (Gauss-Jordan, partial pivoting), l <= 128.
+hipError_t launch_gj_solve(const double* Wt, const double* Zt, int ld, int l, double* X, int ldx, DevFlags* flags,
+                           hipStream_t s);
+// Symmetric part of X shifted by *shift = 2 ||sym(X)||_F, as Gram partials.
+hipError_t launch_sym_pack(const double* X, int ldx, int l, int L, double* partials, double* shift, hipStream_t s);
+// Eigenvalues sigma^2 - shift, the k of largest magnitude with their vectors.
+hipError_t launch_eig_finish(const double* sigma, const double* Ut, int l, int L, const double* shift, int k,
+                             double* lam_out, double* Wu, int ldw, hipStream_t s);
+
 // ---- products with a low-precision A (gemm_lp.hip) ----
 constexpr int kFmtBf16 = 2, kFmtFp8 = 3;           // RSVD_BF16, RSVD_FP8_E4M3
 struct LpGemmArgs {

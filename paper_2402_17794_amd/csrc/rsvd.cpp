@@ -205,7 +205,8 @@ constexpr double kPass2SkipTauF32 = 0x1.0p-24;
 // CholeskyQR2: Q1 = Y R1^{-1} is written to Qout, and the second pass
 // multiplies Qout by R2^{-1} in place.
 rsvd_status run_orth_cols(const Plan& P, void* ws, DevFlags* flags, int dtype, int64_t rows, int l, int L,
-                          const void* Y, void* Qout, int orth_mode, hipStream_t s) {
+                          const void* Y, void* Qout, int orth_mode, hipStream_t s, int64_t ldy = 0) {
+    if (ldy == 0) ldy = L;
     double* R = at<double>(ws, P.R);
     double* Rinv = at<double>(ws, P.Rinv);
     double* GP = at<double>(ws, P.GP);
@@ -213,9 +214,9 @@ rsvd_status run_orth_cols(const Plan& P, void* ws, DevFlags* flags, int dtype, i
     if (orth_mode != RSVD_ORTH_HOUSEHOLDER) {
         const int report = orth_mode == RSVD_ORTH_CHOLQR2;
         const double skip_tau = dtype == RSVD_F32 ? kPass2SkipTauF32 : 0.0;
-        RSVD_TRY(launch_gram(dtype, Y, L, rows, L, GP, nullptr, s));
+        RSVD_TRY(launch_gram(dtype, Y, ldy, rows, L, GP, nullptr, s));
         RSVD_TRY(launch_chol(GP, rows, l, L, R, Rinv, flags, 0, nullptr, work, 0.0, s, skip_tau, report));
-        RSVD_TRY(launch_apply(dtype, Y, L, rows, L, Rinv, L, L, Qout, L, 0, nullptr, &flags->orth_fail, nullptr,
+        RSVD_TRY(launch_apply(dtype, Y, ldy, rows, L, Rinv, L, L, Qout, L, 0, nullptr, &flags->orth_fail, nullptr,
                               nullptr, 1, s));
         RSVD_TRY(launch_gram(dtype, Qout, L, rows, L, GP, &flags->pass2_off, s));
         RSVD_TRY(launch_chol(GP, rows, l, L, R, Rinv, flags, 1, nullptr, work,
@@ -224,7 +225,7 @@ rsvd_status run_orth_cols(const Plan& P, void* ws, DevFlags* flags, int dtype, i
                               nullptr, 1, s));
         if (orth_mode == RSVD_ORTH_CHOLQR2) return RSVD_OK;
     }
-    RSVD_TRY(launch_householder(dtype, Y, L, rows, l, L, Qout, L, at<double>(ws, P.H), at<double>(ws, P.Qw),
+    RSVD_TRY(launch_householder(dtype, Y, ldy, rows, l, L, Qout, L, at<double>(ws, P.H), at<double>(ws, P.Qw),
                                 at<double>(ws, P.part), flags, orth_mode == RSVD_ORTH_HOUSEHOLDER, s));
     return RSVD_OK;
 }
@@ -412,7 +413,7 @@ rsvd_status check_params(const rsvd_matrix* A, const rsvd_params* p) {
         return RSVD_ERR_INVALID_ARG;
     if (p->extra_power_pass < -1 || p->extra_power_pass > 8) return RSVD_ERR_INVALID_ARG;
     if (p->orth < RSVD_ORTH_AUTO || p->orth > RSVD_ORTH_HOUSEHOLDER) return RSVD_ERR_INVALID_ARG;
-    if (p->algorithm != 0 && p->algorithm != 3 && p->algorithm != 4) return RSVD_ERR_INVALID_ARG;
+    if (p->algorithm != 0 && (p->algorithm < 3 || p->algorithm > 6)) return RSVD_ERR_INVALID_ARG;
     if (p->jacobi_max_sweeps < 0 || p->jacobi_max_sweeps > 1000) return RSVD_ERR_INVALID_ARG;
     if (p->test_matrix != RSVD_TEST_GAUSSIAN && p->test_matrix != RSVD_TEST_SRFT) return RSVD_ERR_INVALID_ARG;
     if (p->test_matrix == RSVD_TEST_SRFT && is_lowp(A->dtype)) return RSVD_ERR_UNSUPPORTED;
@@ -422,6 +423,24 @@ rsvd_status check_params(const rsvd_matrix* A, const rsvd_params* p) {
 }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Single-pass Algorithms 5 and 6: the limits of their kernels.
+constexpr int kMaxSingleL = 128;
+constexpr uint32_t kOmegaRowStream = 1;      // Omega_r of Algorithm 6
+bool single_pass(const rsvd_params* p) { return p->algorithm == 5 || p->algorithm == 6; }
+
+rsvd_status check_single_pass(const rsvd_matrix* A, const rsvd_params* p) {
+    if (A->dtype != RSVD_F32 && A->dtype != RSVD_F64) return RSVD_ERR_UNSUPPORTED;
+    if (p->q != 0 || p->test_matrix != RSVD_TEST_GAUSSIAN || p->return_full_l || p->residual)
+        return RSVD_ERR_UNSUPPORTED;
+    if (p->algorithm == 5 && A->rows != A->cols) return RSVD_ERR_INVALID_ARG;
+    if (std::min<int64_t>(p->k + p->p, std::min(A->rows, A->cols)) > kMaxSingleL) return RSVD_ERR_UNSUPPORTED;
+    return RSVD_OK;
+}
+
+// Workspace bytes of a single-pass solve (defined with its layout below).
+rsvd_status sp_workspace_bytes(const rsvd_matrix* A, const rsvd_params* p, size_t* bytes);
+
 
 }  // namespace
 
@@ -473,12 +492,12 @@ rsvd_status rsvd_profile_enable(rsvd_handle* h, int32_t enable) {
 }
 
 rsvd_status rsvd_profile_read(rsvd_handle* h, int32_t kind, double* total_ms, int64_t* launches) {
-    if (!h || !total_ms || !launches || kind < 0 || kind > 6) return RSVD_ERR_INVALID_ARG;
+    if (!h || !total_ms || !launches || kind < 0 || kind > 7) return RSVD_ERR_INVALID_ARG;
     double tot = 0.0;
     int64_t cnt = 0;
     std::vector<rsvd_handle::Rec> keep;
     for (auto& r : h->recs) {
-        const bool match = kind == 3 ? (r.kind <= 2 || r.kind == 4) : r.kind == kind;   // kind 3: every product
+        const bool match = kind == 3 ? (r.kind <= 2 || r.kind == 4 || r.kind == 7) : r.kind == kind;   // kind 3: every product
         if (!match) { keep.push_back(r); continue; }
         if (hipEventSynchronize(r.stop) != hipSuccess) return RSVD_ERR_DEVICE;
         float ms = 0.0f;
@@ -501,6 +520,7 @@ rsvd_status rsvd_workspace_size(const rsvd_handle* h, const rsvd_matrix* A, cons
     rsvd_status st = check_matrix(A);
     if (st != RSVD_OK) return st;
     if ((st = check_params(A, params)) != RSVD_OK) return st;
+    if (single_pass(params)) return sp_workspace_bytes(A, params, bytes);
     Plan P;
     if (!make_plan(A->dtype, A->rows, A->cols, params->k, params->p, params->q, params->return_full_l, P,
                    params->residual & 1))
@@ -513,6 +533,254 @@ rsvd_status rsvd_workspace_size(const rsvd_handle* h, const rsvd_matrix* A, cons
 
 namespace {
 
+// ------------------------------------------------------------------------
+// Single-pass Algorithms 5 and 6 (Section 3.4).
+
+// Workspace: the Plan of Algorithm 4 for the same shape (flags, orth
+// scratch, Q = Q_1 (m x L), W = Q_2 (n x L), small-SVD buffers), then the
+// panels [Omega_r | Y_c] (m x 2L) and [Y_r | Omega_c] or [Y | Omega]
+// (n x 2L), the sketch partials and the FP64 Stage 2 matrices.
+struct SpLayout {
+    Plan base;
+    int alg = 6, Lk = 16, splits = 1, tiles = 1;
+    size_t part_c = 0, part_r = 0, panel_m = 0, panel_n = 0, xpart = 0, CTc = 0, CTr = 0, X = 0, Ut_c = 0,
+           Ut_r = 0, UtP = 0, UtS = 0, UtC = 0, MvC = 0, sig_c = 0, sig_r = 0, sigP = 0, sigS = 0, sigC = 0,
+           lam = 0, G1 = 0, G2 = 0, F = 0, T1 = 0, Cm = 0, T2 = 0, Ct = 0, T3 = 0, Wu = 0, Wv = 0, shiftE = 0,
+           total = 0;
+};
+
+bool sp_layout(int dtype, int alg, int64_t m, int64_t n, int64_t k, int64_t p, SpLayout& S) {
+    Plan& P = S.base;
+    if (!make_plan(dtype, m, n, k, p, 0, 0, P)) return false;
+    if (P.l > kMaxSingleL) return false;
+    S.alg = alg;
+    const int L = P.L;
+    const int Lk = S.Lk = (int)round_up(k, 16);
+    const size_t es = esize(dtype), d8 = sizeof(double);
+    Carver c;
+    c.take(P.total);                                        // the base plan sits at offset 0
+    if (alg == 6) {
+        S.splits = dual_splits(dtype, m, n);
+        S.tiles = dual_row_tiles(dtype, m);
+        S.part_c = c.take(es * (S.splits > 1 ? (size_t)S.splits * m * L : 1));
+        S.part_r = c.take(es * (size_t)S.tiles * n * L);
+        S.panel_m = c.take(es * (size_t)m * 2 * L);
+    }
+    S.panel_n = c.take(es * (size_t)n * 2 * L);
+    S.xpart = c.take(d8 * cross_partials_elems(std::max(m, n), 2 * L, L));
+    S.CTc = c.take(d8 * 2 * L * L);
+    S.sigC = c.take(d8 * L);
+    S.lam = c.take(d8 * L);
+    S.Wu = c.take(d8 * (size_t)L * Lk);
+    S.shiftE = c.take(d8);
+    if (alg == 5) {
+        S.X = c.take(d8 * (size_t)L * L);
+    } else {
+        S.CTr = c.take(d8 * 2 * L * L);
+        for (size_t* f : {&S.Ut_c, &S.Ut_r}) *f = c.take(d8 * (size_t)L * L);
+        for (size_t* f : {&S.UtP, &S.UtS, &S.UtC, &S.MvC, &S.F, &S.T1, &S.Cm, &S.T2, &S.Ct, &S.T3})
+            *f = c.take(d8 * (size_t)Lk * Lk);
+        for (size_t* f : {&S.sig_c, &S.sig_r, &S.sigP, &S.sigS}) *f = c.take(d8 * L);
+        for (size_t* f : {&S.G1, &S.G2}) *f = c.take(d8 * 2 * (size_t)L * Lk);
+        S.Wv = c.take(d8 * (size_t)L * Lk);
+    }
+    S.total = c.off;
+    return true;
+}
+
+rsvd_status sp_workspace_bytes(const rsvd_matrix* A, const rsvd_params* p, size_t* bytes) {
+    rsvd_status st = check_single_pass(A, p);
+    if (st != RSVD_OK) return st;
+    SpLayout S;
+    if (!sp_layout(A->dtype, p->algorithm, A->rows, A->cols, p->k, p->p, S)) return RSVD_ERR_UNSUPPORTED;
+    *bytes = S.total;
+    return RSVD_OK;
+}
+
+// Small SVD of B (l x L valid rows x cols of Bt = B^T, FP64, ld ldb):
+// Gram, shifted Cholesky, one-sided Jacobi, as in Algorithm 4 step 7.
+rsvd_status small_svd(rsvd_handle* hp, const Plan& P, void* ws, const double* Bt, int ldb, int rows, int l, int L,
+                      double* sigma, double* Ut, double* Mv, int max_sweeps, hipStream_t s) {
+    DevFlags* flags = at<DevFlags>(ws, P.flags);
+    RSVD_TRY(launch_gram(0, Bt, ldb, rows, L, at<double>(ws, P.GP), nullptr, s));
+    RSVD_TRY(launch_chol(at<double>(ws, P.GP), rows, l, L, at<double>(ws, P.R), at<double>(ws, P.Rinv), flags, 2,
+                         at<double>(ws, P.shift), at<double>(ws, P.work), 0.0, s));
+    rsvd_handle::Rec jac{6, nullptr, nullptr};
+    if (hp) {
+        jac.start = hp->get_event();
+        jac.stop = hp->get_event();
+        if (!jac.start || !jac.stop) return RSVD_ERR_DEVICE;
+        RSVD_TRY(hipEventRecord(jac.start, s));
+    }
+    RSVD_TRY(launch_jacobi(at<double>(ws, P.R), l, L, at<double>(ws, P.shift), sigma, Ut, Mv, flags,
+                           at<double>(ws, P.work), s, max_sweeps));
+    if (hp) {
+        RSVD_TRY(hipEventRecord(jac.stop, s));
+        hp->recs.push_back(jac);
+    }
+    return RSVD_OK;
+}
+
+// U (m x k) = Qu Wu and Vt (k x n) = (Qv Wv)^T with the sign rule of
+// Algorithm 4 (largest-magnitude entry of each V column positive); S = vals.
+rsvd_status finish_factors(const Plan& P, void* ws, int dt, const void* Qu, int64_t m, const double* Wu,
+                           const void* Qv, int64_t n, const double* Wv, int ldw, int k, const double* vals,
+                           const rsvd_result* out, hipStream_t s) {
+    const int L = P.L;
+    double* av = at<double>(ws, P.amax_val);
+    int* ai = at<int>(ws, P.amax_idx);
+    double* sign = at<double>(ws, P.sign);
+    RSVD_TRY(launch_apply(dt, Qv, L, n, L, Wv, ldw, k, out->Vt, out->ldvt, 1, nullptr, nullptr, av, ai, 0, s));
+    RSVD_TRY(launch_signs(av, ai, apply_blocks(n), k, vals, out->S, sign, s));
+    RSVD_TRY(launch_apply(dt, Qu, L, m, L, Wu, ldw, k, out->U, out->ldu, 0, sign, nullptr, nullptr, nullptr, 0, s));
+    RSVD_TRY(launch_scale_rows(dt, out->Vt, out->ldvt, k, n, sign, s));
+    return RSVD_OK;
+}
+
+rsvd_status solve_single_pass(rsvd_handle* hp, const SpLayout& S, const rsvd_matrix* A, const rsvd_params* params,
+                              const rsvd_result* out, void* ws, hipStream_t s) {
+    const Plan& P = S.base;
+    const int dt = P.dtype, L = P.L, l = (int)P.l, k = (int)P.k, Lk = S.Lk;
+    const int64_t m = P.m, n = P.n;
+    const size_t es = esize(dt);
+    const int om = params->orth, sweeps = params->jacobi_max_sweeps;
+    DevFlags* flags = at<DevFlags>(ws, P.flags);
+    char* pn = at<char>(ws, S.panel_n);
+    void* Q1 = at<char>(ws, P.Q);
+    void* Q2 = at<char>(ws, P.W);
+    double* xpart = at<double>(ws, S.xpart);
+    double* CTc = at<double>(ws, S.CTc);
+    double* Mv = at<double>(ws, P.Mv);
+    double* Wu = at<double>(ws, S.Wu);
+    rsvd_status st;
+    RSVD_TRY(launch_init(at<int>(ws, P.counters), P.ncounters, flags, s));
+    rsvd_handle::Rec stage1{5, nullptr, nullptr};
+    if (hp) {
+        stage1.start = hp->get_event();
+        stage1.stop = hp->get_event();
+        if (!stage1.start || !stage1.stop) return RSVD_ERR_DEVICE;
+        RSVD_TRY(hipEventRecord(stage1.start, s));
+    }
+    if (S.alg == 5) {
+        // Steps 1-3: Y = A Omega into [Y | Omega] (the one pass over A), Omega
+        // beside it (zero padded), Q = orth(Y).
+        if ((st = run_product(hp, P, ws, A, 0, nullptr, 0, params->seed, l, L, P.splits_nn, pn, 2 * L, s)) != RSVD_OK)
+            return st;
+        RSVD_TRY(launch_copy2d(dt, pn + es * L, 2 * L, n, 0, pn + es * L, 2 * L, L, s));
+        RSVD_TRY(launch_omega(dt, params->seed, 0, n, l, pn + es * L, 2 * L, s));
+        if ((st = run_orth_cols(P, ws, flags, dt, n, l, L, pn, Q1, om, s, 2 * L)) != RSVD_OK) return st;
+        if (hp) {
+            RSVD_TRY(hipEventRecord(stage1.stop, s));
+            hp->recs.push_back(stage1);
+        }
+        // Step 4: [Z^T ; W^T] = [Y | Omega]^T Q with Z = Q^T Y, W = Q^T Omega;
+        // C^T = X from W^T X = Z^T.
+        double* X = at<double>(ws, S.X);
+        RSVD_TRY(launch_cross(dt, pn, 2 * L, Q1, L, n, 2 * L, L, xpart, CTc, L, s));
+        RSVD_TRY(launch_gj_solve(CTc + (size_t)L * L, CTc, L, l, X, L, flags, s));
+        // Step 5: eigendecomposition of (C + C^T) / 2 through the shifted
+        // positive definite matrix and the small-SVD chain.
+        RSVD_TRY(launch_sym_pack(X, L, l, L, at<double>(ws, P.GP), at<double>(ws, S.shiftE), s));
+        RSVD_TRY(launch_chol(at<double>(ws, P.GP), l, l, L, at<double>(ws, P.R), at<double>(ws, P.Rinv), flags, 2,
+                             at<double>(ws, P.shift), at<double>(ws, P.work), 0.0, s));
+        rsvd_handle::Rec jac{6, nullptr, nullptr};
+        if (hp) {
+            jac.start = hp->get_event();
+            jac.stop = hp->get_event();
+            if (!jac.start || !jac.stop) return RSVD_ERR_DEVICE;
+            RSVD_TRY(hipEventRecord(jac.start, s));
+        }
+        RSVD_TRY(launch_jacobi(at<double>(ws, P.R), l, L, at<double>(ws, P.shift), at<double>(ws, P.sigma),
+                               at<double>(ws, P.Ut), Mv, flags, at<double>(ws, P.work), s, sweeps));
+        if (hp) {
+            RSVD_TRY(hipEventRecord(jac.stop, s));
+            hp->recs.push_back(jac);
+        }
+        double* lam = at<double>(ws, S.lam);
+        RSVD_TRY(launch_eig_finish(at<double>(ws, P.sigma), at<double>(ws, P.Ut), l, L, at<double>(ws, S.shiftE), k,
+                                   lam, Wu, Lk, s));
+        // Step 6: U = Q U^ (and Vt = U^T), eigenvector signs.
+        if ((st = finish_factors(P, ws, dt, Q1, n, Wu, Q1, n, Wu, Lk, k, lam, out, s)) != RSVD_OK) return st;
+        if (out->Q) RSVD_TRY(launch_copy2d(dt, Q1, L, n, l, out->Q, out->ldq, l, s));
+        RSVD_TRY(launch_export_info(flags, out->info, s, out->jacobi_sweeps));
+        return RSVD_OK;
+    }
+
+    // Algorithm 6.  Steps 1-2: one read of A gives Y_c = A Omega_c (into
+    // [Omega_r | Y_c]) and Y_r = A^T Omega_r (into [Y_r | Omega_c]); the
+    // kernel also writes both test matrices beside them.
+    char* pm = at<char>(ws, S.panel_m);
+    DualArgs a{};
+    a.A = A->data; a.lda = A->ld; a.M = m; a.K = n; a.seed = params->seed; a.ncols = l; a.wcols = L;
+    a.stream_c = 0; a.stream_r = kOmegaRowStream;
+    a.Yc = pm + es * L; a.ldyc = 2 * L;
+    a.part_c = at<char>(ws, S.part_c); a.splits = S.splits;
+    a.part_r = at<char>(ws, S.part_r);
+    a.omega_c_out = pn + es * L; a.ldoc = 2 * L;
+    a.omega_r_out = pm; a.ldor = 2 * L;
+    if (hp) {
+        rsvd_handle::Rec rec{7, hp->get_event(), hp->get_event()};
+        if (!rec.start || !rec.stop) return RSVD_ERR_DEVICE;
+        RSVD_TRY(hipEventRecord(rec.start, s));
+        RSVD_TRY(launch_dual_sketch(dt, a, pn, 2 * L, s, rec.stop));
+        hp->recs.push_back(rec);
+    } else {
+        RSVD_TRY(launch_dual_sketch(dt, a, pn, 2 * L, s));
+    }
+    // Step 3: Q_1 = orth(Y_c), Q_2 = orth(Y_r); the k dominant left singular
+    // vectors are Q_1 U^_c(:, 1:k), Q_2 U^_r(:, 1:k) with U^ from the SVD of
+    // T_c = Q_1^T Y_c and T_r = Q_2^T Y_r.
+    if ((st = run_orth_cols(P, ws, flags, dt, m, l, L, pm + es * L, Q1, om, s, 2 * L)) != RSVD_OK) return st;
+    if ((st = run_orth_cols(P, ws, flags, dt, n, l, L, pn, Q2, om, s, 2 * L)) != RSVD_OK) return st;
+    if (hp) {
+        RSVD_TRY(hipEventRecord(stage1.stop, s));
+        hp->recs.push_back(stage1);
+    }
+    double* CTr = at<double>(ws, S.CTr);
+    double *Ut_c = at<double>(ws, S.Ut_c), *Ut_r = at<double>(ws, S.Ut_r);
+    double *UtP = at<double>(ws, S.UtP), *UtS = at<double>(ws, S.UtS), *UtC = at<double>(ws, S.UtC);
+    double *sigP = at<double>(ws, S.sigP), *sigS = at<double>(ws, S.sigS), *sigC = at<double>(ws, S.sigC);
+    double *G1 = at<double>(ws, S.G1), *G2 = at<double>(ws, S.G2);
+    double *F = at<double>(ws, S.F), *T1 = at<double>(ws, S.T1), *Cm = at<double>(ws, S.Cm);
+    double *T2 = at<double>(ws, S.T2), *Ct = at<double>(ws, S.Ct), *T3 = at<double>(ws, S.T3);
+    double *MvC = at<double>(ws, S.MvC), *Wv = at<double>(ws, S.Wv);
+    // CTc = [Omega_r | Y_c]^T Q_1 = [K_c^T ; T_c^T], CTr = [Y_r | Omega_c]^T Q_2 = [T_r^T ; K_r^T]
+    // with K_c = Q_1^T Omega_r, K_r = Q_2^T Omega_c.
+    RSVD_TRY(launch_cross(dt, pm, 2 * L, Q1, L, m, 2 * L, L, xpart, CTc, L, s));
+    RSVD_TRY(launch_cross(dt, pn, 2 * L, Q2, L, n, 2 * L, L, xpart, CTr, L, s));
+    if ((st = small_svd(hp, P, ws, CTc + (size_t)L * L, L, l, l, L, at<double>(ws, S.sig_c), Ut_c, Mv, sweeps, s)) !=
+        RSVD_OK)
+        return st;
+    if ((st = small_svd(hp, P, ws, CTr, L, l, l, L, at<double>(ws, S.sig_r), Ut_r, Mv, sweeps, s)) != RSVD_OK)
+        return st;
+    // Step 4.  G1 = CTc U^_c,k = [M1 ; N2^T], G2 = CTr U^_r,k = [N1 ; M2^T] with
+    // M1 = Omega_r^T Q_c, N1 = Y_r^T Q_r, M2 = Q_r^T Omega_c, N2 = Q_c^T Y_c.
+    RSVD_TRY(launch_small_gemm(2 * L, k, L, CTc, L, 0, Ut_c, L, 0, G1, Lk, 2 * L, Lk, s));
+    RSVD_TRY(launch_small_gemm(2 * L, k, L, CTr, L, 0, Ut_r, L, 0, G2, Lk, 2 * L, Lk, s));
+    // Normal equations of the joint least-squares problem: P C + C S = F with
+    // P = M1^T M1 = UtP diag(sigP^2) UtP^T, S = M2 M2^T = UtS diag(sigS^2) UtS^T
+    // (eigendecompositions through the small SVDs of M1, M2^T) and
+    // F = M1^T N1 + N2 M2^T = G1^T G2.  C = UtP ((UtP^T F UtS) ./ (sigP_i^2 + sigS_j^2)) UtS^T.
+    if ((st = small_svd(hp, P, ws, G1, Lk, l, k, Lk, sigP, UtP, Mv, sweeps, s)) != RSVD_OK) return st;
+    if ((st = small_svd(hp, P, ws, G2 + (size_t)L * Lk, Lk, l, k, Lk, sigS, UtS, Mv, sweeps, s)) != RSVD_OK)
+        return st;
+    RSVD_TRY(launch_small_gemm(k, k, 2 * L, G1, Lk, 1, G2, Lk, 0, F, Lk, Lk, Lk, s));
+    RSVD_TRY(launch_small_gemm(k, k, k, UtP, Lk, 1, F, Lk, 0, T1, Lk, Lk, Lk, s));
+    RSVD_TRY(launch_small_gemm(k, k, k, T1, Lk, 0, UtS, Lk, 0, Cm, Lk, Lk, Lk, s, sigP, sigS));
+    RSVD_TRY(launch_small_gemm(k, k, k, UtS, Lk, 0, Cm, Lk, 1, T2, Lk, Lk, Lk, s));
+    RSVD_TRY(launch_small_gemm(k, k, k, T2, Lk, 0, UtP, Lk, 1, Ct, Lk, Lk, Lk, s));          // C^T
+    // Step 5: SVD of C (Bt = C^T): C = UtC diag(sigC) V^^T, V^ = C^T UtC diag(1/sigC).
+    if ((st = small_svd(hp, P, ws, Ct, Lk, k, k, Lk, sigC, UtC, MvC, sweeps, s)) != RSVD_OK) return st;
+    // Step 6: U = Q_1 (U^_c,k UtC), V = Q_2 (U^_r,k C^T MvC).
+    RSVD_TRY(launch_small_gemm(L, k, k, Ut_c, L, 0, UtC, Lk, 0, Wu, Lk, L, Lk, s));
+    RSVD_TRY(launch_small_gemm(k, k, k, Ct, Lk, 0, MvC, Lk, 0, T3, Lk, Lk, Lk, s));
+    RSVD_TRY(launch_small_gemm(L, k, k, Ut_r, L, 0, T3, Lk, 0, Wv, Lk, L, Lk, s));
+    if ((st = finish_factors(P, ws, dt, Q1, m, Wu, Q2, n, Wv, Lk, k, sigC, out, s)) != RSVD_OK) return st;
+    if (out->Q) RSVD_TRY(launch_copy2d(dt, Q1, L, m, l, out->Q, out->ldq, l, s));
+    RSVD_TRY(launch_export_info(flags, out->info, s, out->jacobi_sweeps));
+    return RSVD_OK;
+}
+
 // One solve on `stream` with the workspace ws.  profile: allow the event
 // records of rsvd_profile_enable (they may create HIP events).
 rsvd_status solve_impl(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* params, const rsvd_result* out,
@@ -521,6 +789,19 @@ rsvd_status solve_impl(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* 
     rsvd_status st = check_matrix(A);
     if (st != RSVD_OK) return st;
     if ((st = check_params(A, params)) != RSVD_OK) return st;
+    if (single_pass(params)) {
+        if ((st = check_single_pass(A, params)) != RSVD_OK) return st;
+        SpLayout S;
+        if (!sp_layout(A->dtype, params->algorithm, A->rows, A->cols, params->k, params->p, S))
+            return RSVD_ERR_UNSUPPORTED;
+        if (!out->U || !out->S || !out->Vt || !out->info) return RSVD_ERR_INVALID_ARG;
+        if (out->ldu < params->k || out->ldvt < A->cols) return RSVD_ERR_INVALID_ARG;
+        if (out->Q && out->ldq < S.base.l) return RSVD_ERR_INVALID_ARG;
+        if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return RSVD_ERR_INVALID_ARG;
+        if (ws_bytes < S.total) return RSVD_ERR_WORKSPACE_TOO_SMALL;
+        if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_DEVICE;
+        return solve_single_pass(profile && h->profiling ? h : nullptr, S, A, params, out, ws, as_stream(stream));
+    }
     Plan P;
     if (!make_plan(A->dtype, A->rows, A->cols, params->k, params->p, params->q, params->return_full_l, P,
                    params->residual & 1))
@@ -705,6 +986,49 @@ LpGemmLayout lp_gemm_layout(const rsvd_matrix* A, int trans, int64_t ncols) {
 }  // namespace
 
 extern "C" {
+
+rsvd_status rsvd_dual_sketch_workspace_size(const rsvd_matrix* A, int64_t l, size_t* bytes) {
+    rsvd_status st = check_matrix(A);
+    if (st != RSVD_OK) return st;
+    if (!bytes || l < 1) return RSVD_ERR_INVALID_ARG;
+    if (A->dtype != RSVD_F32 && A->dtype != RSVD_F64) return RSVD_ERR_UNSUPPORTED;
+    if (l > kMaxSingleL) return RSVD_ERR_UNSUPPORTED;
+    const int L = (int)round_up(l, 16);
+    const int64_t m = A->rows, n = A->cols;
+    const int splits = dual_splits(A->dtype, m, n);
+    Carver c;
+    c.take(esize(A->dtype) * (splits > 1 ? (size_t)splits * m * L : 1));
+    c.take(esize(A->dtype) * (size_t)dual_row_tiles(A->dtype, m) * n * L);
+    *bytes = c.off;
+    return RSVD_OK;
+}
+
+rsvd_status rsvd_dual_sketch(rsvd_handle* h, const rsvd_matrix* A, uint64_t seed, int64_t l, void* Yc, int64_t ldyc,
+                             void* Yr, int64_t ldyr, void* omega_c, int64_t ldoc, void* omega_r, int64_t ldor,
+                             void* ws, size_t ws_bytes, void* stream) {
+    if (!h) return RSVD_ERR_INVALID_ARG;
+    size_t need = 0;
+    rsvd_status st = rsvd_dual_sketch_workspace_size(A, l, &need);
+    if (st != RSVD_OK) return st;
+    if (!Yc || !Yr || ldyc < l || ldyr < l) return RSVD_ERR_INVALID_ARG;
+    if ((omega_c && ldoc < l) || (omega_r && ldor < l)) return RSVD_ERR_INVALID_ARG;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return RSVD_ERR_INVALID_ARG;
+    if (ws_bytes < need) return RSVD_ERR_WORKSPACE_TOO_SMALL;
+    if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_DEVICE;
+    const int L = (int)round_up(l, 16);
+    const int64_t m = A->rows, n = A->cols;
+    const int splits = dual_splits(A->dtype, m, n);
+    Carver c;
+    const size_t o_pc = c.take(esize(A->dtype) * (splits > 1 ? (size_t)splits * m * L : 1));
+    const size_t o_pr = c.take(esize(A->dtype) * (size_t)dual_row_tiles(A->dtype, m) * n * L);
+    DualArgs a{};
+    a.A = A->data; a.lda = A->ld; a.M = m; a.K = n; a.seed = seed; a.ncols = (int)l; a.wcols = (int)l;
+    a.stream_c = 0; a.stream_r = kOmegaRowStream;
+    a.Yc = Yc; a.ldyc = ldyc; a.part_c = at<char>(ws, o_pc); a.splits = splits; a.part_r = at<char>(ws, o_pr);
+    a.omega_c_out = omega_c; a.ldoc = ldoc; a.omega_r_out = omega_r; a.ldor = ldor;
+    RSVD_TRY(launch_dual_sketch(A->dtype, a, Yr, ldyr, as_stream(stream)));
+    return RSVD_OK;
+}
 
 rsvd_status rsvd_gemm_workspace_size(const rsvd_matrix* A, int32_t trans, int64_t ncols, size_t* bytes) {
     rsvd_status st = check_matrix(A);

@@ -53,6 +53,7 @@ class LowPrecisionMatrix:
 ORTH_AUTO, ORTH_CHOLQR2, ORTH_HOUSEHOLDER = 0, 1, 2
 INFO_ORTH_BREAKDOWN = 16
 INFO_FALLBACK_TIMEOUT = 32
+INFO_SINGULAR_SYSTEM = 64
 
 
 class rsvd_params(ctypes.Structure):
@@ -82,6 +83,7 @@ class rsvd_result(ctypes.Structure):
 EXPORTS = ["rsvd_create", "rsvd_destroy", "rsvd_l_used", "rsvd_workspace_size", "rsvd_solve", "rsvd_solve_noalloc",
            "rsvd_srft_omega", "rsvd_canonical_sines_workspace_size", "rsvd_canonical_sines",
            "rsvd_adaptive_range_workspace_size", "rsvd_adaptive_range",
+           "rsvd_dual_sketch_workspace_size", "rsvd_dual_sketch",
            "rsvd_status_string", "rsvd_profile_enable", "rsvd_profile_read", "rsvd_quantize", "rsvd_omega",
            "rsvd_philox_words", "rsvd_gemm_workspace_size", "rsvd_gemm", "rsvd_orth_workspace_size", "rsvd_orth",
            "rsvd_server_create", "rsvd_server_submit", "rsvd_server_poll", "rsvd_server_wait", "rsvd_server_drain",
@@ -133,6 +135,9 @@ def load_library(path=LIB_PATH):
         "rsvd_adaptive_range": ([P, ctypes.POINTER(rsvd_matrix), ctypes.c_double, I32, I64, U64, P, I64,
                                  ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I32), P, SZ, P],
                                 I32),
+        "rsvd_dual_sketch_workspace_size": ([ctypes.POINTER(rsvd_matrix), I64, ctypes.POINTER(SZ)], I32),
+        "rsvd_dual_sketch": ([P, ctypes.POINTER(rsvd_matrix), U64, I64, P, I64, P, I64, P, I64, P, I64, P, SZ, P],
+                             I32),
         "rsvd_gemm_workspace_size": ([ctypes.POINTER(rsvd_matrix), I32, I64, ctypes.POINTER(SZ)], I32),
         "rsvd_gemm": ([P, ctypes.POINTER(rsvd_matrix), I32, P, I64, U64, I64, P, I64, P, SZ, P], I32),
         "rsvd_orth_workspace_size": ([I32, I64, I64, ctypes.POINTER(SZ)], I32),
@@ -252,7 +257,9 @@ class Solver:
     uses the library's fixed device scratch instead of a workspace (no
     workspace tensor is made).  orth: ORTH_AUTO, ORTH_CHOLQR2 or
     ORTH_HOUSEHOLDER (force_householder=True is ORTH_HOUSEHOLDER);
-    algorithm: 4 (default) or 3 (no orth between the power products);
+    algorithm: 4 (default), 3 (no orth between the power products), or the
+    single-pass 5 (symmetric A: S holds signed eigenvalues, Vt = U^T) and 6
+    (general A, two sketches from one read);
     jacobi_max_sweeps: sweep cap of the small SVD (0 = default)."""
 
     def __init__(self, A, k, p=10, q=0, seed=0, residual=False, return_full_l=False, force_householder=False,
@@ -304,7 +311,7 @@ class Solver:
 def solve(A, k, p=10, q=0, seed=0, residual=False, return_full_l=False, force_householder=False, return_q=False,
           stream=None, residual_iters=0, extra_power_pass=-1, noalloc=False, orth=ORTH_AUTO, algorithm=4,
           jacobi_max_sweeps=0, test_matrix=TEST_GAUSSIAN):
-    """Randomized SVD (Algorithm 4, or Algorithm 3 with algorithm=3) of a
+    """Randomized SVD (Algorithm 4; Algorithm 3, 5 or 6 with algorithm=3, 5, 6) of a
     CUDA tensor A.  Returns a dict with U (m x r), S (r, float64), Vt
     (r x n), info (int), l, and optionally residual_t ([spectral estimate,
     Frobenius norm] of A - QQ^T A, float64 tensor) and Q (m x l).
@@ -401,6 +408,7 @@ class Server:
 
 
 PROFILE_SKETCH, PROFILE_NN, PROFILE_TN, PROFILE_ALL, PROFILE_PROJ32, PROFILE_STAGE1, PROFILE_JACOBI = 0, 1, 2, 3, 4, 5, 6
+PROFILE_DUAL = 7
 
 
 def profile_enable(device, enable=True):
@@ -505,6 +513,26 @@ def gemm(A, X=None, trans=False, seed=0, ncols=None):
                          X.stride(0) if X is not None else 0, seed, ncols, ctypes.c_void_p(Y.data_ptr()), ncols,
                          ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(None, A.device)))
     return Y
+
+
+def dual_sketch(A, l, seed=0):
+    """Two-sided sketch of Algorithm 6 from one read of A: returns
+    (Y_c = A Omega_c, Y_r = A^T Omega_r, Omega_c, Omega_r) with the test
+    matrices of streams 0 (n x l) and 1 (m x l) as the kernel generated them."""
+    lib = load_library()
+    M = _as_matrix(A)
+    m, n = A.shape
+    nb = ctypes.c_size_t()
+    _check(lib.rsvd_dual_sketch_workspace_size(ctypes.byref(M), l, ctypes.byref(nb)))
+    ws = _workspace(nb.value, A.device)
+    kw = dict(dtype=A.dtype, device=A.device)
+    Yc, Yr, Oc, Or = torch.empty((m, l), **kw), torch.empty((n, l), **kw), torch.empty((n, l), **kw), \
+        torch.empty((m, l), **kw)
+    _check(lib.rsvd_dual_sketch(_handle(A.device), ctypes.byref(M), seed, l, ctypes.c_void_p(Yc.data_ptr()), l,
+                                ctypes.c_void_p(Yr.data_ptr()), l, ctypes.c_void_p(Oc.data_ptr()), l,
+                                ctypes.c_void_p(Or.data_ptr()), l, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                _stream_ptr(None, A.device)))
+    return Yc, Yr, Oc, Or
 
 
 def orth(Y, force_householder=False, mode=None):

@@ -60,6 +60,38 @@ def test_host_only_entry_points(lib):
     assert b"scratch" in lib.rsvd_status_string(rsvd.RSVD_ERR_TOO_LARGE)
 
 
+def test_single_pass_argument_checks(lib):
+    """Algorithms 5 and 6: the host checks of their limits (no GPU needed)."""
+    from paper_2402_17794_amd import rsvd
+    nb = ctypes.c_size_t()
+    sq = rsvd.rsvd_matrix(0x1000, rsvd.RSVD_F32, 0, 4096, 4096, 4096)
+    rect = rsvd.rsvd_matrix(0x1000, rsvd.RSVD_F64, 0, 3000, 2000, 2000)
+
+    def ws(A, **kw):
+        args = dict(k=100, p=10, q=0)
+        args.update(kw)
+        p = rsvd.make_params(args.pop("k"), args.pop("p"), args.pop("q"), **args)
+        return lib.rsvd_workspace_size(None, ctypes.byref(A), ctypes.byref(p), ctypes.byref(nb))
+
+    for alg in (5, 6):
+        assert ws(sq, algorithm=alg) == 0 and nb.value > 4096 * 224 * 4
+        assert ws(sq, algorithm=alg, q=1) == 2                   # single pass: no power iterations
+        assert ws(sq, algorithm=alg, k=120) == 2                 # l = 130 > 128
+        assert ws(sq, algorithm=alg, residual=1) == 2
+        assert ws(sq, algorithm=alg, return_full_l=1) == 2
+        assert ws(sq, algorithm=alg, test_matrix=rsvd.TEST_SRFT) == 2
+    assert ws(rect, algorithm=6) == 0
+    assert ws(rect, algorithm=5) == 1                            # Algorithm 5 needs a square A
+    assert ws(sq, algorithm=7) == 1
+    bf = rsvd.rsvd_matrix(0x1000, rsvd.RSVD_BF16, 0, 4096, 4096, 4096)
+    assert ws(bf, algorithm=6) == 2
+    # Algorithm 6 holds the row-tile partials of A^T Omega_r: 32 tiles of 128 rows.
+    assert ws(sq, algorithm=6) == 0 and nb.value >= 32 * 4096 * 112 * 4
+    assert lib.rsvd_dual_sketch_workspace_size(ctypes.byref(sq), 110, ctypes.byref(nb)) == 0
+    assert nb.value >= 32 * 4096 * 112 * 4
+    assert lib.rsvd_dual_sketch_workspace_size(ctypes.byref(sq), 129, ctypes.byref(nb)) == 2
+
+
 def test_workspace_grows_with_the_block_jacobi_scratch(lib):
     """The workspace holds the block Jacobi's X (kMaxL^2 doubles) and its
     per-sweep words for any l, so an l > 128 solve needs nothing else."""
