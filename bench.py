@@ -10,7 +10,9 @@ default workload is the FP32 configuration: A = U diag(max(0.95^i, 1e-6)) V^T,
 Prints one JSON line: solves/s, ms per solve, p50/p99 latency, algorithmic
 TFLOP/s, the accuracy against the FP64 oracle, the roofline of the dominant
 kernel (timed with HIP events on the solve's stream) and the FP64 CPU
-oracle's own rate on this host.
+oracle's own rate on this host.  After the default workload the same line
+carries the single-pass Algorithm 6 on the same matrix (its two-sided sketch
+kernel's roofline) and the mixed-precision workload's three storage forms.
 """
 
 import argparse
@@ -212,6 +214,56 @@ def bench_lowp(args, cfg, A, torch, rsvd, workloads):
     return out
 
 
+def bench_single_pass(args, A, cfg, torch, rsvd, with_oracle):
+    """Algorithm 6 (single pass) on the same matrix: solves/s, and the
+    two-sided sketch kernel (A Omega_c and A^T Omega_r from one read of A)
+    against the FP32/FP64 MFMA peak, with the oracle's sigma error."""
+    m, n, k, p = cfg["m"], cfg["n"], cfg["k"], cfg["p"]
+    dev = A.device
+    solver = rsvd.Solver(A, k, p, 0, seed=0, algorithm=6)
+    l = solver.l
+    for _ in range(args.warmup):
+        solver()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        solver()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    rsvd.profile_enable(dev, True)
+    for _ in range(args.steps):
+        solver()
+    torch.cuda.synchronize()
+    rsvd.profile_enable(dev, False)
+    d_tot, d_cnt = rsvd.profile_read(dev, rsvd.PROFILE_DUAL)
+    s_tot, s_cnt = rsvd.profile_read(dev, rsvd.PROFILE_STAGE1)
+    j_tot, j_cnt = rsvd.profile_read(dev, rsvd.PROFILE_JACOBI)
+    rsvd.profile_read(dev, rsvd.PROFILE_ALL)
+    d_ms = d_tot / max(1, d_cnt)
+    flops = 2 * 2.0 * m * n * l
+    ach = flops / (d_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[cfg["dtype"]]
+    out = {
+        "algorithm": 6, "solves_per_s": 1.0 / dt, "ms_per_solve": dt * 1e3, "l": l,
+        "info": int(solver.info.item()),
+        "two_sided_sketch": {"kernel": "dual_sketch_kernel<float,%d>" % ((l + 15) // 16), "avg_launch_ms": d_ms,
+                             "flops_per_launch": flops, "achieved_tflops": ach, "peak_tflops": peak,
+                             "frac": ach / peak, "a_bytes_read_once": float(m * n * A.element_size()),
+                             "note": "A Omega_c and A^T Omega_r (2 x 2mnl flops) from one read of A; its row-tile "
+                                     "partials of A^T Omega_r are reduced by a separate kernel (outside this time)"},
+        "stage1_ms": s_tot / max(1, s_cnt),
+        "small_svds_ms": j_tot / max(1, args.steps),
+        "small_svds_per_solve": j_cnt / max(1, args.steps),
+    }
+    if with_oracle:
+        from oracle.single_pass import rsvd_alg6
+        ref = rsvd_alg6(A.double().cpu().numpy(), k, p, seed=0)
+        S = solver.S.cpu().numpy()
+        out["rel_err_vs_fp64_oracle_sigma_normwise"] = float(np.max(np.abs(S - ref["S"])) / ref["S"][0])
+    del solver
+    return out
+
+
 def bench_serving(args, cfg, torch, rsvd, workloads):
     """The serving workload through the request server: a Poisson replay of
     the trace (latency percentiles at the offered load), then a saturation
@@ -315,6 +367,8 @@ def main():
     ap.add_argument("--config", default="c2_fp32_8192")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c4", action="store_true", help="skip the mixed-precision forms after the default workload")
+    ap.add_argument("--no-single-pass", action="store_true",
+                    help="skip the single-pass Algorithm 6 timing after the default workload")
     ap.add_argument("--input", choices=("workload", "gaussian"), default="workload",
                     help="gaussian: i.i.d. N(0,1)/sqrt(n) matrix of the same shape, drawn on the device without a "
                          "QR; for hardware-counter runs, where the products' traffic does not depend on the values")
@@ -523,6 +577,9 @@ def main():
     sig = workloads.config_sigma(args.config)
     if sig is not None and args.input == "workload":
         out["err_vs_true_spectrum_normwise"] = float(np.max(np.abs(S_gpu - sig[:k])) / sig[0])
+    if args.config == "c2_fp32_8192" and args.input == "workload" and not args.no_single_pass:
+        print("bench: single-pass Algorithm 6 on the same matrix ...", file=sys.stderr, flush=True)
+        out["single_pass"] = bench_single_pass(args, A, cfg, torch, rsvd, not args.no_cpu_baseline)
     if args.config == "c2_fp32_8192" and args.input == "workload" and not args.no_c4:
         # The largest configuration, timed in the same run: the mixed-precision
         # workload in its three storage forms (5 timed solves each, no oracle
