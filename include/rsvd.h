@@ -51,8 +51,10 @@ typedef enum {
     RSVD_ERR_NO_MEMORY = 3,        /* a host or device allocation failed */
     RSVD_ERR_WORKSPACE_TOO_SMALL = 4,
     RSVD_ERR_DEVICE = 5,           /* a HIP runtime call failed */
-    RSVD_ERR_TOO_LARGE = 6         /* rsvd_solve_noalloc: the problem needs more device scratch
+    RSVD_ERR_TOO_LARGE = 6,        /* rsvd_solve_noalloc: the problem needs more device scratch
                                       than RSVD_NOALLOC_SCRATCH_BYTES */
+    RSVD_ERR_QUEUE_FULL = 7        /* rsvd_server_submit: max_pending requests already wait for
+                                      admission; nothing was queued, submit again later */
 } rsvd_status;
 
 typedef enum {
@@ -267,36 +269,61 @@ rsvd_status rsvd_quantize(int32_t dtype, const float* A, int64_t rows, int64_t c
  *
  * A server owns a device arena of hbm_budget_bytes (allocated once, at
  * create), n_streams ordinary streams and a scheduler thread.  Submitted
- * requests are queued and admitted in arrival order as soon as a stream is
- * free and the request's workspace (rsvd_workspace_size) fits in the arena
- * (admission by HBM footprint); an admitted request is one rsvd_solve on its
- * stream, so requests that arrive while others run overlap on the device.
- * A request borrows the caller's A and result buffers until it is done; its
- * result is the same as that of rsvd_solve alone.  Submit, poll, wait,
- * drain and stats may be called from any thread.  A request whose workspace
- * exceeds the whole arena is refused at submit (RSVD_ERR_NO_MEMORY).
- * Latency = time from submit until the scheduler sees the request's
- * completion event. */
+ * requests wait in a queue of at most max_pending entries (0 = 4096; a submit
+ * to a full queue returns RSVD_ERR_QUEUE_FULL and queues nothing).  They are
+ * admitted oldest first as soon as a stream is free and the request's
+ * workspace (rsvd_workspace_size) fits in the arena (admission by HBM
+ * footprint).  When the oldest request does not fit, younger requests that
+ * fit are admitted past it, but the oldest is passed over at most 8 times;
+ * after that admission waits until it fits.  An admitted request is one
+ * rsvd_solve on its stream, so requests that arrive while others run overlap
+ * on the device.  A request borrows the caller's A and result buffers until
+ * it is done; its result is the same as that of rsvd_solve alone.  Submit,
+ * poll, wait, release, drain and stats may be called from any thread.  A
+ * request whose workspace exceeds the whole arena is refused at submit
+ * (RSVD_ERR_NO_MEMORY).  Latency = time from submit until the scheduler sees
+ * the request's completion event. */
 typedef struct rsvd_server rsvd_server;
-rsvd_status rsvd_server_create(rsvd_server** out, int device, size_t hbm_budget_bytes, int n_streams);
+rsvd_status rsvd_server_create(rsvd_server** out, int device, size_t hbm_budget_bytes, int n_streams,
+                               int32_t max_pending);
+/* ready_event (nullable, a hipEvent_t): the request's stream waits for it
+ * before the solve's first kernel.  A caller that writes A, or allocates the
+ * result buffers, with work on its own stream records an event there after
+ * that work and passes it here, so the request never reads A before it is
+ * written nor writes a buffer still in use (the server's streams do not
+ * synchronise with other streams).  The event is waited on when the request
+ * is admitted; it must stay valid until then. */
 rsvd_status rsvd_server_submit(rsvd_server* s, const rsvd_matrix* A, const rsvd_params* params,
-                               const rsvd_result* out, uint64_t* ticket);
+                               const rsvd_result* out, void* ready_event, uint64_t* ticket);
 /* done = 1 once the request's kernels have completed; final_status: its status. */
 rsvd_status rsvd_server_poll(rsvd_server* s, uint64_t ticket, int* done, rsvd_status* final_status);
 /* Block until the request is done; latency_ms (nullable) receives its latency. */
 rsvd_status rsvd_server_wait(rsvd_server* s, uint64_t ticket, rsvd_status* final_status, double* latency_ms);
+/* Forget a done request (its ticket becomes unknown): a long-running server
+ * holds a record for every request not yet released.  RSVD_ERR_INVALID_ARG
+ * for an unknown ticket or a request not done yet. */
+rsvd_status rsvd_server_release(rsvd_server* s, uint64_t ticket);
+/* paused != 0: admit nothing until called again with 0 (queued requests
+ * wait; running ones finish).  For controlled batching and tests. */
+rsvd_status rsvd_server_pause(rsvd_server* s, int32_t paused);
 /* Block until every submitted request is done. */
 rsvd_status rsvd_server_drain(rsvd_server* s);
-/* Over the completed requests: latency percentiles, completed / (last completion - first submit). */
+/* Latency percentiles over the last 65536 completed requests; solves/s =
+ * completed / (last completion - first submit); completed counts all. */
 rsvd_status rsvd_server_stats(rsvd_server* s, double* p50_ms, double* p99_ms, double* solves_per_s,
                               int64_t* completed);
 /* Launch graphs (on by default): each admitted request's kernels are captured
- * into a HIP graph and launched as one; every stream slot keeps the
- * executable graphs of its last 8 shape buckets (precision, m, n, k, p, q
- * and the options) and updates the one of a request's bucket with the
- * request's pointers instead of instantiating a new one.  enable = 0 makes
- * later admissions launch the kernels directly.  Results are the same either
- * way. */
+ * into a HIP graph and launched as one.  Executable graphs are pooled by
+ * bucket: a request takes an idle graph of its bucket and updates it with its
+ * own pointers, sizes and launch grids instead of instantiating a new one;
+ * the graph is idle again when the request retires (at most 256 idle graphs
+ * are kept, least recently used evicted).  A bucket is what fixes the
+ * sequence of kernels: precision, l rounded up to 16, the output width
+ * rounded up to 16, q and the options, and whether each product kind is split
+ * along its reduction; so requests of different m, n and k share one.  An
+ * update the runtime refuses falls back to a new instantiation.  enable = 0
+ * makes later admissions launch the kernels directly.  Results are the same
+ * either way. */
 rsvd_status rsvd_server_use_graphs(rsvd_server* s, int32_t enable);
 /* Requests launched as graphs so far, and executable graphs instantiated
  * (launches minus instantiations = launches that reused an updated graph). */

@@ -204,7 +204,8 @@ hipError_t launch_copy2d(int dtype, const void* src, int64_t lds, int64_t rows, 
 
 // Zero `count` ints and the flags block.
 hipError_t launch_init(int* counters, int count, DevFlags* flags, hipStream_t s);
-// Copy the flags' info word into the caller's info (OR-ed).
+// Write the flags' info word to the caller's info (an assignment: the
+// caller's word needs no initialisation).
 // sweeps (nullable): also the Jacobi sweep count of the small SVD.
 hipError_t launch_export_info(const DevFlags* flags, int* info, hipStream_t s, int* sweeps = nullptr);
 

@@ -456,6 +456,7 @@ const char* rsvd_status_string(rsvd_status s) {
         case RSVD_ERR_DEVICE: return "HIP runtime error";
         case RSVD_ERR_TOO_LARGE:
             return "problem needs more device scratch than rsvd_solve_noalloc holds (RSVD_NOALLOC_SCRATCH_BYTES)";
+        case RSVD_ERR_QUEUE_FULL: return "server queue full (max_pending requests wait for admission)";
     }
     return "unknown status";
 }

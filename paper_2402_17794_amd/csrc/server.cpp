@@ -1,9 +1,11 @@
 // Batched request server of the C ABI (rsvd_server_*): continuous batching
 // of independent randomized SVD requests of uneven shape on one GPU.
 //
-// Requests are queued on submit and admitted in arrival order as soon as a
-// stream slot is free and their workspace fits in the server's HBM budget
-// (one device arena, sub-allocated first fit).  An admitted request is one
+// Requests are queued on submit (at most max_pending) and admitted oldest
+// first as soon as a stream slot is free and their workspace fits in the
+// server's HBM budget (one device arena, sub-allocated first fit); younger
+// requests that fit may pass an oldest one that does not, a bounded number of
+// times.  An admitted request is one
 // rsvd_solve on its slot's stream, so requests that arrive while others run
 // overlap on the device; each uses its own workspace and the same
 // deterministic kernels, so its result is the same alone and in the mix.
@@ -13,12 +15,16 @@
 // the completion.
 //
 // Launch graphs: by default an admitted request's kernels are captured from
-// rsvd_solve into a HIP graph and launched as one graph.  Each slot keeps
-// the executable graphs of its last few shape buckets (a bucket = every
-// parameter that fixes the kernel sequence: precision, m, n, k, p, q and the
-// options); a request of a cached bucket updates that executable graph in
-// place with its own pointers and sizes (hipGraphExecUpdate), otherwise a new
-// one is instantiated.  The captured kernels are exactly those rsvd_solve
+// rsvd_solve into a HIP graph and launched as one graph.  Executable graphs
+// are pooled by bucket (a bucket = what fixes the kernel sequence:
+// precision, l and the output width rounded to 16, q, the options, and
+// whether each product is split along its reduction).  An admitted request
+// takes an idle executable graph of its bucket, updates it in place with its
+// own pointers, sizes and grids (hipGraphExecUpdate) and launches it; the
+// graph returns to the pool when the request retires, so a graph never runs
+// twice at once.  With no idle graph of the bucket, or when the runtime
+// refuses the update, a new one is instantiated; the pool keeps at most
+// kGraphPool idle graphs (least recently used evicted).  The captured kernels are exactly those rsvd_solve
 // enqueues (no memset or copy nodes), so a graph computes what the direct
 // launches compute.
 #include <hip/hip_runtime.h>
@@ -36,6 +42,7 @@
 #include <vector>
 
 #include "../../include/rsvd.h"
+#include "kernels.hpp"
 
 namespace {
 
@@ -85,10 +92,11 @@ private:
 };
 
 // Everything about a request that decides which kernels rsvd_solve launches.
+constexpr int kKeyLen = 18;
 struct BucketKey {
-    int64_t v[17];
+    int64_t v[kKeyLen];
     bool operator==(const BucketKey& o) const {
-        for (int i = 0; i < 17; ++i)
+        for (int i = 0; i < kKeyLen; ++i)
             if (v[i] != o.v[i]) return false;
         return true;
     }
@@ -99,7 +107,11 @@ struct GraphEntry {
     hipGraphExec_t exec = nullptr;
     uint64_t last_use = 0;
 };
-constexpr size_t kGraphsPerSlot = 8;
+constexpr size_t kGraphPool = 256;
+constexpr int kMaxBypass = 8;             // times the oldest request may be passed over
+constexpr size_t kAdmitWindow = 64;       // pending requests looked at per admission pass
+constexpr size_t kLatencyWindow = 65536;  // latencies kept for the percentiles
+constexpr int kDefaultMaxPending = 4096;
 
 struct Request {
     uint64_t ticket;
@@ -112,6 +124,9 @@ struct Request {
     Clock::time_point t_submit, t_done;
     rsvd_status status = RSVD_OK;
     bool done = false;
+    hipEvent_t ready = nullptr;           // the caller's event the request's stream waits for
+    int bypassed = 0;                     // younger requests admitted while this one was the oldest
+    GraphEntry graph;                     // the executable graph it was launched as (exec null: direct)
 };
 
 }  // namespace
@@ -130,19 +145,22 @@ struct rsvd_server {
     std::condition_variable cv_work, cv_done;
     std::deque<Request*> pending;
     std::vector<Request*> running;
-    std::map<uint64_t, Request*> all;
+    std::map<uint64_t, Request*> all;     // every request not yet released
     uint64_t next_ticket = 1;
-    bool stop = false;
+    size_t max_pending = kDefaultMaxPending;
+    bool stop = false, paused = false;
     std::thread worker;
 
-    // launch graphs, per slot
+    // launch graphs: the idle pool (touched by the scheduler thread only)
     std::atomic<bool> use_graphs{true};
-    std::vector<std::vector<GraphEntry>> graphs;       // touched by the scheduler thread only
+    std::vector<GraphEntry> idle_graphs;
     uint64_t graph_clock = 0;
     std::atomic<int64_t> graph_launches{0}, graph_instantiations{0};
 
-    // statistics
+    // statistics: the last kLatencyWindow latencies (a ring) and a count
     std::vector<double> latencies_ms;
+    size_t lat_next = 0;
+    int64_t completed = 0;
     Clock::time_point t_first{}, t_last{};
     bool any = false;
 
@@ -152,13 +170,42 @@ struct rsvd_server {
 
 namespace {
 
+// The kernels a solve launches depend on the shape only through l (their
+// tile templates and the small-matrix kernels' forms), the output width and
+// whether a product is split along its reduction (a reduction kernel
+// follows); grids, sizes and pointers are launch arguments, which a graph
+// update replaces.
 BucketKey bucket_of(const Request* r) {
     const rsvd_params& p = r->params;
-    return BucketKey{{(int64_t)r->A.dtype, r->A.rows, r->A.cols, p.k, p.p, p.q, (int64_t)p.extra_power_pass,
+    const int64_t m = r->A.rows, n = r->A.cols;
+    const int64_t l = std::min(p.k + p.p, std::min(m, n));
+    const int L = (int)((l + 15) / 16 * 16);
+    const int64_t width = p.return_full_l ? l : p.k;
+    const bool lowp = r->A.dtype == RSVD_BF16 || r->A.dtype == RSVD_FP8_E4M3;
+    const int wdt = lowp ? RSVD_F32 : r->A.dtype;
+    int snn = 1, stn = 1;
+    if (p.algorithm == 6) {
+        snn = rsvd::dual_splits(wdt, m, n);
+        rsvd::gemm_partials_elems(wdt, n, n, L, &stn);
+    } else if (lowp) {
+        rsvd::lp_partials_elems(m, n, L, &snn);
+        rsvd::lp_partials_elems(n, m, L, &stn);
+    } else {
+        rsvd::gemm_partials_elems(wdt, m, n, L, &snn);
+        rsvd::gemm_partials_elems(wdt, n, m, L, &stn);
+    }
+    int s16 = 0;
+    if (p.residual & 1) {
+        int a = 1, b = 1;
+        rsvd::gemm_partials_elems(RSVD_F32, m, n, 16, &a);
+        rsvd::gemm_partials_elems(RSVD_F32, n, m, 16, &b);
+        s16 = (a > 1) + 2 * (b > 1);
+    }
+    return BucketKey{{(int64_t)r->A.dtype, L, (width + 15) / 16, p.q, (int64_t)p.extra_power_pass,
                       (int64_t)p.residual, (int64_t)p.residual_iters, (int64_t)p.return_full_l,
                       (int64_t)p.orth, r->out.Q != nullptr, r->A.master != nullptr,
                       r->A.col_scale != nullptr, (int64_t)p.algorithm, (int64_t)p.jacobi_max_sweeps,
-                      (int64_t)p.test_matrix}};
+                      (int64_t)p.test_matrix, snn > 1, stn > 1, s16}};
 }
 
 }  // namespace
@@ -167,6 +214,8 @@ BucketKey bucket_of(const Request* r) {
 // into a graph that replaces (or updates) the slot's graph of its bucket.
 rsvd_status rsvd_server::launch(Request* r, int slot, void* ws) {
     hipStream_t st = streams[slot];
+    // Order the request after the caller's work (outside any capture).
+    if (r->ready && hipStreamWaitEvent(st, r->ready, 0) != hipSuccess) return RSVD_ERR_DEVICE;
     if (!use_graphs) return rsvd_solve(h, &r->A, &r->params, &r->out, ws, r->ws_bytes, st);
     if (hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) != hipSuccess) return RSVD_ERR_DEVICE;
     const rsvd_status rs = rsvd_solve(h, &r->A, &r->params, &r->out, ws, r->ws_bytes, st);
@@ -177,41 +226,36 @@ rsvd_status rsvd_server::launch(Request* r, int slot, void* ws) {
         return rs != RSVD_OK ? rs : RSVD_ERR_DEVICE;
     }
     const BucketKey key = bucket_of(r);
-    std::vector<GraphEntry>& cache = graphs[slot];
-    GraphEntry* ent = nullptr;
-    for (auto& e : cache)
-        if (e.key == key) ent = &e;
+    GraphEntry ent{key, nullptr, 0};
+    for (size_t e = 0; e < idle_graphs.size(); ++e)
+        if (idle_graphs[e].key == key) {          // take an idle graph of the bucket
+            ent = idle_graphs[e];
+            idle_graphs[e] = idle_graphs.back();
+            idle_graphs.pop_back();
+            break;
+        }
     bool ready = false;
-    if (ent) {
+    if (ent.exec) {
         hipGraphNode_t err_node = nullptr;
         hipGraphExecUpdateResult res;
-        if (hipGraphExecUpdate(ent->exec, g, &err_node, &res) == hipSuccess && res == hipGraphExecUpdateSuccess) {
+        if (hipGraphExecUpdate(ent.exec, g, &err_node, &res) == hipSuccess && res == hipGraphExecUpdateSuccess) {
             ready = true;
         } else {
-            (void)hipGraphExecDestroy(ent->exec);
-            ent->exec = nullptr;
+            (void)hipGraphExecDestroy(ent.exec);
+            ent.exec = nullptr;
         }
-    } else {
-        if (cache.size() >= kGraphsPerSlot) {         // evict the least recently used bucket
-            auto lru = std::min_element(cache.begin(), cache.end(),
-                                        [](const GraphEntry& a, const GraphEntry& b) { return a.last_use < b.last_use; });
-            if (lru->exec) (void)hipGraphExecDestroy(lru->exec);
-            cache.erase(lru);
-        }
-        cache.push_back(GraphEntry{key, nullptr, 0});
-        ent = &cache.back();
     }
     if (!ready) {
-        if (hipGraphInstantiate(&ent->exec, g, nullptr, nullptr, 0) != hipSuccess) {
-            ent->exec = nullptr;
+        if (hipGraphInstantiate(&ent.exec, g, nullptr, nullptr, 0) != hipSuccess) {
             (void)hipGraphDestroy(g);
             return RSVD_ERR_DEVICE;
         }
         ++graph_instantiations;
     }
-    ent->last_use = ++graph_clock;
-    const hipError_t el = hipGraphLaunch(ent->exec, st);
+    ent.last_use = ++graph_clock;
+    const hipError_t el = hipGraphLaunch(ent.exec, st);
     (void)hipGraphDestroy(g);
+    r->graph = ent;                               // returned to the pool when the request retires
     if (el != hipSuccess) return RSVD_ERR_DEVICE;
     ++graph_launches;
     return RSVD_OK;
@@ -231,33 +275,57 @@ void rsvd_server::loop() {
             if (q != hipSuccess) r->status = RSVD_ERR_DEVICE;
             arena->release(r->ws_off);
             slot_busy[r->slot] = 0;
+            if (r->graph.exec) {                // its graph is idle again
+                if (idle_graphs.size() >= kGraphPool) {
+                    auto lru = std::min_element(idle_graphs.begin(), idle_graphs.end(),
+                                                [](const GraphEntry& a, const GraphEntry& b) {
+                                                    return a.last_use < b.last_use;
+                                                });
+                    (void)hipGraphExecDestroy(lru->exec);
+                    *lru = idle_graphs.back();
+                    idle_graphs.pop_back();
+                }
+                idle_graphs.push_back(r->graph);
+                r->graph.exec = nullptr;
+            }
             r->done = true;
-            latencies_ms.push_back(std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count());
+            const double lat = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
+            if (latencies_ms.size() < kLatencyWindow) latencies_ms.push_back(lat);
+            else latencies_ms[lat_next] = lat;
+            lat_next = (lat_next + 1) % kLatencyWindow;
+            ++completed;
             t_last = r->t_done;
             running[i] = running.back();
             running.pop_back();
             progressed = true;
         }
         if (progressed) cv_done.notify_all();
-        // Admit in arrival order while a slot is free and the workspace fits.
-        while (!pending.empty()) {
-            Request* r = pending.front();
+        // Admit oldest first while a slot is free and the workspace fits; when
+        // the oldest does not fit, younger ones that fit may pass it, at most
+        // kMaxBypass times in all.
+        size_t scanned = 0;
+        for (auto it = pending.begin(); !paused && it != pending.end() && scanned < kAdmitWindow; ++scanned) {
+            Request* r = *it;
+            const bool oldest = it == pending.begin();
             int slot = -1;
-            for (size_t s = 0; s < slot_busy.size(); ++s)
-                if (!slot_busy[s]) { slot = (int)s; break; }
+            for (size_t sl = 0; sl < slot_busy.size(); ++sl)
+                if (!slot_busy[sl]) { slot = (int)sl; break; }
             if (slot < 0) break;
+            if (!oldest && pending.front()->bypassed >= kMaxBypass) break;
             size_t off = 0;
             if (!arena->alloc(r->ws_bytes, &off)) {
-                if (running.empty()) {          // can never fit
+                if (oldest && running.empty()) {       // can never fit
                     r->status = RSVD_ERR_NO_MEMORY;
                     r->done = true;
-                    pending.pop_front();
+                    it = pending.erase(it);
                     cv_done.notify_all();
                     continue;
                 }
-                break;
+                ++it;
+                continue;
             }
-            pending.pop_front();
+            if (!oldest) ++pending.front()->bypassed;
+            it = pending.erase(it);
             r->ws_off = off;
             r->slot = slot;
             slot_busy[slot] = 1;
@@ -271,10 +339,11 @@ void rsvd_server::loop() {
                 r->status = st != RSVD_OK ? st : RSVD_ERR_DEVICE;
             }
             running.push_back(r);
+            it = pending.begin();               // the queue changed while unlocked: rescan from the oldest
         }
         if (stop && pending.empty() && running.empty()) break;
-        if (running.empty() && pending.empty()) {
-            cv_work.wait(lk, [&] { return stop || !pending.empty(); });
+        if (running.empty() && (pending.empty() || paused)) {
+            cv_work.wait(lk, [&] { return stop || (!pending.empty() && !paused); });
         } else {
             // poll the in-flight events at a short interval
             cv_work.wait_for(lk, std::chrono::microseconds(20));
@@ -284,12 +353,15 @@ void rsvd_server::loop() {
 
 extern "C" {
 
-rsvd_status rsvd_server_create(rsvd_server** out, int device, size_t hbm_budget_bytes, int n_streams) {
-    if (!out || n_streams < 1 || n_streams > 64 || hbm_budget_bytes < kArenaAlign) return RSVD_ERR_INVALID_ARG;
+rsvd_status rsvd_server_create(rsvd_server** out, int device, size_t hbm_budget_bytes, int n_streams,
+                               int32_t max_pending) {
+    if (!out || n_streams < 1 || n_streams > 64 || hbm_budget_bytes < kArenaAlign || max_pending < 0)
+        return RSVD_ERR_INVALID_ARG;
     *out = nullptr;
     rsvd_server* s = new (std::nothrow) rsvd_server;
     if (!s) return RSVD_ERR_NO_MEMORY;
     s->device = device;
+    s->max_pending = max_pending ? (size_t)max_pending : (size_t)kDefaultMaxPending;
     rsvd_status st = rsvd_create(&s->h, device);
     if (st != RSVD_OK) { delete s; return st; }
     if (hipSetDevice(device) != hipSuccess) { rsvd_destroy(s->h); delete s; return RSVD_ERR_DEVICE; }
@@ -303,7 +375,6 @@ rsvd_status rsvd_server_create(rsvd_server** out, int device, size_t hbm_budget_
     s->streams.assign(n_streams, nullptr);
     s->events.assign(n_streams, nullptr);
     s->slot_busy.assign(n_streams, 0);
-    s->graphs.assign(n_streams, {});
     for (int i = 0; i < n_streams; ++i) {
         // default priority: every stream of the server is an ordinary stream
         if (hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) != hipSuccess ||
@@ -319,7 +390,7 @@ rsvd_status rsvd_server_create(rsvd_server** out, int device, size_t hbm_budget_
 }
 
 rsvd_status rsvd_server_submit(rsvd_server* s, const rsvd_matrix* A, const rsvd_params* params,
-                               const rsvd_result* out, uint64_t* ticket) {
+                               const rsvd_result* out, void* ready_event, uint64_t* ticket) {
     if (!s || !A || !params || !out || !ticket) return RSVD_ERR_INVALID_ARG;
     size_t bytes = 0;
     rsvd_status st = rsvd_workspace_size(s->h, A, params, &bytes);
@@ -331,10 +402,12 @@ rsvd_status rsvd_server_submit(rsvd_server* s, const rsvd_matrix* A, const rsvd_
     r->params = *params;
     r->out = *out;
     r->ws_bytes = bytes;
+    r->ready = static_cast<hipEvent_t>(ready_event);
     r->t_submit = Clock::now();
     {
         std::lock_guard<std::mutex> g(s->mu);
         if (s->stop) { delete r; return RSVD_ERR_INVALID_ARG; }
+        if (s->pending.size() >= s->max_pending) { delete r; return RSVD_ERR_QUEUE_FULL; }
         r->ticket = s->next_ticket++;
         if (!s->any) { s->t_first = r->t_submit; s->any = true; }
         s->all[r->ticket] = r;
@@ -367,6 +440,26 @@ rsvd_status rsvd_server_wait(rsvd_server* s, uint64_t ticket, rsvd_status* final
     return RSVD_OK;
 }
 
+rsvd_status rsvd_server_release(rsvd_server* s, uint64_t ticket) {
+    if (!s) return RSVD_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end() || !it->second->done) return RSVD_ERR_INVALID_ARG;
+    delete it->second;
+    s->all.erase(it);
+    return RSVD_OK;
+}
+
+rsvd_status rsvd_server_pause(rsvd_server* s, int32_t paused) {
+    if (!s) return RSVD_ERR_INVALID_ARG;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->paused = paused != 0;
+    }
+    s->cv_work.notify_all();
+    return RSVD_OK;
+}
+
 rsvd_status rsvd_server_drain(rsvd_server* s) {
     if (!s) return RSVD_ERR_INVALID_ARG;
     std::unique_lock<std::mutex> lk(s->mu);
@@ -379,7 +472,7 @@ rsvd_status rsvd_server_stats(rsvd_server* s, double* p50_ms, double* p99_ms, do
     if (!s) return RSVD_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> g(s->mu);
     std::vector<double> v = s->latencies_ms;
-    const size_t nlat = v.size();
+    const int64_t nlat = s->completed;
     auto pct = [&](double p) {
         if (v.empty()) return 0.0;
         const size_t i = std::min(v.size() - 1, (size_t)(p * (double)(v.size() - 1) + 0.5));
@@ -392,7 +485,7 @@ rsvd_status rsvd_server_stats(rsvd_server* s, double* p50_ms, double* p99_ms, do
         const double span = std::chrono::duration<double>(s->t_last - s->t_first).count();
         *solves_per_s = (nlat && span > 0) ? (double)nlat / span : 0.0;
     }
-    if (completed) *completed = (int64_t)nlat;
+    if (completed) *completed = nlat;
     return RSVD_OK;
 }
 
@@ -414,13 +507,13 @@ rsvd_status rsvd_server_destroy(rsvd_server* s) {
     {
         std::lock_guard<std::mutex> g(s->mu);
         s->stop = true;
+        s->paused = false;                  // queued requests still run before the thread ends
     }
     s->cv_work.notify_all();
     if (s->worker.joinable()) s->worker.join();
     for (auto& kv : s->all) delete kv.second;
-    for (auto& cache : s->graphs)
-        for (auto& e : cache)
-            if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    for (auto& e : s->idle_graphs)
+        if (e.exec) (void)hipGraphExecDestroy(e.exec);
     for (size_t i = 0; i < s->streams.size(); ++i) {
         if (s->streams[i]) (void)hipStreamDestroy(s->streams[i]);
         if (s->events[i]) (void)hipEventDestroy(s->events[i]);

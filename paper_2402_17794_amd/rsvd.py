@@ -87,7 +87,8 @@ EXPORTS = ["rsvd_create", "rsvd_destroy", "rsvd_l_used", "rsvd_workspace_size", 
            "rsvd_status_string", "rsvd_profile_enable", "rsvd_profile_read", "rsvd_quantize", "rsvd_omega",
            "rsvd_philox_words", "rsvd_gemm_workspace_size", "rsvd_gemm", "rsvd_orth_workspace_size", "rsvd_orth",
            "rsvd_server_create", "rsvd_server_submit", "rsvd_server_poll", "rsvd_server_wait", "rsvd_server_drain",
-           "rsvd_server_stats", "rsvd_server_destroy", "rsvd_server_use_graphs", "rsvd_server_graph_stats"]
+           "rsvd_server_stats", "rsvd_server_destroy", "rsvd_server_use_graphs", "rsvd_server_graph_stats",
+           "rsvd_server_release", "rsvd_server_pause"]
 
 _lib = None
 
@@ -115,9 +116,11 @@ def load_library(path=LIB_PATH):
         "rsvd_profile_enable": ([P, I32], I32),
         "rsvd_profile_read": ([P, I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)], I32),
         "rsvd_quantize": ([I32, P, I64, I64, I64, P, I64, P, P], I32),
-        "rsvd_server_create": ([ctypes.POINTER(P), ctypes.c_int, SZ, ctypes.c_int], I32),
+        "rsvd_server_create": ([ctypes.POINTER(P), ctypes.c_int, SZ, ctypes.c_int, I32], I32),
         "rsvd_server_submit": ([P, ctypes.POINTER(rsvd_matrix), ctypes.POINTER(rsvd_params),
-                                ctypes.POINTER(rsvd_result), ctypes.POINTER(U64)], I32),
+                                ctypes.POINTER(rsvd_result), P, ctypes.POINTER(U64)], I32),
+        "rsvd_server_release": ([P, U64], I32),
+        "rsvd_server_pause": ([P, I32], I32),
         "rsvd_server_poll": ([P, U64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(I32)], I32),
         "rsvd_server_wait": ([P, U64, ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_double)], I32),
         "rsvd_server_drain": ([P], I32),
@@ -153,13 +156,17 @@ def load_library(path=LIB_PATH):
 
 
 class RsvdError(RuntimeError):
-    pass
+    """A non-zero rsvd_status; `status` holds the code."""
+
+    def __init__(self, msg, status=0):
+        super().__init__(msg)
+        self.status = status
 
 
 def _check(status):
     if status != 0:
         msg = load_library().rsvd_status_string(status).decode()
-        raise RsvdError(f"librsvd: {msg} (status {status})")
+        raise RsvdError(f"librsvd: {msg} (status {status})", status)
 
 
 _handles = {}
@@ -245,6 +252,7 @@ def _residual_mode(residual):
 
 
 RSVD_ERR_TOO_LARGE = 6
+RSVD_ERR_QUEUE_FULL = 7
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
@@ -330,7 +338,7 @@ class Request:
     """A submitted server request: owns its output tensors (and keeps A
     alive) until it is done."""
 
-    def __init__(self, server, A, k, p, q, seed, return_full_l, extra_power_pass):
+    def __init__(self, server, A, k, p, q, seed, return_full_l, extra_power_pass, algorithm=4):
         m, n = A.shape
         self.A, self.l = A, l_used(m, n, k, p)
         r = self.l if return_full_l else k
@@ -340,24 +348,38 @@ class Request:
         self.Vt = torch.empty((r, n), dtype=A.dtype, device=dev)
         self.info = torch.empty((1,), dtype=torch.int32, device=dev)    # assigned by the solve
         self._M = _as_matrix(A)
-        self._params = make_params(k, p, q, seed, 0, return_full_l, extra_power_pass=extra_power_pass)
+        self._params = make_params(k, p, q, seed, 0, return_full_l, extra_power_pass=extra_power_pass,
+                                   algorithm=algorithm)
         self._result = rsvd_result(self.U.data_ptr(), r, self.S.data_ptr(), self.Vt.data_ptr(), n, None,
                                    self.info.data_ptr(), None, self.l)
+        # The server's streams do not wait for torch's: the request waits for
+        # this event, recorded after whatever made A and the outputs.
+        self._ready = torch.cuda.Event()
+        self._ready.record(torch.cuda.current_stream(dev))
         t = ctypes.c_uint64()
         _check(server.lib.rsvd_server_submit(server.ptr, ctypes.byref(self._M), ctypes.byref(self._params),
-                                             ctypes.byref(self._result), ctypes.byref(t)))
+                                             ctypes.byref(self._result), ctypes.c_void_p(self._ready.cuda_event),
+                                             ctypes.byref(t)))
         self.ticket = t.value
         self.server = server
+        self._latency = None
 
     def done(self):
+        if self._latency is not None:
+            return True
         d, st = ctypes.c_int(), ctypes.c_int32()
         _check(self.server.lib.rsvd_server_poll(self.server.ptr, self.ticket, ctypes.byref(d), ctypes.byref(st)))
         return bool(d.value)
 
     def wait(self):
-        """Block until done; returns the latency in ms (submit to completion)."""
+        """Block until done and release the server's record of the request;
+        returns the latency in ms (submit to completion)."""
+        if self._latency is not None:
+            return self._latency
         st, lat = ctypes.c_int32(), ctypes.c_double()
         _check(self.server.lib.rsvd_server_wait(self.server.ptr, self.ticket, ctypes.byref(st), ctypes.byref(lat)))
+        _check(self.server.lib.rsvd_server_release(self.server.ptr, self.ticket))
+        self._latency = lat.value
         _check(st.value)
         return lat.value
 
@@ -366,15 +388,22 @@ class Server:
     """Continuous-batching request server (rsvd_server_*): requests are
     admitted by HBM footprint into `n_streams` concurrent slots."""
 
-    def __init__(self, device="cuda:0", hbm_budget_bytes=16 << 30, n_streams=4):
+    def __init__(self, device="cuda:0", hbm_budget_bytes=16 << 30, n_streams=4, max_pending=0):
         self.lib = load_library()
         dev = torch.device(device)
         idx = dev.index if dev.index is not None else torch.cuda.current_device()
         self.ptr = ctypes.c_void_p()
-        _check(self.lib.rsvd_server_create(ctypes.byref(self.ptr), idx, int(hbm_budget_bytes), int(n_streams)))
+        _check(self.lib.rsvd_server_create(ctypes.byref(self.ptr), idx, int(hbm_budget_bytes), int(n_streams),
+                                           int(max_pending)))
 
-    def submit(self, A, k, p=10, q=0, seed=0, return_full_l=False, extra_power_pass=-1):
-        return Request(self, A, k, p, q, seed, return_full_l, extra_power_pass)
+    def submit(self, A, k, p=10, q=0, seed=0, return_full_l=False, extra_power_pass=-1, algorithm=4):
+        """Queue a solve (RsvdError with status RSVD_ERR_QUEUE_FULL when
+        max_pending requests already wait)."""
+        return Request(self, A, k, p, q, seed, return_full_l, extra_power_pass, algorithm)
+
+    def pause(self, paused=True):
+        """Hold (or resume) admissions; queued requests wait."""
+        _check(self.lib.rsvd_server_pause(self.ptr, int(paused)))
 
     def drain(self):
         _check(self.lib.rsvd_server_drain(self.ptr))

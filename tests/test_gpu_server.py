@@ -7,9 +7,15 @@
 * Admission by HBM footprint: with an arena that holds only about one
   request's workspace, requests still all complete (they queue); a request
   larger than the whole arena is refused at submit.
-* Launch graphs: requests of one shape bucket replay an updated executable
-  graph; every replay equals the direct solve, with graphs on and off.
+* Launch graphs: requests of one bucket (same l rounded to 16, q, options and
+  split pattern; any m, n, k) replay an updated executable graph; every
+  replay equals the direct solve, with graphs on and off.
+* A persistent loop: a bounded queue (RSVD_ERR_QUEUE_FULL), released tickets,
+  a bounded bypass of an oldest request that does not fit, and ordering after
+  the caller's stream for an A written on the device just before submit.
 """
+
+import ctypes
 
 import numpy as np
 import pytest
@@ -131,4 +137,105 @@ def test_graph_replays_equal_direct_solves(R, graphs):
         assert launches == 8 and inst == 2       # one instantiation per bucket, six updates
     else:
         assert launches == 0 and inst == 0
+    srv.close()
+
+
+def test_queue_bound_pause_and_release(R):
+    A = torch.randn(600, 400, device="cuda", dtype=torch.float64)
+    srv = R.Server("cuda:0", hbm_budget_bytes=1 << 30, n_streams=2, max_pending=3)
+    srv.pause(True)
+    reqs = [srv.submit(A, 10, 5, 0, seed=i) for i in range(3)]
+    with pytest.raises(R.RsvdError) as e:
+        srv.submit(A, 10, 5, 0, seed=9)
+    assert e.value.status == R.RSVD_ERR_QUEUE_FULL
+    assert not any(r.done() for r in reqs)           # nothing admitted while paused
+    srv.pause(False)
+    for r in reqs:
+        r.wait()                                      # waits, then releases the ticket
+    d, st = ctypes.c_int(), ctypes.c_int32()
+    assert srv.lib.rsvd_server_poll(srv.ptr, reqs[0].ticket, ctypes.byref(d), ctypes.byref(st)) == \
+        1                                             # RSVD_ERR_INVALID_ARG: released, unknown ticket
+    extra = srv.submit(A, 10, 5, 0, seed=3)           # room again
+    extra.wait()
+    st = srv.stats()
+    assert st["completed"] == 4
+    srv.close()
+
+
+def test_oldest_request_is_bypassed(R):
+    """Arena for the big request alone: while R (medium) runs, B (big) waits;
+    S (small), submitted after B, fits beside R and is admitted past B."""
+    Ar = torch.randn(3000, 2000, device="cuda")
+    Ab = torch.randn(6000, 4000, device="cuda")
+    As = torch.randn(300, 200, device="cuda")
+    wr, wb, ws = (R.workspace_size(A, 60, 10, 1) for A in (Ar, Ab, As))
+    budget = wb + (1 << 16)
+    assert wr + wb > budget and wr + ws <= budget
+    srv = R.Server("cuda:0", hbm_budget_bytes=budget, n_streams=4)
+    srv.pause(True)
+    r = srv.submit(Ar, 60, 10, 1, seed=1)
+    b = srv.submit(Ab, 60, 10, 1, seed=2)
+    sm = srv.submit(As, 60, 10, 1, seed=3)
+    srv.pause(False)
+    lat_s = sm.wait()
+    assert not b.done()                               # S finished while B still waited or ran
+    lat_b = b.wait()
+    r.wait()
+    assert lat_s < lat_b
+    for t, A, seed in ((r, Ar, 1), (b, Ab, 2), (sm, As, 3)):
+        direct = R.solve(A, 60, 10, 1, seed=seed)
+        torch.cuda.synchronize()
+        assert torch.equal(t.S, direct["S"]) and torch.equal(t.U, direct["U"])
+    srv.close()
+
+
+def test_device_written_input_is_ordered(R):
+    """A written by device work on torch's stream immediately before submit
+    (no host synchronisation): the request waits for it."""
+    srv = R.Server("cuda:0", hbm_budget_bytes=1 << 30, n_streams=3)
+    outs = []
+    for i in range(6):
+        g = torch.Generator(device="cuda")
+        g.manual_seed(100 + i)
+        A = torch.randn(2048, 1024, device="cuda", generator=g) @ torch.randn(1024, 1024, device="cuda",
+                                                                                generator=g)
+        outs.append((A, srv.submit(A, 40, 10, 1, seed=i)))
+    for i, (A, t) in enumerate(outs):
+        t.wait()
+        torch.cuda.synchronize()
+        direct = R.solve(A, 40, 10, 1, seed=i)
+        torch.cuda.synchronize()
+        assert torch.equal(t.S, direct["S"]) and torch.equal(t.Vt, direct["Vt"])
+        assert t.info.item() == direct["info_tensor"].item()
+    srv.close()
+
+
+def test_graph_bucket_spans_shapes(R):
+    """Requests of different m, n and k with the same l rounded to 16, q and
+    split pattern share one bucket: after the first, each updates the slot's
+    graph, and every result equals the direct solve."""
+    srv = R.Server("cuda:0", hbm_budget_bytes=1 << 30, n_streams=1)
+    shapes = [(4096, 3000, 40), (4000, 3500, 45), (3900, 2900, 38), (4096, 4096, 44)]
+    for i, (m, n, k) in enumerate(shapes):
+        A = torch.randn(m, n, device="cuda")
+        direct = R.solve(A, k, 6, 1, seed=i)
+        torch.cuda.synchronize()
+        t = srv.submit(A, k, 6, 1, seed=i)
+        t.wait()
+        torch.cuda.synchronize()
+        assert torch.equal(t.S, direct["S"]) and torch.equal(t.U, direct["U"]) and torch.equal(t.Vt, direct["Vt"])
+    launches, inst = srv.graph_stats()
+    assert launches == len(shapes) and inst < launches
+    srv.close()
+
+
+def test_single_pass_requests(R):
+    A = torch.randn(1500, 1000, device="cuda")
+    direct = R.solve(A, 30, 10, 0, seed=4, algorithm=6)
+    torch.cuda.synchronize()
+    srv = R.Server("cuda:0", hbm_budget_bytes=1 << 30, n_streams=2)
+    t = srv.submit(A, 30, 10, 0, seed=4, algorithm=6)
+    t.wait()
+    torch.cuda.synchronize()
+    assert torch.equal(t.S, direct["S"]) and torch.equal(t.U, direct["U"])
     srv.close()
