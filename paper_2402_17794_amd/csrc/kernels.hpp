@@ -185,9 +185,13 @@ hipError_t launch_householder(int dtype, const void* Y, int64_t ldy, int64_t row
 constexpr int kJacobiBlockSweeps = 30;                   // sweep cap of the l > 128 form
 constexpr size_t kJacobiWorkDoubles = (size_t)kMaxL * kMaxL + kJacobiBlockSweeps + 8;
 // max_sweeps: sweep cap (0 = the default of the form); reaching it sets
-// RSVD_INFO_JACOBI_NOT_CONVERGED.
+// RSVD_INFO_JACOBI_NOT_CONVERGED.  flags->jacobi_sweeps receives the largest
+// sweep count of the solve's small SVDs.  batch (l <= 128 only): that many
+// independent problems of the same l in one launch, one workgroup each,
+// problem b at R + b L^2, shift + b, sigma + b L, Ut + b L^2, Mv + b L^2.
 hipError_t launch_jacobi(const double* R, int l, int L, const double* shift, double* sigma, double* Ut,
-                         double* Mv, DevFlags* flags, double* work, hipStream_t s, int max_sweeps = 0);
+                         double* Mv, DevFlags* flags, double* work, hipStream_t s, int max_sweeps = 0,
+                         int batch = 1);
 
 // Reduce the per-block argmax partials of the V columns, choose signs,
 // write S (r values) and sign[c].

@@ -544,8 +544,11 @@ namespace {
 struct SpLayout {
     Plan base;
     int alg = 6, Lk = 16, splits = 1, tiles = 1;
-    size_t part_c = 0, part_r = 0, panel_m = 0, panel_n = 0, xpart = 0, CTc = 0, CTr = 0, X = 0, Ut_c = 0,
-           Ut_r = 0, UtP = 0, UtS = 0, UtC = 0, MvC = 0, sig_c = 0, sig_r = 0, sigP = 0, sigS = 0, sigC = 0,
+    // Pairs solved by one two-problem small-SVD launch sit side by side:
+    // Ut_c, Ut_r (L x L each), UtP, UtS (Lk x Lk each) and their sigmas,
+    // factors, shifts and Mv scratch.
+    size_t part_c = 0, part_r = 0, panel_m = 0, panel_n = 0, xpart = 0, CTc = 0, CTr = 0, X = 0, Ut_cr = 0,
+           UtPS = 0, UtC = 0, MvC = 0, sig_cr = 0, sigPS = 0, sigC = 0, R2 = 0, shift2 = 0, Mv2 = 0,
            lam = 0, G1 = 0, G2 = 0, F = 0, T1 = 0, Cm = 0, T2 = 0, Ct = 0, T3 = 0, Wu = 0, Wv = 0, shiftE = 0,
            total = 0;
 };
@@ -578,10 +581,15 @@ bool sp_layout(int dtype, int alg, int64_t m, int64_t n, int64_t k, int64_t p, S
         S.X = c.take(d8 * (size_t)L * L);
     } else {
         S.CTr = c.take(d8 * 2 * L * L);
-        for (size_t* f : {&S.Ut_c, &S.Ut_r}) *f = c.take(d8 * (size_t)L * L);
-        for (size_t* f : {&S.UtP, &S.UtS, &S.UtC, &S.MvC, &S.F, &S.T1, &S.Cm, &S.T2, &S.Ct, &S.T3})
+        S.Ut_cr = c.take(d8 * 2 * (size_t)L * L);
+        S.UtPS = c.take(d8 * 2 * (size_t)Lk * Lk);
+        for (size_t* f : {&S.UtC, &S.MvC, &S.F, &S.T1, &S.Cm, &S.T2, &S.Ct, &S.T3})
             *f = c.take(d8 * (size_t)Lk * Lk);
-        for (size_t* f : {&S.sig_c, &S.sig_r, &S.sigP, &S.sigS}) *f = c.take(d8 * L);
+        S.sig_cr = c.take(d8 * 2 * L);
+        S.sigPS = c.take(d8 * 2 * Lk);
+        S.R2 = c.take(d8 * 2 * (size_t)L * L);
+        S.Mv2 = c.take(d8 * 2 * (size_t)L * L);
+        S.shift2 = c.take(d8 * 2);
         for (size_t* f : {&S.G1, &S.G2}) *f = c.take(d8 * 2 * (size_t)L * Lk);
         S.Wv = c.take(d8 * (size_t)L * Lk);
     }
@@ -615,6 +623,33 @@ rsvd_status small_svd(rsvd_handle* hp, const Plan& P, void* ws, const double* Bt
     }
     RSVD_TRY(launch_jacobi(at<double>(ws, P.R), l, L, at<double>(ws, P.shift), sigma, Ut, Mv, flags,
                            at<double>(ws, P.work), s, max_sweeps));
+    if (hp) {
+        RSVD_TRY(hipEventRecord(jac.stop, s));
+        hp->recs.push_back(jac);
+    }
+    return RSVD_OK;
+}
+
+// Two independent small SVDs of the same size in one Jacobi launch (two
+// workgroups): Bt0, Bt1 (rows x L, ld ldb) -> sigma + b L, Ut + b L^2
+// (factors R2 + b L^2, shifts shift2[b], Mv scratch Mv2 + b L^2).
+rsvd_status small_svd2(rsvd_handle* hp, const Plan& P, void* ws, const double* Bt0, const double* Bt1, int ldb,
+                       int rows, int l, int L, double* R2, double* shift2, double* sigma, double* Ut, double* Mv2,
+                       int max_sweeps, hipStream_t s) {
+    DevFlags* flags = at<DevFlags>(ws, P.flags);
+    for (int b = 0; b < 2; ++b) {
+        RSVD_TRY(launch_gram(0, b ? Bt1 : Bt0, ldb, rows, L, at<double>(ws, P.GP), nullptr, s));
+        RSVD_TRY(launch_chol(at<double>(ws, P.GP), rows, l, L, R2 + (size_t)b * L * L, at<double>(ws, P.Rinv), flags,
+                             2, shift2 + b, at<double>(ws, P.work), 0.0, s));
+    }
+    rsvd_handle::Rec jac{6, nullptr, nullptr};
+    if (hp) {
+        jac.start = hp->get_event();
+        jac.stop = hp->get_event();
+        if (!jac.start || !jac.stop) return RSVD_ERR_DEVICE;
+        RSVD_TRY(hipEventRecord(jac.start, s));
+    }
+    RSVD_TRY(launch_jacobi(R2, l, L, shift2, sigma, Ut, Mv2, flags, at<double>(ws, P.work), s, max_sweeps, 2));
     if (hp) {
         RSVD_TRY(hipEventRecord(jac.stop, s));
         hp->recs.push_back(jac);
@@ -738,9 +773,10 @@ rsvd_status solve_single_pass(rsvd_handle* hp, const SpLayout& S, const rsvd_mat
         hp->recs.push_back(stage1);
     }
     double* CTr = at<double>(ws, S.CTr);
-    double *Ut_c = at<double>(ws, S.Ut_c), *Ut_r = at<double>(ws, S.Ut_r);
-    double *UtP = at<double>(ws, S.UtP), *UtS = at<double>(ws, S.UtS), *UtC = at<double>(ws, S.UtC);
-    double *sigP = at<double>(ws, S.sigP), *sigS = at<double>(ws, S.sigS), *sigC = at<double>(ws, S.sigC);
+    double *Ut_c = at<double>(ws, S.Ut_cr), *Ut_r = Ut_c + (size_t)L * L;
+    double *UtP = at<double>(ws, S.UtPS), *UtS = UtP + (size_t)Lk * Lk, *UtC = at<double>(ws, S.UtC);
+    double *sigP = at<double>(ws, S.sigPS), *sigS = sigP + Lk, *sigC = at<double>(ws, S.sigC);
+    double *R2 = at<double>(ws, S.R2), *shift2 = at<double>(ws, S.shift2), *Mv2 = at<double>(ws, S.Mv2);
     double *G1 = at<double>(ws, S.G1), *G2 = at<double>(ws, S.G2);
     double *F = at<double>(ws, S.F), *T1 = at<double>(ws, S.T1), *Cm = at<double>(ws, S.Cm);
     double *T2 = at<double>(ws, S.T2), *Ct = at<double>(ws, S.Ct), *T3 = at<double>(ws, S.T3);
@@ -749,10 +785,9 @@ rsvd_status solve_single_pass(rsvd_handle* hp, const SpLayout& S, const rsvd_mat
     // with K_c = Q_1^T Omega_r, K_r = Q_2^T Omega_c.
     RSVD_TRY(launch_cross(dt, pm, 2 * L, Q1, L, m, 2 * L, L, xpart, CTc, L, s));
     RSVD_TRY(launch_cross(dt, pn, 2 * L, Q2, L, n, 2 * L, L, xpart, CTr, L, s));
-    if ((st = small_svd(hp, P, ws, CTc + (size_t)L * L, L, l, l, L, at<double>(ws, S.sig_c), Ut_c, Mv, sweeps, s)) !=
-        RSVD_OK)
-        return st;
-    if ((st = small_svd(hp, P, ws, CTr, L, l, l, L, at<double>(ws, S.sig_r), Ut_r, Mv, sweeps, s)) != RSVD_OK)
+    // SVDs of T_c and T_r, side by side.
+    if ((st = small_svd2(hp, P, ws, CTc + (size_t)L * L, CTr, L, l, l, L, R2, shift2, at<double>(ws, S.sig_cr),
+                         Ut_c, Mv2, sweeps, s)) != RSVD_OK)
         return st;
     // Step 4.  G1 = CTc U^_c,k = [M1 ; N2^T], G2 = CTr U^_r,k = [N1 ; M2^T] with
     // M1 = Omega_r^T Q_c, N1 = Y_r^T Q_r, M2 = Q_r^T Omega_c, N2 = Q_c^T Y_c.
@@ -762,8 +797,8 @@ rsvd_status solve_single_pass(rsvd_handle* hp, const SpLayout& S, const rsvd_mat
     // P = M1^T M1 = UtP diag(sigP^2) UtP^T, S = M2 M2^T = UtS diag(sigS^2) UtS^T
     // (eigendecompositions through the small SVDs of M1, M2^T) and
     // F = M1^T N1 + N2 M2^T = G1^T G2.  C = UtP ((UtP^T F UtS) ./ (sigP_i^2 + sigS_j^2)) UtS^T.
-    if ((st = small_svd(hp, P, ws, G1, Lk, l, k, Lk, sigP, UtP, Mv, sweeps, s)) != RSVD_OK) return st;
-    if ((st = small_svd(hp, P, ws, G2 + (size_t)L * Lk, Lk, l, k, Lk, sigS, UtS, Mv, sweeps, s)) != RSVD_OK)
+    if ((st = small_svd2(hp, P, ws, G1, G2 + (size_t)L * Lk, Lk, l, k, Lk, R2, shift2, sigP, UtP, Mv2, sweeps, s)) !=
+        RSVD_OK)
         return st;
     RSVD_TRY(launch_small_gemm(k, k, 2 * L, G1, Lk, 1, G2, Lk, 0, F, Lk, Lk, Lk, s));
     RSVD_TRY(launch_small_gemm(k, k, k, UtP, Lk, 1, F, Lk, 0, T1, Lk, Lk, Lk, s));

@@ -155,12 +155,25 @@ __device__ __forceinline__ void jacobi_rank(const double* nrm2, int* rank_of, in
 // runs only after a sweep whose rotations all had |t| <= 2^-20, since with
 // the quadratic convergence of the last sweeps nothing earlier can pass it;
 // it saves the final sweep, which would rotate nothing.
+// Independent problems of one launch (one workgroup each): problem b reads
+// Rm + b * r and shift_p[b] and writes sigma + b * s, Ut + b * o, Mv + b * o.
+struct JBatch {
+    int64_t r, o;
+    int s;
+};
+
 template <int R>
 __global__ __launch_bounds__(512) void jacobi_oe_kernel(const double* __restrict__ Rm, int l, int L,
                                                         const double* __restrict__ shift_p,
                                                         double* __restrict__ sigma, double* __restrict__ Ut,
-                                                        double* __restrict__ Mv, DevFlags* flags, int max_sweeps) {
+                                                        double* __restrict__ Mv, DevFlags* flags, int max_sweeps,
+                                                        JBatch bs) {
     constexpr int LPP = 8, GMAX = kJacobiRegMax / 2;
+    Rm += blockIdx.x * bs.r;
+    shift_p += blockIdx.x;
+    sigma += blockIdx.x * bs.s;
+    Ut += blockIdx.x * bs.o;
+    Mv += blockIdx.x * bs.o;
     constexpr int BUF = 2 * R * GMAX * LPP;                 // exchange buffer [side][k][group][lane]
     static_assert(LPP * R <= kJacobiRegMax, "rows per column");
     __shared__ double xch[BUF];
@@ -316,7 +329,7 @@ __global__ __launch_bounds__(512) void jacobi_oe_kernel(const double* __restrict
         small = !__syncthreads_or(big);
     }
     if (!converged && tid == 0) atomicOr(&flags->info, RSVD_INFO_JACOBI_NOT_CONVERGED);
-    if (tid == 0) flags->jacobi_sweeps = sweeps_run;
+    if (tid == 0) atomicMax(&flags->jacobi_sweeps, sweeps_run);
 
 #pragma unroll
     for (int k = 0; k < R; ++k) {
@@ -520,7 +533,7 @@ __global__ __launch_bounds__(512) void jacobi_blk_finish_kernel(const double* __
         if (rotw[sweeps - 1] != 0) atomicOr(&flags->info, RSVD_INFO_JACOBI_NOT_CONVERGED);
         int run = 0;                  // sweeps until (and with) the first one that rotated nothing
         while (run < sweeps && rotw[run] != 0) ++run;
-        flags->jacobi_sweeps = min(run + 1, sweeps);
+        atomicMax(&flags->jacobi_sweeps, min(run + 1, sweeps));
     }
     for (int c = wid; c < l; c += 8) {
         double s2 = 0.0;
@@ -563,29 +576,31 @@ static void launch_jacobi_blk(const double* Rm, int l, int L, const double* shif
 
 template <int R>
 static void launch_jacobi_oe(const double* Rm, int l, int L, const double* shift, double* sigma, double* Ut,
-                             double* Mv, DevFlags* flags, hipStream_t s, int sweeps) {
+                             double* Mv, DevFlags* flags, hipStream_t s, int sweeps, int batch, JBatch bs) {
     const int groups = ((l + 1) & ~1) / 2;
     const int threads = (int)round_up(groups * 8, kWave);
-    hipLaunchKernelGGL(jacobi_oe_kernel<R>, dim3(1), dim3(threads), 0, s, Rm, l, L, shift, sigma, Ut, Mv, flags,
-                       sweeps);
+    hipLaunchKernelGGL(jacobi_oe_kernel<R>, dim3(batch), dim3(threads), 0, s, Rm, l, L, shift, sigma, Ut, Mv, flags,
+                       sweeps, bs);
 }
 
 hipError_t launch_jacobi(const double* R, int l, int L, const double* shift, double* sigma, double* Ut, double* Mv,
-                         DevFlags* flags, double* work, hipStream_t s, int max_sweeps) {
-    if (l < 1 || l > kMaxL || L < l || max_sweeps < 0) return hipErrorInvalidValue;
+                         DevFlags* flags, double* work, hipStream_t s, int max_sweeps, int batch) {
+    if (l < 1 || l > kMaxL || L < l || max_sweeps < 0 || batch < 1) return hipErrorInvalidValue;
+    if (batch > 1 && l > kJacobiRegMax) return hipErrorInvalidValue;
+    const JBatch bs{(int64_t)L * L, (int64_t)L * L, L};
     const int oe_sweeps = max_sweeps ? max_sweeps : kJacobiMaxSweeps;
     const int blk_sweeps = max_sweeps ? std::min(max_sweeps, kJacobiBlockSweeps) : kJacobiBlockSweeps;
     if (l <= kJacobiRegMax) {
         // rows per lane and column: 2 ceil(l / 16), so 8 lanes cover ceil(l / 16) * 16 >= l rows
         switch ((l + 15) / 16) {
-            case 1: launch_jacobi_oe<2>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps); break;
-            case 2: launch_jacobi_oe<4>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps); break;
-            case 3: launch_jacobi_oe<6>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps); break;
-            case 4: launch_jacobi_oe<8>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps); break;
-            case 5: launch_jacobi_oe<10>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps); break;
-            case 6: launch_jacobi_oe<12>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps); break;
-            case 7: launch_jacobi_oe<14>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps); break;
-            default: launch_jacobi_oe<16>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps); break;
+            case 1: launch_jacobi_oe<2>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps, batch, bs); break;
+            case 2: launch_jacobi_oe<4>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps, batch, bs); break;
+            case 3: launch_jacobi_oe<6>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps, batch, bs); break;
+            case 4: launch_jacobi_oe<8>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps, batch, bs); break;
+            case 5: launch_jacobi_oe<10>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps, batch, bs); break;
+            case 6: launch_jacobi_oe<12>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps, batch, bs); break;
+            case 7: launch_jacobi_oe<14>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps, batch, bs); break;
+            default: launch_jacobi_oe<16>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps, batch, bs); break;
         }
     } else {
         // rows per lane and column: ceil(l / 16), 16 lanes per column pair
