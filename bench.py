@@ -214,7 +214,7 @@ def bench_lowp(args, cfg, A, torch, rsvd, workloads):
     return out
 
 
-def bench_single_pass(args, A, cfg, torch, rsvd, with_oracle):
+def bench_single_pass(args, A, cfg, torch, rsvd, prof_summary, with_oracle):
     """Algorithm 6 (single pass) on the same matrix: solves/s, and the
     two-sided sketch kernel (A Omega_c and A^T Omega_r from one read of A)
     against the FP32/FP64 MFMA peak, with the oracle's sigma error."""
@@ -255,6 +255,11 @@ def bench_single_pass(args, A, cfg, torch, rsvd, with_oracle):
         "small_svds_ms": j_tot / max(1, args.steps),
         "small_svds_per_solve": j_cnt / max(1, args.steps),
     }
+    # HBM bytes per launch from the committed counter summary, while the
+    # kernel's source is the one the counters measured.
+    tr = prof_summary.read_traffic(os.path.join(ROOT, "profiles", "dual_sketch_c2_fp32_8192_traffic.txt"))
+    out["two_sided_sketch"]["traffic"] = tr[0] if tr is not None and tr[1] == prof_summary.gemm_source_hash("dual") \
+        else None
     if with_oracle:
         from oracle.single_pass import rsvd_alg6
         ref = rsvd_alg6(A.double().cpu().numpy(), k, p, seed=0)
@@ -577,9 +582,10 @@ def main():
     sig = workloads.config_sigma(args.config)
     if sig is not None and args.input == "workload":
         out["err_vs_true_spectrum_normwise"] = float(np.max(np.abs(S_gpu - sig[:k])) / sig[0])
-    if args.config == "c2_fp32_8192" and args.input == "workload" and not args.no_single_pass:
+    if args.config == "c2_fp32_8192" and not args.no_single_pass:
         print("bench: single-pass Algorithm 6 on the same matrix ...", file=sys.stderr, flush=True)
-        out["single_pass"] = bench_single_pass(args, A, cfg, torch, rsvd, not args.no_cpu_baseline)
+        out["single_pass"] = bench_single_pass(args, A, cfg, torch, rsvd, prof_summary,
+                                               not args.no_cpu_baseline and args.input == "workload")
     if args.config == "c2_fp32_8192" and args.input == "workload" and not args.no_c4:
         # The largest configuration, timed in the same run: the mixed-precision
         # workload in its three storage forms (5 timed solves each, no oracle

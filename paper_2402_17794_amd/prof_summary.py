@@ -5,7 +5,7 @@
         library's kernels and the calibration copy.
 
     python -m paper_2402_17794_amd.prof_summary traffic FETCH_DIR WRITE_DIR --kernel SUBSTR
-            --title T --command C
+            --title T --command C [--region product|dual]
         HBM traffic per dispatch of the kernel whose name contains SUBSTR,
         from a FETCH_SIZE run and a WRITE_SIZE run (*_counter_collection.csv).
         Both counters are scaled by what they read for the plain copy of
@@ -28,16 +28,22 @@ CALIB_BYTES = 256 << 20                     # the calibration copy in bench.py
 CALIB_NAME = "__amd_rocclr_copyBuffer"
 PKG = os.path.dirname(os.path.abspath(__file__))
 GEMM_HEADERS = ("csrc/common.hpp", "csrc/philox.hpp")
-BEGIN, END = "// ---- product kernel (begin) ----", "// ---- product kernel (end) ----"
+REGIONS = {
+    "product": ("// ---- product kernel (begin) ----", "// ---- product kernel (end) ----"),
+    "dual": ("// ---- two-sided sketch of the single-pass Algorithm 6 (begin) ----",
+             "// ---- two-sided sketch (end) ----"),
+}
 
 
-def gemm_source_hash():
-    """Hash of the product kernel's device source (the marked region of
-    csrc/gemm.hip and the device headers it uses); host-side launch code is
-    outside it."""
+def gemm_source_hash(region="product"):
+    """Hash of a product kernel's device source (the marked region of
+    csrc/gemm.hip, `product` for the products of Algorithm 4, `dual` for the
+    two-sided sketch, and the device headers they use); host-side launch
+    code of the products is outside it."""
+    begin, end = REGIONS[region]
     h = hashlib.sha256()
     src = open(os.path.join(PKG, "csrc/gemm.hip")).read()
-    h.update(src[src.index(BEGIN):src.index(END)].encode())
+    h.update(src[src.index(begin):src.index(end)].encode())
     for f in GEMM_HEADERS:
         with open(os.path.join(PKG, f), "rb") as fh:
             h.update(fh.read())
@@ -122,7 +128,7 @@ def traffic(args):
     print(f"fetch_bytes_scaled: {fb:.6e}")
     print(f"write_bytes_scaled: {wb:.6e}")
     print(f"traffic_bytes_per_launch: {fb + wb:.6e}")
-    print(f"gemm_source_hash: {gemm_source_hash()}")
+    print(f"gemm_source_hash: {gemm_source_hash(args.region)}")
 
 
 def read_traffic(path):
@@ -153,6 +159,8 @@ def main(argv=None):
     b.add_argument("--kernel", required=True)
     b.add_argument("--title", required=True)
     b.add_argument("--command", action="append", required=True)
+    b.add_argument("--region", default="product", choices=sorted(REGIONS),
+                   help="source region whose hash is recorded (product: Algorithm 4 products, dual: two-sided sketch)")
     args = ap.parse_args(argv)
     (kernels if args.mode == "kernels" else traffic)(args)
 
