@@ -286,6 +286,8 @@ def bench_serving(args, cfg, torch, rsvd, workloads):
     torch.cuda.synchronize()
     print(f"bench: inputs ready in {time.perf_counter() - tg:.1f} s", file=sys.stderr, flush=True)
     budget = int(cfg["budget_gb"] * (1 << 30))
+    if args.streams:
+        cfg = dict(cfg, streams=args.streams)
     for A, r in list(zip(mats, trace))[: args.warmup]:
         rsvd.solve(A, r["k"], r["p"], r["q"], seed=r["seed"])
     torch.cuda.synchronize()
@@ -374,6 +376,7 @@ def main():
     ap.add_argument("--no-c4", action="store_true", help="skip the mixed-precision forms after the default workload")
     ap.add_argument("--no-single-pass", action="store_true",
                     help="skip the single-pass Algorithm 6 timing after the default workload")
+    ap.add_argument("--streams", type=int, default=0, help="serving workload: stream slots (0 = the config's)")
     ap.add_argument("--input", choices=("workload", "gaussian"), default="workload",
                     help="gaussian: i.i.d. N(0,1)/sqrt(n) matrix of the same shape, drawn on the device without a "
                          "QR; for hardware-counter runs, where the products' traffic does not depend on the values")
@@ -384,10 +387,18 @@ def main():
               "a multi-GPU row-block sharding is described in DESIGN.md but not built.", file=sys.stderr)
         sys.exit(2)
 
-    import torch
-    from paper_2402_17794_amd import prof_summary, rsvd, workloads
+    from paper_2402_17794_amd import workloads
 
     cfg = workloads.CONFIGS[args.config]
+    if cfg.get("serving"):
+        # One hardware queue per stream slot (HIP maps streams onto
+        # GPU_MAX_HW_QUEUES queues, 4 by default, and kernels of streams that
+        # share a queue run one after another).  Set before HIP starts.
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", str(min(32, args.streams or cfg["streams"])))
+
+    import torch
+    from paper_2402_17794_amd import prof_summary, rsvd
+
     if cfg.get("serving"):
         print(json.dumps(bench_serving(args, cfg, torch, rsvd, workloads)), flush=True)
         return

@@ -157,7 +157,7 @@ CONFIGS = {
     "c3b_fp32_slow_2048": dict(m=2048, n=2048, k=50, p=10, q=1, dtype="f32",
                                spectrum=("power", 1.0)),
     # Serving: 2000 FP32 requests, Poisson arrivals at 200 req/s (serving_trace below).
-    "c5_serving": dict(serving=True, count=2000, rate=200.0, dtype="f32", budget_gb=16, streams=8),
+    "c5_serving": dict(serving=True, count=2000, rate=200.0, dtype="f32", budget_gb=16, streams=16),
     # Mixed precision: FP32 master, solved as FP32, BF16 and column-scaled FP8.
     "c4_mixed_32768x16384": dict(m=32768, n=16384, k=256, p=16, q=2, dtype="f32",
                                  spectrum=("power", 1.5), lowp=True),
