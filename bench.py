@@ -453,6 +453,24 @@ def main():
     info = int(solver.info.item())
     print(f"bench: {args.steps} solves in {dt * 1e3:.2f} ms", file=sys.stderr, flush=True)
 
+    # Two solves in flight: the same solves alternating between two streams,
+    # each with its own workspace (a solve's small SVD runs on one compute
+    # unit while the next solve's products use the others).  Reported beside
+    # the headline, which is one solve at a time.
+    streams2 = [torch.cuda.Stream(dev), torch.cuda.Stream(dev)]
+    solvers2 = [rsvd.Solver(A, k, p, q, seed=0, stream=st) for st in streams2]
+    torch.cuda.synchronize()
+    for i in range(2 * args.warmup):
+        solvers2[i % 2]()
+    torch.cuda.synchronize()
+    t2a = time.perf_counter()
+    for i in range(args.steps):
+        solvers2[i % 2]()
+    torch.cuda.synchronize()
+    dt2 = time.perf_counter() - t2a
+    same2 = all(torch.equal(sv.S, solver.S) and torch.equal(sv.U, solver.U) for sv in solvers2)
+    del solvers2, streams2
+
     # Same solves again with every product with A bracketed by HIP events on
     # the solve's stream: per-launch kernel durations for the roofline.
     rsvd.profile_enable(dev, True)
@@ -544,6 +562,9 @@ def main():
             "ms_per_solve": kinds[dom][0] / args.steps,
         },
         "small_svd_jacobi": {"ms": jac_ms, "sweeps": sweeps, "l": l},
+        "two_in_flight": {"solves_per_s": args.steps / dt2, "ms_per_solve": dt2 / args.steps * 1e3,
+                          "results_equal_single_stream": bool(same2),
+                          "note": "the same solves alternating between two streams with separate workspaces"},
     }
     # The roofline of the kernel that takes the most time per solve: the
     # product kind above, or the small SVD's Jacobi iteration (FP64 vector
