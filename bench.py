@@ -306,7 +306,7 @@ def bench_serving(args, cfg, torch, rsvd, workloads):
         srv.drain()
         wall = time.perf_counter() - t0
         st = srv.stats()
-        st["graph_launches"], st["graph_instantiations"] = srv.graph_stats()
+        st["graph_launches"], st["graph_instantiations"], st["graph_fallbacks"] = srv.graph_stats()
         srv.close()
         return reqs, st, wall
 

@@ -312,7 +312,7 @@ rsvd_status rsvd_server_drain(rsvd_server* s);
  * completed / (last completion - first submit); completed counts all. */
 rsvd_status rsvd_server_stats(rsvd_server* s, double* p50_ms, double* p99_ms, double* solves_per_s,
                               int64_t* completed);
-/* Launch graphs (on by default): each admitted request's kernels are captured
+/* Launch graphs (off by default): each admitted request's kernels are captured
  * into a HIP graph and launched as one.  Executable graphs are pooled by
  * bucket: a request takes an idle graph of its bucket and updates it with its
  * own pointers, sizes and launch grids instead of instantiating a new one;
@@ -321,13 +321,19 @@ rsvd_status rsvd_server_stats(rsvd_server* s, double* p50_ms, double* p99_ms, do
  * sequence of kernels: precision, l rounded up to 16, the output width
  * rounded up to 16, q and the options, and whether each product kind is split
  * along its reduction; so requests of different m, n and k share one.  An
- * update the runtime refuses falls back to a new instantiation.  enable = 0
- * makes later admissions launch the kernels directly.  Results are the same
- * either way. */
+ * update the runtime refuses falls back to a new instantiation, and a request
+ * whose capture fails is launched directly.  HIP refuses a device-wide
+ * synchronisation (hipDeviceSynchronize) from any thread while a stream of the
+ * device is capturing: with graphs on, the rest of the process must wait on
+ * streams or events instead.  enable = 0 (the default) launches the kernels
+ * directly.  Results are the same either way. */
 rsvd_status rsvd_server_use_graphs(rsvd_server* s, int32_t enable);
-/* Requests launched as graphs so far, and executable graphs instantiated
- * (launches minus instantiations = launches that reused an updated graph). */
-rsvd_status rsvd_server_graph_stats(rsvd_server* s, int64_t* launches, int64_t* instantiations);
+/* Requests launched as graphs so far, executable graphs instantiated
+ * (launches minus instantiations = launches that reused an updated graph), and
+ * requests launched directly because their capture failed.  Any pointer may be
+ * NULL. */
+rsvd_status rsvd_server_graph_stats(rsvd_server* s, int64_t* launches, int64_t* instantiations,
+                                    int64_t* fallbacks);
 /* Drains, then releases the arena, streams, graphs and thread. */
 rsvd_status rsvd_server_destroy(rsvd_server* s);
 

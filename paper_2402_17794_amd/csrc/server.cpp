@@ -14,8 +14,11 @@
 // to the pools).  Latency is measured from submit to the scheduler seeing
 // the completion.
 //
-// Launch graphs: by default an admitted request's kernels are captured from
-// rsvd_solve into a HIP graph and launched as one graph.  Executable graphs
+// Launch graphs (off by default, rsvd_server_use_graphs): an admitted
+// request's kernels are captured from rsvd_solve into a HIP graph and
+// launched as one graph.  HIP refuses a device-wide synchronisation from any
+// thread while a stream of the device is capturing, so with graphs on the
+// rest of the process must wait on streams or events, not on the device.  Executable graphs
 // are pooled by bucket (a bucket = what fixes the kernel sequence:
 // precision, l and the output width rounded to 16, q, the options, and
 // whether each product is split along its reduction).  An admitted request
@@ -152,10 +155,10 @@ struct rsvd_server {
     std::thread worker;
 
     // launch graphs: the idle pool (touched by the scheduler thread only)
-    std::atomic<bool> use_graphs{true};
+    std::atomic<bool> use_graphs{false};
     std::vector<GraphEntry> idle_graphs;
     uint64_t graph_clock = 0;
-    std::atomic<int64_t> graph_launches{0}, graph_instantiations{0};
+    std::atomic<int64_t> graph_launches{0}, graph_instantiations{0}, graph_fallbacks{0};
 
     // statistics: the last kLatencyWindow latencies (a ring) and a count
     std::vector<double> latencies_ms;
@@ -217,13 +220,22 @@ rsvd_status rsvd_server::launch(Request* r, int slot, void* ws) {
     // Order the request after the caller's work (outside any capture).
     if (r->ready && hipStreamWaitEvent(st, r->ready, 0) != hipSuccess) return RSVD_ERR_DEVICE;
     if (!use_graphs) return rsvd_solve(h, &r->A, &r->params, &r->out, ws, r->ws_bytes, st);
-    if (hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) != hipSuccess) return RSVD_ERR_DEVICE;
+    // A capture that fails for any reason recorded nothing that ran: the
+    // request is then launched directly (an invalid request gets the same
+    // error from the direct call).
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        ++graph_fallbacks;
+        return rsvd_solve(h, &r->A, &r->params, &r->out, ws, r->ws_bytes, st);
+    }
     const rsvd_status rs = rsvd_solve(h, &r->A, &r->params, &r->out, ws, r->ws_bytes, st);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(st, &g);
     if (rs != RSVD_OK || ec != hipSuccess || !g) {
         if (g) (void)hipGraphDestroy(g);
-        return rs != RSVD_OK ? rs : RSVD_ERR_DEVICE;
+        (void)hipGetLastError();
+        if (rs == RSVD_OK) ++graph_fallbacks;
+        return rsvd_solve(h, &r->A, &r->params, &r->out, ws, r->ws_bytes, st);
     }
     const BucketKey key = bucket_of(r);
     GraphEntry ent{key, nullptr, 0};
@@ -495,10 +507,12 @@ rsvd_status rsvd_server_use_graphs(rsvd_server* s, int32_t enable) {
     return RSVD_OK;
 }
 
-rsvd_status rsvd_server_graph_stats(rsvd_server* s, int64_t* launches, int64_t* instantiations) {
+rsvd_status rsvd_server_graph_stats(rsvd_server* s, int64_t* launches, int64_t* instantiations,
+                                    int64_t* fallbacks) {
     if (!s) return RSVD_ERR_INVALID_ARG;
     if (launches) *launches = s->graph_launches;
     if (instantiations) *instantiations = s->graph_instantiations;
+    if (fallbacks) *fallbacks = s->graph_fallbacks;
     return RSVD_OK;
 }
 

@@ -128,7 +128,7 @@ def load_library(path=LIB_PATH):
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)], I32),
         "rsvd_server_destroy": ([P], I32),
         "rsvd_server_use_graphs": ([P, I32], I32),
-        "rsvd_server_graph_stats": ([P, ctypes.POINTER(I64), ctypes.POINTER(I64)], I32),
+        "rsvd_server_graph_stats": ([P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64)], I32),
         "rsvd_omega": ([I32, U64, ctypes.c_uint32, I64, I64, P, I64, P], I32),
         "rsvd_philox_words": ([U64, ctypes.c_uint32, P, I64, P, P], I32),
         "rsvd_srft_omega": ([I32, U64, I64, I64, P, I64, P, P], I32),
@@ -409,14 +409,18 @@ class Server:
         _check(self.lib.rsvd_server_drain(self.ptr))
 
     def use_graphs(self, enable=True):
-        """Launch later admissions as captured per-bucket graphs (default) or directly."""
+        """Launch later admissions as captured per-bucket graphs, or directly
+        (the default).  While graphs are on, other code must not synchronise
+        the whole device (HIP refuses it during a capture): wait on streams,
+        events or the server's tickets instead."""
         _check(self.lib.rsvd_server_use_graphs(self.ptr, int(enable)))
 
     def graph_stats(self):
-        """(requests launched as graphs, executable graphs instantiated)."""
-        n, inst = ctypes.c_int64(), ctypes.c_int64()
-        _check(self.lib.rsvd_server_graph_stats(self.ptr, ctypes.byref(n), ctypes.byref(inst)))
-        return n.value, inst.value
+        """(requests launched as graphs, executable graphs instantiated,
+        requests launched directly after a failed capture)."""
+        n, inst, fb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(self.lib.rsvd_server_graph_stats(self.ptr, ctypes.byref(n), ctypes.byref(inst), ctypes.byref(fb)))
+        return n.value, inst.value, fb.value
 
     def stats(self):
         p50, p99, sps, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()

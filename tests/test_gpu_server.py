@@ -9,7 +9,9 @@
   larger than the whole arena is refused at submit.
 * Launch graphs: requests of one bucket (same l rounded to 16, q, options and
   split pattern; any m, n, k) replay an updated executable graph; every
-  replay equals the direct solve, with graphs on and off.
+  replay equals the direct solve, with graphs on and off.  Graphs are off by
+  default, and then the caller may synchronise the whole device while
+  requests run.
 * A persistent loop: a bounded queue (RSVD_ERR_QUEUE_FULL), released tickets,
   a bounded bypass of an oldest request that does not fit, and ordering after
   the caller's stream for an A written on the device just before submit.
@@ -132,9 +134,9 @@ def test_graph_replays_equal_direct_solves(R, graphs):
             torch.cuda.synchronize()
             for key, val in (("U", t.U), ("S", t.S), ("Vt", t.Vt)):
                 assert torch.equal(val, direct[key]), (rep, b, key)
-    launches, inst = srv.graph_stats()
+    launches, inst, fallbacks = srv.graph_stats()
     if graphs:
-        assert launches == 8 and inst == 2       # one instantiation per bucket, six updates
+        assert launches == 8 and inst == 2 and fallbacks == 0   # one instantiation per bucket, six updates
     else:
         assert launches == 0 and inst == 0
     srv.close()
@@ -210,11 +212,36 @@ def test_device_written_input_is_ordered(R):
     srv.close()
 
 
+def test_device_synchronize_while_serving(R):
+    """Default mode (direct launches), three slots kept busy, and the caller's
+    thread synchronising the whole device again and again while the scheduler
+    admits and launches: no call fails, nothing went through a graph, and
+    every result is bitwise the direct solve's."""
+    srv = R.Server("cuda:0", hbm_budget_bytes=1 << 30, n_streams=3)
+    As = [torch.randn(1500, 900, device="cuda", dtype=torch.float32) for _ in range(12)]
+    torch.cuda.synchronize()
+    tickets = [srv.submit(A, 40, 10, 1, seed=i) for i, A in enumerate(As)]
+    syncs = 0
+    while not all(t.done() for t in tickets):
+        torch.cuda.synchronize()
+        syncs += 1
+    for t in tickets:
+        t.wait()
+    assert syncs > 0
+    for i, (A, t) in enumerate(zip(As, tickets)):
+        direct = R.solve(A, 40, 10, 1, seed=i)
+        torch.cuda.synchronize()
+        assert torch.equal(t.S, direct["S"]) and torch.equal(t.U, direct["U"]) and torch.equal(t.Vt, direct["Vt"])
+    assert srv.graph_stats() == (0, 0, 0)
+    srv.close()
+
+
 def test_graph_bucket_spans_shapes(R):
     """Requests of different m, n and k with the same l rounded to 16, q and
     split pattern share one bucket: after the first, each updates the slot's
     graph, and every result equals the direct solve."""
     srv = R.Server("cuda:0", hbm_budget_bytes=1 << 30, n_streams=1)
+    srv.use_graphs(True)
     shapes = [(4096, 3000, 40), (4000, 3500, 45), (3900, 2900, 38), (4096, 4096, 44)]
     for i, (m, n, k) in enumerate(shapes):
         A = torch.randn(m, n, device="cuda")
@@ -224,7 +251,7 @@ def test_graph_bucket_spans_shapes(R):
         t.wait()
         torch.cuda.synchronize()
         assert torch.equal(t.S, direct["S"]) and torch.equal(t.U, direct["U"]) and torch.equal(t.Vt, direct["Vt"])
-    launches, inst = srv.graph_stats()
+    launches, inst, _ = srv.graph_stats()
     assert launches == len(shapes) and inst < launches
     srv.close()
 
