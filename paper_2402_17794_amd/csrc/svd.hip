@@ -39,10 +39,6 @@ __device__ __forceinline__ double octet_sum(double x) {
 // Reciprocal and reciprocal square root: the hardware estimates refined by
 // Newton steps (each squares the relative error), to full FP64 accuracy
 // for normal arguments without the rescaling of the library forms.
-__device__ __forceinline__ double rcp_newton1(double x) {
-    const double y = __builtin_amdgcn_rcp(x);
-    return fma(y, fma(-x, y, 1.0), y);
-}
 __device__ __forceinline__ double rcp_newton(double x) {
     double y = __builtin_amdgcn_rcp(x);
     y = fma(y, fma(-x, y, 1.0), y);
@@ -56,17 +52,19 @@ __device__ __forceinline__ double rsq_newton(double x) {
 }
 
 // Tangent t of the Jacobi rotation for a column pair with squared norms a, b
-// and inner product g: zeta = (b - a) / 2g, t = sign(zeta) / (|zeta| +
-// sqrt(1 + zeta^2)), which makes the rotated pair orthogonal.  t = 0 (and
-// `rot` untouched) when |g| <= tol sqrt(a b), the pair already orthogonal.
+// and inner product g: with d = b - a, e = 2g and r = (d^2 + e^2)^(1/2),
+// t = sign(d) e / (|d| + r), the root of smaller magnitude of
+// g t^2 + (b - a) t - g = 0, which makes the rotated pair orthogonal.  The
+// form has no quotient that can overflow (the columns are scaled so that
+// a, b <= 1, hence |d|, |e| <= 2) and no branch.  t = 0 (and `rot`
+// untouched) when |g| <= tol sqrt(a b), the pair already orthogonal.
 __device__ __forceinline__ double jacobi_tan(double a, double b, double g, int& rot) {
     const bool r = g * g > (kJacobiTol * kJacobiTol) * (a * b);
     rot |= (int)r;
-    const double q = (b - a) * rcp_newton1(2.0 * (r ? g : 1.0));
-    const double aq = fabs(q);
-    const double h = fma(aq, aq, 1.0);
-    const double t = aq > 1e15 ? 0.5 * rcp_newton1(aq) : rcp_newton(aq + h * rsq_newton(h));
-    return r ? (q >= 0.0 ? t : -t) : 0.0;
+    const double d = b - a, e = 2.0 * g;
+    const double s2 = fma(d, d, e * e);
+    const double t = (d >= 0.0 ? e : -e) * rcp_newton(fma(s2, rsq_newton(s2), fabs(d)));
+    return r ? t : 0.0;
 }
 
 // A column of X as held by jacobi_oe_kernel: the true column is sc times the
@@ -132,18 +130,22 @@ __device__ __forceinline__ void jacobi_rank(const double* nrm2, int* rank_of, in
 // columns meets exactly once (the sequence is reversed, one adjacent swap
 // per pair).
 //
-// A group of 8 lanes holds positions 2g and 2g + 1, lane e rows e + 8k (k <
-// R, rows >= l zero).  Even rounds are group-local: three DPP lane sums and
-// no memory traffic.  Odd rounds pair the group's second column with the
-// next group's first: both groups write their two columns to LDS, read their
-// neighbours', and each group computes the cross pair's rotation itself
-// (same inputs, same instructions, so both get the same rotation) and keeps
-// its own output column.  Two barriers per two rounds; 7 wavefronts at l =
-// 110, one pair per group.
+// A group of 8 lanes holds four consecutive positions 4g .. 4g + 3, lane e
+// rows e + 8k (k < R, rows >= l zero); positions are padded to a multiple of
+// 4 with zero columns, which never rotate.  Even rounds pair (4g, 4g + 1) and
+// (4g + 2, 4g + 3), odd rounds (4g + 1, 4g + 2) inside the group and
+// (4g + 3, 4g + 4) across neighbouring groups: group-local pairs need three
+// DPP lane sums and no memory traffic, and only a group's first and last
+// column go through LDS, once per two rounds.  Both groups of a cross pair
+// compute its rotation (same inputs, same instructions, so both get the same
+// rotation) and each keeps its own output column; the group-local middle
+// pair is rotated while the neighbours' columns arrive.  The exchange
+// alternates between two LDS buffers, so one barrier per two rounds orders
+// it.  At l = 110: 28 groups on 4 wavefronts, one per SIMD.
 //
 // The odd round has no branches: a group at either end of the row pairs its
-// column with itself through LDS with a zero inner product, which makes the
-// rotation the identity (t = 0) and the update y' = 0 * y + y.
+// end column with itself through LDS, with the inner product scaled by 0,
+// which makes the rotation the identity (t = 0) and the update y' = 0 * y + y.
 //
 // Columns carry scales (JColumn), so a rotation costs one FMA per element
 // and output; at the start of every sweep the scales are folded back in and
@@ -163,88 +165,112 @@ struct JBatch {
 };
 
 template <int R>
-__global__ __launch_bounds__(512) void jacobi_oe_kernel(const double* __restrict__ Rm, int l, int L,
+__global__ __launch_bounds__(256) void jacobi_oe_kernel(const double* __restrict__ Rm, int l, int L,
                                                         const double* __restrict__ shift_p,
                                                         double* __restrict__ sigma, double* __restrict__ Ut,
                                                         double* __restrict__ Mv, DevFlags* flags, int max_sweeps,
                                                         JBatch bs) {
-    constexpr int LPP = 8, GMAX = kJacobiRegMax / 2;
+    constexpr int LPP = 8, QMAX = kJacobiRegMax / 4;
     Rm += blockIdx.x * bs.r;
     shift_p += blockIdx.x;
     sigma += blockIdx.x * bs.s;
     Ut += blockIdx.x * bs.o;
     Mv += blockIdx.x * bs.o;
-    constexpr int BUF = 2 * R * GMAX * LPP;                 // exchange buffer [side][k][group][lane]
+    // [side][k][group][lane]: the four columns of each group for the test of
+    // all pairs, or two exchange buffers of two sides (first column, last
+    // column) for the rounds.
+    constexpr int BUF = 4 * R * QMAX * LPP;
     static_assert(LPP * R <= kJacobiRegMax, "rows per column");
     __shared__ double xch[BUF];
-    __shared__ JColumn xcol[2][GMAX];
+    __shared__ JColumn xcol[4][QMAX];
     __shared__ double nrm2[kJacobiRegMax];
     __shared__ int rank_of[kJacobiRegMax];
     const int tid = threadIdx.x, gi = tid / LPP, e = tid % LPP;
-    const int n2 = (l + 1) & ~1, G = n2 / 2;
+    const int n4 = (l + 3) & ~3, G = n4 / 4;
     const bool active = gi < G;
     const bool hasR = gi < G - 1, hasL = active && gi > 0;
-    auto xidx = [&](int side, int k, int g) { return ((side * R + k) * GMAX + g) * LPP + e; };
+    auto xidx = [&](int side, int k, int g) { return ((side * R + k) * QMAX + g) * LPP + e; };
 
-    double x0[R], x1[R];
-    JColumn c0, c1;
-    c0.id = 2 * gi;
-    c1.id = 2 * gi + 1;
+    double x[4][R];
+    JColumn c[4];
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
-        const int r = e + LPP * k;
-        x0[k] = (active && 2 * gi < l && r < l) ? Rm[(int64_t)(2 * gi) * L + r] : 0.0;
-        x1[k] = (active && 2 * gi + 1 < l && r < l) ? Rm[(int64_t)(2 * gi + 1) * L + r] : 0.0;
+    for (int s = 0; s < 4; ++s) {
+        const int col = 4 * gi + s;
+        c[s].id = col;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int r = e + LPP * k;
+            x[s][k] = (active && col < l && r < l) ? Rm[(int64_t)col * L + r] : 0.0;
+        }
     }
     for (int i = tid; i < kJacobiRegMax; i += blockDim.x) nrm2[i] = 0.0;
     __syncthreads();
     {
-        const double s0 = octet_sum(partial_dot<R>(x0, x0)), s1 = octet_sum(partial_dot<R>(x1, x1));
+        double sq[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) sq[s] = octet_sum(partial_dot<R>(x[s], x[s]));
         if (active && e == 0) {
-            nrm2[2 * gi] = s0;
-            nrm2[2 * gi + 1] = s1;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) nrm2[4 * gi + s] = sq[s];
         }
     }
     __syncthreads();
     double mx = 0.0;
-    for (int i = 0; i < n2; ++i) mx = fmax(mx, nrm2[i]);
+    for (int i = 0; i < n4; ++i) mx = fmax(mx, nrm2[i]);
     const int ex = mx > 0.0 ? ilogb(mx) / 2 : 0;
-    c0.sc = c1.sc = ldexp(1.0, -ex);
-    c0.isc = c1.isc = 1.0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        c[s].sc = ldexp(1.0, -ex);
+        c[s].isc = 1.0;
+    }
 
     const int nwaves = (int)(blockDim.x / 64), wave = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
-    // An end group pairs with itself: it reads back its own other column.
+    // An end group pairs its end column with itself: it reads back its own.
     const int sr = hasR ? 0 : 1, gr = hasR ? gi + 1 : gi;
     const int sl = hasL ? 1 : 0, gl = hasL ? gi - 1 : gi;
     bool converged = (l < 2), small = false;
     int sweeps_run = 0;
-    for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
+    int rot = 0, big = 0;
+    // Rotation of the group-local pair at positions (p, p + 1); position p
+    // takes the rotated second column.
+    auto local = [&](double (&xa)[R], double (&xb)[R], JColumn& ca, JColumn& cb) {
+        const double g = octet_sum(partial_dot<R>(xa, xb)) * (ca.sc * cb.sc);
+        const double t = jacobi_tan(ca.nr, cb.nr, g, rot);
+        big |= (int)(fabs(t) > 0x1.0p-20);
+        const JRot o = jacobi_rot(ca, cb, g, t);
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            x0[k] *= c0.sc;
-            x1[k] *= c1.sc;
+            const double yi = xa[k], yj = xb[k];
+            xa[k] = fma(o.tir, yi, yj);
+            xb[k] = fma(-o.tr, yj, yi);
         }
-        c0.sc = c1.sc = c0.isc = c1.isc = 1.0;
-        {
-            const double p0 = partial_dot<R>(x0, x0), p1 = partial_dot<R>(x1, x1);
-            c0.nr = octet_sum(p0);
-            c1.nr = octet_sum(p1);
+        ca = o.cj;
+        cb = o.ci;
+    };
+    for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+#pragma unroll
+            for (int k = 0; k < R; ++k) x[s][k] *= c[s].sc;
+            c[s].sc = c[s].isc = 1.0;
         }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) c[s].nr = octet_sum(partial_dot<R>(x[s], x[s]));
         if (small) {
             // Test of every pair of columns: G = X^T X, 16 x 16 tiles on and
             // above the diagonal, against |g| <= tol sqrt(a b) with the norms
             // of this sweep start.
 #pragma unroll
-            for (int k = 0; k < R; ++k) {
-                xch[xidx(0, k, gi)] = x0[k];
-                xch[xidx(1, k, gi)] = x1[k];
+            for (int s = 0; s < 4; ++s) {
+#pragma unroll
+                for (int k = 0; k < R; ++k) xch[xidx(s, k, gi)] = x[s][k];
             }
             if (e == 0) {
-                nrm2[2 * gi] = c0.nr;
-                nrm2[2 * gi + 1] = c1.nr;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) nrm2[4 * gi + s] = c[s].nr;
             }
             __syncthreads();
-            const int ntc = (n2 + 15) / 16, ntiles = ntc * (ntc + 1) / 2;
+            const int ntc = (n4 + 15) / 16, ntiles = ntc * (ntc + 1) / 2;
             int bad = 0;
             for (int t = wave; t < ntiles; t += nwaves) {
                 int a = 0, b = t;
@@ -256,14 +282,14 @@ __global__ __launch_bounds__(512) void jacobi_oe_kernel(const double* __restrict
                 for (int kk = 0; kk < LPP * R; kk += 4) {
                     const int row = kk + lk;       // row = e' + 8 k'
                     const int k = row / LPP, ee = row % LPP;
-                    const double av = xch[(((pa & 1) * R + k) * GMAX + (pa >> 1)) * LPP + ee];
-                    const double bv = xch[(((pb & 1) * R + k) * GMAX + (pb >> 1)) * LPP + ee];
+                    const double av = xch[(((pa & 3) * R + k) * QMAX + (pa >> 2)) * LPP + ee];
+                    const double bv = xch[(((pb & 3) * R + k) * QMAX + (pb >> 2)) * LPP + ee];
                     acc = mfma16x16x4(av, bv, acc);
                 }
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int i = 16 * a + acc_row<double>(lk, v), j = pb;
-                    if (i < j && j < n2) bad |= (int)(acc[v] * acc[v] > (kJacobiTol * kJacobiTol) * (nrm2[i] * nrm2[j]));
+                    if (i < j && j < n4) bad |= (int)(acc[v] * acc[v] > (kJacobiTol * kJacobiTol) * (nrm2[i] * nrm2[j]));
                 }
             }
             if (!__syncthreads_or(bad)) {
@@ -272,58 +298,50 @@ __global__ __launch_bounds__(512) void jacobi_oe_kernel(const double* __restrict
             }
         }
         ++sweeps_run;
-        int rot = 0, big = 0;
-        for (int h = 0; h < G; ++h) {
-            {   // even round: pair (2g, 2g + 1); position 2g takes the rotated second column
-                const double g = octet_sum(partial_dot<R>(x0, x1)) * (c0.sc * c1.sc);
-                const double t = jacobi_tan(c0.nr, c1.nr, g, rot);
-                big |= (int)(fabs(t) > 0x1.0p-20);
-                const JRot o = jacobi_rot(c0, c1, g, t);
-#pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    const double yi = x0[k], yj = x1[k];
-                    x0[k] = fma(o.tir, yi, yj);
-                    x1[k] = fma(-o.tr, yj, yi);
-                }
-                c0 = o.cj;
-                c1 = o.ci;
-            }
-            // odd round: pairs (2g + 1, 2g + 2) across neighbouring groups
+        rot = 0;
+        big = 0;
+        for (int h = 0; h < 2 * G; ++h) {
+            // even round: both pairs group-local
+            local(x[0], x[1], c[0], c[1]);
+            local(x[2], x[3], c[2], c[3]);
+            // odd round: publish the end columns, rotate the middle pair, then
+            // the two cross pairs
+            const int b0 = 2 * (h & 1);
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                xch[xidx(0, k, gi)] = x0[k];
-                xch[xidx(1, k, gi)] = x1[k];
+                xch[xidx(b0, k, gi)] = x[0][k];
+                xch[xidx(b0 + 1, k, gi)] = x[3][k];
             }
             if (e == 0) {
-                xcol[0][gi] = c0;
-                xcol[1][gi] = c1;
+                xcol[b0][gi] = c[0];
+                xcol[b0 + 1][gi] = c[3];
             }
             __syncthreads();
             double yr[R], yl[R];
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                yr[k] = xch[xidx(sr, k, gr)];
-                yl[k] = xch[xidx(sl, k, gl)];
+                yr[k] = xch[xidx(b0 + sr, k, gr)];
+                yl[k] = xch[xidx(b0 + sl, k, gl)];
             }
-            const JColumn cr = xcol[sr][gr], cl = xcol[sl][gl];
-            __syncthreads();
-            const double pr = partial_dot<R>(x1, yr), pl = partial_dot<R>(yl, x0);
-            const double gR = hasR ? octet_sum(pr) * (c1.sc * cr.sc) : 0.0;
-            const double gL = hasL ? octet_sum(pl) * (cl.sc * c0.sc) : 0.0;
-            const double tR = jacobi_tan(c1.nr, cr.nr, gR, rot);
-            const double tL = jacobi_tan(cl.nr, c0.nr, gL, rot);
+            const JColumn cr = xcol[b0 + sr][gr], cl = xcol[b0 + sl][gl];
+            local(x[1], x[2], c[1], c[2]);
+            const double pr = partial_dot<R>(x[3], yr), pl = partial_dot<R>(yl, x[0]);
+            const double gR = octet_sum(pr) * (hasR ? c[3].sc * cr.sc : 0.0);
+            const double gL = octet_sum(pl) * (hasL ? cl.sc * c[0].sc : 0.0);
+            const double tR = jacobi_tan(c[3].nr, cr.nr, gR, rot);
+            const double tL = jacobi_tan(cl.nr, c[0].nr, gL, rot);
             big |= (int)(fmax(fabs(tR), fabs(tL)) > 0x1.0p-20);
-            const JRot oR = jacobi_rot(c1, cr, gR, tR);
-            const JRot oL = jacobi_rot(cl, c0, gL, tL);
-            // Position 2g + 1 takes the rotated right neighbour, position 2g
+            const JRot oR = jacobi_rot(c[3], cr, gR, tR);
+            const JRot oL = jacobi_rot(cl, c[0], gL, tL);
+            // Position 4g + 3 takes the rotated right neighbour, position 4g
             // the rotated left one (at an end: the column itself, t = 0).
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                x1[k] = fma(oR.tir, x1[k], yr[k]);
-                x0[k] = fma(-oL.tr, x0[k], yl[k]);
+                x[3][k] = fma(oR.tir, x[3][k], yr[k]);
+                x[0][k] = fma(-oL.tr, x[0][k], yl[k]);
             }
-            c1 = oR.cj;
-            c0 = oL.ci;
+            c[3] = oR.cj;
+            c[0] = oL.ci;
         }
         converged = !__syncthreads_or(rot);
         small = !__syncthreads_or(big);
@@ -332,16 +350,19 @@ __global__ __launch_bounds__(512) void jacobi_oe_kernel(const double* __restrict
     if (tid == 0) atomicMax(&flags->jacobi_sweeps, sweeps_run);
 
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
-        x0[k] *= c0.sc;
-        x1[k] *= c1.sc;
+    for (int s = 0; s < 4; ++s) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) x[s][k] *= c[s].sc;
     }
     __syncthreads();
     {
-        const double s0 = octet_sum(partial_dot<R>(x0, x0)), s1 = octet_sum(partial_dot<R>(x1, x1));
+        double sq[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) sq[s] = octet_sum(partial_dot<R>(x[s], x[s]));
         if (active && e == 0) {
-            if (c0.id < l) nrm2[c0.id] = s0;
-            if (c1.id < l) nrm2[c1.id] = s1;
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                if (c[s].id < l) nrm2[c[s].id] = sq[s];
         }
     }
     __syncthreads();
@@ -354,20 +375,20 @@ __global__ __launch_bounds__(512) void jacobi_oe_kernel(const double* __restrict
     __syncthreads();
     if (active) {
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int c = q ? c1.id : c0.id;
-            if (c >= l) continue;
-            const double nc = sqrt(nrm2[c]);
-            const double sc = sqrt(fmax(nrm2[c] * sc4 - shift, 0.0));
+        for (int q = 0; q < 4; ++q) {
+            const int cid = c[q].id;
+            if (cid >= l) continue;
+            const double nc = sqrt(nrm2[cid]);
+            const double sv = sqrt(fmax(nrm2[cid] * sc4 - shift, 0.0));
             const double inv = nc > 0.0 ? 1.0 / nc : 0.0;
-            const int col = rank_of[c];
+            const int col = rank_of[cid];
 #pragma unroll
             for (int k = 0; k < R; ++k) {
                 const int r = e + LPP * k;
                 if (r < l) {
-                    const double u = nc > 0.0 ? (q ? x1[k] : x0[k]) * inv : (r == c ? 1.0 : 0.0);
+                    const double u = nc > 0.0 ? x[q][k] * inv : (r == cid ? 1.0 : 0.0);
                     Ut[(int64_t)r * L + col] = u;
-                    Mv[(int64_t)r * L + col] = sc > 0.0 ? u / sc : 0.0;
+                    Mv[(int64_t)r * L + col] = sv > 0.0 ? u / sv : 0.0;
                 }
             }
         }
@@ -391,7 +412,7 @@ __device__ __forceinline__ void rr_pair(int r, int s, int n2, int& p1, int& p2) 
 // launch in which every workgroup takes one pair of blocks, loads its 32
 // columns into registers (16 lanes per column pair, rows e + 16 k), runs one
 // odd-even transposition sweep over them (every pair of the 32 columns meets
-// once, exactly as in jacobi_oe_kernel) and writes them back.  The launches
+// once, the ordering of jacobi_oe_kernel) and writes them back.  The launches
 // of a sweep together meet every pair of columns at least once; the kernel
 // boundaries order the rounds, so no workgroup waits for another.  A word per
 // sweep records whether any pair rotated; the launches of a sweep return at
@@ -577,7 +598,7 @@ static void launch_jacobi_blk(const double* Rm, int l, int L, const double* shif
 template <int R>
 static void launch_jacobi_oe(const double* Rm, int l, int L, const double* shift, double* sigma, double* Ut,
                              double* Mv, DevFlags* flags, hipStream_t s, int sweeps, int batch, JBatch bs) {
-    const int groups = ((l + 1) & ~1) / 2;
+    const int groups = ((l + 3) & ~3) / 4;
     const int threads = (int)round_up(groups * 8, kWave);
     hipLaunchKernelGGL(jacobi_oe_kernel<R>, dim3(batch), dim3(threads), 0, s, Rm, l, L, shift, sigma, Ut, Mv, flags,
                        sweeps, bs);
