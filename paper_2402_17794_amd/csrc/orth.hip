@@ -140,14 +140,6 @@ constexpr int kCholLdsMax = 128;
 constexpr int kCholBlkNt = kMaxL / 16;
 constexpr int kCholBlkLd = kMaxL + 4;          // LDS panel row stride (doubles)
 
-__device__ __forceinline__ double lane_bcast(double x, int src) {      // x of lane `src` (uniform), in every lane
-    const int2 v = __builtin_bit_cast(int2, x);
-    int2 r;
-    r.x = __builtin_amdgcn_readlane(v.x, src);
-    r.y = __builtin_amdgcn_readlane(v.y, src);
-    return __builtin_bit_cast(double, r);
-}
-
 // 1 / sqrt(x) for a positive normal x: the hardware estimate and two Newton
 // steps (each squares the relative error), about one ulp.
 __device__ __forceinline__ double rsqrt_nr(double x) {
@@ -155,6 +147,82 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 #pragma unroll
     for (int i = 0; i < 2; ++i) y = fma(0.5 * y, fma(-(x * y), y, 1.0), y);
     return y;
+}
+
+// Cholesky of a 16 x 16 diagonal tile T of the augmented matrix [T | I] by
+// one wavefront: lane = 16 q + c holds rows 4q .. 4q + 3 of column c of T
+// (xg, upper triangle) and of the identity (xi), which the same row
+// operations turn into R^{-T}.  Pivot j subtracts T[j][i] T[j][c] / d_j from
+// entry (i, c) of every row i > j and then scales row j by d_j^{-1/2}.  Row j
+// (its 32 entries, written by the lanes that hold it) reaches every lane
+// through LDS: each lane reads the pivot, its own column's entries and its
+// four rows' entries.  A wavefront's LDS operations complete in issue order,
+// so the reads see the writes; the wave barrier only keeps the compiler from
+// moving them.  rowbuf: 16 x 32 doubles, 16-byte aligned.  The pivots are
+// tested on the way, without a branch on the chain (a bad pivot only spoils
+// the steps after it): the result is true when pivot j < nvalid is not
+// positive, not finite or not above rel (dgj[j] + shift) (dgj: the diagonal
+// of G from the tile's first index).
+__device__ __forceinline__ bool chol_tile16(double (&xg)[4], double (&xi)[4], double* rowbuf, const double* dgj,
+                                            int nvalid, double rel, double shift) {
+    const int lane = threadIdx.x & 63, c = lane & 15, q = lane >> 4;
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        double* const rj = rowbuf + 32 * j;
+        const bool holds = q == (j >> 2);               // this lane holds row j (entry j & 3)
+        if (holds) {
+            rj[c] = xg[j & 3];
+            rj[16 + c] = xi[j & 3];
+        }
+        __builtin_amdgcn_wave_barrier();
+        const double d = rj[j];
+        const double2 t01 = *reinterpret_cast<const double2*>(rj + 4 * q);
+        const double2 t23 = *reinterpret_cast<const double2*>(rj + 4 * q + 2);
+        const double wg = rj[c], wi = rj[16 + c];
+        if (j < nvalid) bad |= !(d > rel * (dgj[j] + shift)) || !(d > 0.0) || !isfinite(d);
+        const double rs = rsqrt_nr(d), rd = rs * rs;
+        const double ti[4] = {t01.x, t01.y, t23.x, t23.y};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const double f = (4 * q + m > j) ? ti[m] * rd : 0.0;
+            xg[m] = fma(-f, wg, xg[m]);
+            xi[m] = fma(-f, wi, xi[m]);
+        }
+        const double sc = holds ? rs : 1.0;
+        xg[j & 3] *= sc;
+        xi[j & 3] *= sc;
+    }
+    return bad;
+}
+
+// The same factorisation with the row entries broadcast by lane reads (lane c
+// < 16: column c of T in x, lane 16 + c: column c of the identity; scale row
+// j by d_j^{-1/2}, subtract R[j][i] times it from every row i > j).  It needs
+// fewer vector registers than chol_tile16, which the 1024-thread block form
+// cannot spare.
+__device__ __forceinline__ double lane_bcast(double x, int src) {      // x of lane `src` (uniform), in every lane
+    const int2 v = __builtin_bit_cast(int2, x);
+    int2 r;
+    r.x = __builtin_amdgcn_readlane(v.x, src);
+    r.y = __builtin_amdgcn_readlane(v.y, src);
+    return __builtin_bit_cast(double, r);
+}
+__device__ __forceinline__ bool chol_tile16_lanes(double (&x)[16], const double* dgj, int nvalid, double rel,
+                                                  double shift) {
+    double dj[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        dj[j] = lane_bcast(x[j], j);
+        x[j] *= rsqrt_nr(dj[j]);
+#pragma unroll
+        for (int i = j + 1; i < 16; ++i) x[i] = fma(-lane_bcast(x[j], i), x[j], x[i]);
+    }
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+        if (j < nvalid) bad |= !(dj[j] > rel * (dgj[j] + shift)) || !(dj[j] > 0.0) || !isfinite(dj[j]);
+    return bad;
 }
 
 // End of a Cholesky kernel (modes 0, 1): the orth flags, and in mode 0 the
@@ -278,8 +346,6 @@ __global__ __launch_bounds__(1024) void chol_blk_kernel(const double* __restrict
         return;
     }
     const bool nonfinite = s_nonfinite != 0;
-    double gmax = 0.0;
-    for (int j = 0; j < l; ++j) gmax = fmax(gmax, dg[j]);
     const double rel = (mode == 0) ? 1e-12 : (mode == 1 ? 1e-2 : 0.0);
     double shift = 0.0;
     bool broke = nonfinite;
@@ -293,29 +359,15 @@ __global__ __launch_bounds__(1024) void chol_blk_kernel(const double* __restrict
         for (int p = 0; p < nt; ++p) {
             const int j0 = 16 * p;
             if (wid == 0) {
-                // 1. Diagonal block in registers, lane = column of [A_pp | I]:
-                // pivot j scales row j by d_j^{-1/2} and subtracts R_pp[j][i]
-                // times it from every row i > j, the row entries broadcast by
-                // lane reads; the identity half becomes R_pp^{-T}.  The pivots
-                // are tested afterwards (a bad pivot only spoils later steps).
+                // 1. Diagonal block in registers, lane = column of [A_pp | I]
+                // (chol_tile16_lanes); the identity half becomes R_pp^{-T}.
                 const int c = lane & 15;
                 double x[16];
 #pragma unroll
                 for (int r = 0; r < 16; ++r)
                     x[r] = lane < 16 ? (r <= c ? A[(size_t)(j0 + r) * L + j0 + c] : 0.0)
                                      : (lane < 32 && r == c ? 1.0 : 0.0);
-                double dj[16];
-#pragma unroll
-                for (int j = 0; j < 16; ++j) {
-                    dj[j] = lane_bcast(x[j], j);
-                    x[j] *= rsqrt_nr(dj[j]);
-#pragma unroll
-                    for (int i = j + 1; i < 16; ++i) x[i] = fma(-lane_bcast(x[j], i), x[j], x[i]);
-                }
-                bool bad = false;
-#pragma unroll
-                for (int j = 0; j < 16; ++j)
-                    if (j0 + j < l) bad |= !(dj[j] > rel * (dg[j0 + j] + shift)) || !(dj[j] > 0.0) || !isfinite(dj[j]);
+                const bool bad = chol_tile16_lanes(x, dg + j0, l - j0, rel, shift);
                 if (!bad) {
                     if (lane < 16) {        // R_pp (upper) back into A for the mode-2 output
 #pragma unroll
@@ -368,6 +420,8 @@ __global__ __launch_bounds__(1024) void chol_blk_kernel(const double* __restrict
         }
         broke = s_broke != 0;
         if (!broke || mode != 2) break;
+        double gmax = 0.0;                // largest diagonal entry (only on a retry)
+        for (int j = 0; j < l; ++j) gmax = fmax(gmax, dg[j]);
         shift = (shift == 0.0) ? gmax * 0x1.0p-40 : shift * 1024.0;
         if (!(shift > 0.0)) shift = 0x1.0p-1000;
     }
@@ -536,8 +590,6 @@ __global__ __launch_bounds__(kCholThreads) void chol_rl_kernel(const double* __r
         return;
     }
     const bool nonfinite = s_nonfinite != 0;
-    double gmax = 0.0;
-    for (int j = 0; j < l; ++j) gmax = fmax(gmax, dg[j]);
     const double rel = (mode == 0) ? 1e-12 : (mode == 1 ? 1e-2 : 0.0);
     // Where this tile publishes its rows: base + a * pst + b.
     const bool rdiag = !left && bi == bj;
@@ -611,6 +663,8 @@ __global__ __launch_bounds__(kCholThreads) void chol_rl_kernel(const double* __r
             }
         }
         if (!broke || mode != 2) break;
+        double gmax = 0.0;                // largest diagonal entry (only on a retry)
+        for (int j = 0; j < l; ++j) gmax = fmax(gmax, dg[j]);
         shift = (shift == 0.0) ? gmax * 0x1.0p-40 : shift * 1024.0;
         if (!(shift > 0.0)) shift = 0x1.0p-1000;
     }
@@ -674,6 +728,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_mfma_kernel(const double* _
     __shared__ double Gt[NTT * kTileSz];        // left tiles (a, b), a <= b
     __shared__ double Mt[NTT * kTileSz];        // right tiles (q, c), c <= q
     __shared__ double dg[16 * kCholMfmaMaxNt];
+    __shared__ __align__(16) double rowbuf[16 * 32];  // pivot rows of a diagonal tile
     __shared__ double red[kCholThreads / 64];
     __shared__ unsigned long long s_emax;
     __shared__ int s_nonfinite, s_broke;
@@ -738,21 +793,19 @@ __global__ __launch_bounds__(kCholThreads) void chol_mfma_kernel(const double* _
     __syncthreads();
     if (mode == 1 && __longlong_as_double((long long)s_emax) <= tau) {
         // Second pass: first-order factor R^{-1} = I - U, U = triu(E) - diag(E) / 2.
-        for (int idx = tid; idx < L * L; idx += kCholThreads) {
-            const int x = idx / L, y = idx - x * L;
-            double ri = 0.0;
-            if (x <= y && y < l) {
-                const double e = gt(x >> 4, y >> 4)[(x & 15) * kTileLd + (y & 15)] - (x == y ? 1.0 : 0.0);
-                ri = (x == y ? 1.0 : 0.0) - (x < y ? e : 0.5 * e);
+        for (int x = wid; x < L; x += nw)
+            for (int y = lane; y < L; y += 64) {
+                double ri = 0.0;
+                if (x <= y && y < l) {
+                    const double e = gt(x >> 4, y >> 4)[(x & 15) * kTileLd + (y & 15)] - (x == y ? 1.0 : 0.0);
+                    ri = (x == y ? 1.0 : 0.0) - (x < y ? e : 0.5 * e);
+                }
+                Rinv[x * L + y] = ri;
             }
-            Rinv[idx] = ri;
-        }
         if (tid == 0) flags->orth_fail = 0;
         return;
     }
     const bool nonfinite = s_nonfinite != 0;
-    double gmax = 0.0;
-    for (int j = 0; j < l; ++j) gmax = fmax(gmax, dg[j]);
     const double rel = (mode == 0) ? 1e-12 : (mode == 1 ? 1e-2 : 0.0);
     const bool inv = mode != 2;                 // R^{-1} wanted: the whole right half
     double shift = 0.0;
@@ -766,40 +819,25 @@ __global__ __launch_bounds__(kCholThreads) void chol_mfma_kernel(const double* _
             for (int idx = tid; idx < NTT * kTileSz; idx += kCholThreads) Mt[idx] = 0.0;
         if (tid == 0) s_broke = 0;
         __syncthreads();
-        // 1. Diagonal tile p in registers (wavefront 0), lane = column of [G_pp | I].
+        // 1. Diagonal tile p of [G_pp | I] in registers (wavefront 0,
+        // chol_tile16): a bad pivot only spoils the steps after it, which
+        // are then discarded.
         auto factor_diag = [&](int p) {
             double* const T = gt(p, p);
-            const int c = lane & 15;
-            double x[16];
+            const int c = lane & 15, r0 = 4 * (lane >> 4);
+            double xg[4], xi[4];
 #pragma unroll
-            for (int r = 0; r < 16; ++r)
-                x[r] = lane < 16 ? (r <= c ? T[r * kTileLd + c] : 0.0) : (lane < 32 && r == c ? 1.0 : 0.0);
-            // Straight-line elimination; the pivots are tested afterwards
-            // (a bad pivot only spoils the steps after it, which are then
-            // discarded), so no branch sits on the chain from one pivot
-            // to the next.
-            double dj[16];
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                dj[j] = lane_bcast(x[j], j);                 // same value in every lane
-                x[j] *= rsqrt_nr(dj[j]);
-#pragma unroll
-                for (int i = j + 1; i < 16; ++i) x[i] = fma(-lane_bcast(x[j], i), x[j], x[i]);
+            for (int m = 0; m < 4; ++m) {
+                xg[m] = r0 + m <= c ? T[(r0 + m) * kTileLd + c] : 0.0;
+                xi[m] = r0 + m == c ? 1.0 : 0.0;
             }
-            bool bad = false;
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const int gj = 16 * p + j;
-                if (gj < l) bad |= !(dj[j] > rel * (dg[gj] + shift)) || !(dj[j] > 0.0) || !isfinite(dj[j]);
-            }
+            const bool bad = chol_tile16(xg, xi, rowbuf, dg + 16 * p, l - 16 * p, rel, shift);
             if (!bad) {
-                if (lane < 16) {
+                double* const D = mt(p, p);
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) T[r * kTileLd + c] = r <= c ? x[r] : 0.0;
-                } else if (lane < 32) {
-                    double* const D = mt(p, p);
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) D[r * kTileLd + c] = x[r];
+                for (int m = 0; m < 4; ++m) {
+                    T[(r0 + m) * kTileLd + c] = r0 + m <= c ? xg[m] : 0.0;
+                    D[(r0 + m) * kTileLd + c] = xi[m];
                 }
             } else if (lane == 0) {
                 s_broke = 1;
@@ -860,20 +898,24 @@ __global__ __launch_bounds__(kCholThreads) void chol_mfma_kernel(const double* _
         }
         broke = s_broke != 0;
         if (!broke || mode != 2) break;
+        double gmax = 0.0;                // largest diagonal entry (only on a retry)
+        for (int j = 0; j < l; ++j) gmax = fmax(gmax, dg[j]);
         shift = (shift == 0.0) ? gmax * 0x1.0p-40 : shift * 1024.0;
         if (!(shift > 0.0)) shift = 0x1.0p-1000;
     }
     double ssum = 0.0;                          // sum of G_ii Rinv_ij^2 over this thread's entries
     if (!broke) {
-        for (int idx = tid; idx < L * L; idx += kCholThreads) {
-            const int x = idx / L, y = idx - x * L;
-            const bool in = x <= y && y < l;
-            if (mode == 2) {
-                R[idx] = in ? gt(x >> 4, y >> 4)[(x & 15) * kTileLd + (y & 15)] : 0.0;
-            } else {
-                const double v = in ? mt(y >> 4, x >> 4)[(y & 15) * kTileLd + (x & 15)] : 0.0;
-                Rinv[idx] = v;
-                if (in) ssum = fma(dg[x] * v, v, ssum);
+        for (int x = wid; x < L; x += nw) {
+            const double dgx = x < l ? dg[x] : 0.0;
+            for (int y = lane; y < L; y += 64) {
+                const bool in = x <= y && y < l;
+                if (mode == 2) {
+                    R[x * L + y] = in ? gt(x >> 4, y >> 4)[(x & 15) * kTileLd + (y & 15)] : 0.0;
+                } else {
+                    const double v = in ? mt(y >> 4, x >> 4)[(y & 15) * kTileLd + (x & 15)] : 0.0;
+                    Rinv[x * L + y] = v;
+                    ssum = fma(dgx * v, v, ssum);
+                }
             }
         }
     }
