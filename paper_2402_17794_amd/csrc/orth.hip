@@ -953,8 +953,8 @@ hipError_t launch_chol(const double* partials, int64_t rows, int l, int L, doubl
 // workgroup owns 32 rows; wavefront w owns row block w & 1 and the column
 // tiles t = (w >> 1), (w >> 1) + 2, ...  The inner dimension is staged
 // through LDS 16 at a time with a one-slice register prefetch.  With `upper`
-// set, M is upper triangular and the zero blocks below its diagonal are
-// skipped.
+// set, M is upper triangular and this form skips the zero blocks below its
+// diagonal (the LDS form below multiplies them).
 constexpr int kApplyRows = 32;
 int apply_blocks(int64_t rows) { return (int)ceil_div(rows, kApplyRows); }
 
@@ -1127,18 +1127,27 @@ __global__ __launch_bounds__(256) void apply_lds_kernel(const T* in, int64_t ldi
     doublex4 acc[NTW];
 #pragma unroll
     for (int j = 0; j < NTW; ++j) acc[j] = doublex4{0, 0, 0, 0};
+    // Per 16-deep K block, the operand fragments (4 MFMA steps x the wave's
+    // column tiles) are read from LDS together, then the matrix instructions
+    // run back to back.  The loop has no branch: a tile past CT reads a
+    // clamped column and is never stored, and with `upper` the zero blocks of
+    // M below its diagonal are multiplied like the others (at L <= 128,
+    // skipping them per tile put a branch around every matrix instruction,
+    // which then waited for its result before the next: 2.3 times slower).
+    (void)upper;
     for (int a0 = 0; a0 < L; a0 += 16) {
+        double av[4], bv[NTW][4];
 #pragma unroll
-        for (int kk = 0; kk < 16; kk += 4) {
-            const double av_ = inS[(rb + li) * SI + a0 + kk + lk];
+        for (int kk = 0; kk < 4; ++kk) {
+            const int k = a0 + 4 * kk + lk;
+            av[kk] = inS[(rb + li) * SI + k];
 #pragma unroll
-            for (int j = 0; j < NTW; ++j) {
-                const int t = tw + 2 * j;
-                if (t >= CT) continue;
-                if (upper && a0 >= 16 * (t + 1)) continue;
-                acc[j] = mfma16x16x4(av_, MS[(a0 + kk + lk) * SM + 16 * t + li], acc[j]);
-            }
+            for (int j = 0; j < NTW; ++j) bv[j][kk] = MS[k * SM + min(16 * (tw + 2 * j), W - 16) + li];
         }
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int j = 0; j < NTW; ++j) acc[j] = mfma16x16x4(av[kk], bv[j][kk], acc[j]);
     }
     if (amax_val) __syncthreads();                     // the input rows' LDS becomes the argmax scratch
     auto avs = [&](int rr, int col) -> double& { return inS[rr * SM + col]; };
