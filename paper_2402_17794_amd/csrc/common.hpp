@@ -78,4 +78,14 @@ __device__ __forceinline__ double block_sum(double x, double* scratch) {
 __host__ __device__ constexpr int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ constexpr int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 
+// Workgroup ids are dealt round-robin over the 8 XCDs (XCD = id mod 8), each
+// with its own L2.  Block b = xcd_block(id, n) of n blocks gives XCD x the
+// contiguous eighth x of the blocks (when 8 divides n; else b = id), so a
+// chain of row-blocked kernels (split-K reduce, Gram, apply, the next
+// product's slice of its thin operand) reads on each XCD the rows that the
+// XCD wrote, from its own L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t id, int64_t n) {
+    return (n % 8 == 0) ? (id % 8) * (n / 8) + id / 8 : id;
+}
+
 }  // namespace rsvd

@@ -307,7 +307,7 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const T* __restrict_
     using V = typename Vec16<T>::type;
     constexpr int VEC = Vec16<T>::n;
     const int64_t nvec = M * (L / VEC);
-    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t idx = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
     if (idx >= nvec) return;
     const int64_t pstride = M * L;
     V x[SMAX];

@@ -51,8 +51,10 @@ __global__ __launch_bounds__(64 * kGramWaves) void gram_kernel(const T* __restri
     if (skip && *skip) return;
     const int nt = L / 16;
     const int npairs = nt * (nt + 1) / 2;
-    const int pair = blockIdx.x % npairs;
-    const int chunk = blockIdx.x / npairs;
+    // chunk-fastest ids: with 8 chunks each XCD takes one chunk (the rows the
+    // split-K reduce and apply kernels of the same XCD wrote; xcd_block)
+    const int chunk = blockIdx.x % nchunks;
+    const int pair = blockIdx.x / nchunks;
     int a = 0, p = pair;
     while (p >= nt - a) { p -= nt - a; ++a; }
     const int b = a + p;
@@ -974,7 +976,8 @@ __global__ __launch_bounds__(256) void apply_kernel(const T* in, int64_t ldi, in
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int rb = 16 * (wave & 1), tw = wave >> 1;
-    const int64_t row0 = (int64_t)blockIdx.x * kApplyRows;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t row0 = blk * kApplyRows;
     doublex4 acc[NTW];
 #pragma unroll
     for (int j = 0; j < NTW; ++j) acc[j] = doublex4{0, 0, 0, 0};
@@ -1047,8 +1050,8 @@ __global__ __launch_bounds__(256) void apply_kernel(const T* in, int64_t ldi, in
         int bi = 0;
         for (int rr = 0; rr < kApplyRows; ++rr)      // lowest row wins ties
             if (fabs(avs(rr, col)) > best) { best = fabs(avs(rr, col)); val = avs(rr, col); bi = rr; }
-        amax_val[(int64_t)blockIdx.x * ncols_out + col] = val;
-        amax_idx[(int64_t)blockIdx.x * ncols_out + col] = (int)(row0 + bi);
+        amax_val[blk * ncols_out + col] = val;
+        amax_idx[blk * ncols_out + col] = (int)(row0 + bi);
     }
 }
 
@@ -1077,7 +1080,8 @@ __global__ __launch_bounds__(256) void apply_lds_kernel(const T* in, int64_t ldi
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int rb = 16 * (wave & 1), tw = wave >> 1;
-    const int64_t row0 = (int64_t)blockIdx.x * kApplyRows;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t row0 = blk * kApplyRows;
     // Input rows (16-byte vectors of `in`) and M (pairs of doubles), every
     // load of the thread issued before the first store.  L and W are
     // multiples of 16, the leading dimensions multiples of 16 elements and
@@ -1177,8 +1181,8 @@ __global__ __launch_bounds__(256) void apply_lds_kernel(const T* in, int64_t ldi
         int bi = 0;
         for (int rr = 0; rr < kApplyRows; ++rr)      // lowest row wins ties
             if (fabs(avs(rr, col)) > best) { best = fabs(avs(rr, col)); val = avs(rr, col); bi = rr; }
-        amax_val[(int64_t)blockIdx.x * ncols_out + col] = val;
-        amax_idx[(int64_t)blockIdx.x * ncols_out + col] = (int)(row0 + bi);
+        amax_val[blk * ncols_out + col] = val;
+        amax_idx[blk * ncols_out + col] = (int)(row0 + bi);
     }
 }
 
