@@ -310,8 +310,14 @@ __global__ __launch_bounds__(256) void lp_gemm_kernel(LpGemmArgs g) {
     auto store_x = [&](int64_t k0) {
         if constexpr (OMEGA) {
             // Omega'_kj for rows k0 + 4 gi .. + 3 of column j, FP8: diag(s) Omega / t.
-            float inv_t = 1.0f;
-            if (AB == 1) inv_t = 448.0f / (kOmegaBound * g.omega_scale[0]);
+            float inv_t = 1.0f, sk[4] = {0.f, 0.f, 0.f, 0.f};
+            static_assert(256 % (BK / 4) == 0, "a thread keeps its 4 rows of k");
+            if (AB == 1) {
+                inv_t = 448.0f / (kOmegaBound * g.omega_scale[0]);
+                const int64_t r = k0 + 4 * (tid % (BK / 4));
+#pragma unroll
+                for (int e = 0; e < 4; ++e) sk[e] = r + e < kend ? g.col_scale[r + e] : 0.f;
+            }
 #pragma unroll
             for (int it = 0; it < NOB; ++it) {
                 const int idx = tid + 256 * it;
@@ -330,7 +336,7 @@ __global__ __launch_bounds__(256) void lp_gemm_kernel(LpGemmArgs g) {
                         uint32_t w = 0;
 #pragma unroll
                         for (int e = 0; e < 4; ++e) {
-                            const float v = (r + e < kend) ? (g.col_scale[r + e] * z[e]) * inv_t : 0.f;
+                            const float v = (r + e < kend) ? (sk[e] * z[e]) * inv_t : 0.f;
                             w |= (uint32_t)f32_to_e4m3(v) << (8 * e);
                         }
                         *reinterpret_cast<uint32_t*>(dst) = w;

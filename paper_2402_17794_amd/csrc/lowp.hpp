@@ -29,18 +29,20 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float x) {
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// E4M3 with round to nearest even, saturating at +-448, NaN -> 0x7f, without
+// branches: in the normal range (|x| >= 2^-6) the mantissa is rounded to 3
+// bits in the FP32 bit pattern (a carry moves the exponent up), below it the
+// value is q 2^-9 with q = rint(512 |x|) (q = 8 is the smallest normal).
 __device__ __forceinline__ uint8_t f32_to_e4m3(float x) {
     const uint32_t u = __float_as_uint(x);
-    const uint8_t sign = (uint8_t)((u >> 24) & 0x80u);
-    const float a = __uint_as_float(u & 0x7fffffffu);
-    if (!(a == a)) return 0x7f;                                          // NaN
-    if (a >= 448.0f) return sign | 0x7e;                                 // saturate
-    int e = (int)((u >> 23) & 0xffu) - 127;                              // binade of a
-    if (e < -6) return sign | (uint8_t)rintf(a * 512.0f);                // subnormal: q * 2^-9, q <= 8
-    int q = (int)rintf(ldexpf(a, 3 - e));                                // 8 <= q <= 16
-    if (q == 16) { q = 8; ++e; }
-    const int code = ((e + 7) << 3) | (q - 8);
-    return sign | (uint8_t)(code > 0x7e ? 0x7e : code);
+    const uint32_t sign = (u >> 24) & 0x80u;
+    const uint32_t a = u & 0x7fffffffu;
+    const uint32_t rn = a + 0x7ffffu + ((a >> 20) & 1u);
+    const int normal = (int)(rn >> 20) - (120 << 3);          // ((e + 7) << 3) | m
+    const int sub = (int)rintf(__uint_as_float(a) * 512.0f);
+    int code = a >= 0x3c800000u ? normal : sub;               // 2^-6
+    code = code < 0x7e ? code : 0x7e;
+    return a > 0x7f800000u ? (uint8_t)0x7f : (uint8_t)(sign | (uint32_t)code);
 }
 
 __device__ __forceinline__ float e4m3_to_f32(uint8_t b) {
