@@ -65,6 +65,33 @@ def test_quantizers_bit_exact(R, m, n):
     assert np.array_equal(qf.col_scale.cpu().numpy(), s)
 
 
+def test_fp8_rounding_at_every_code_boundary(R):
+    """Columns whose largest entry is 448 are quantized with the scale 448 /
+    448 = 1, so their entries meet the E4M3 rounding unscaled: every midpoint
+    between neighbouring codes (ties to even), one FP32 step either side of
+    it, every code itself, the normal/subnormal boundary and values past 448,
+    with both signs; bit for bit against the oracle's quantizer."""
+    codes = np.arange(0x7f, dtype=np.uint8)                       # 0 .. 0x7e, then 448
+    vals = Qz.dequantize_fp8(codes[:, None], np.ones(1, dtype=np.float32))[:, 0].astype(np.float64)
+    vals = vals[np.isfinite(vals)]
+    mids = (vals[:-1] + vals[1:]) / 2
+    pts = np.concatenate([vals, mids, 2.0 ** -6 * np.array([1.0, 0.999, 1.001]), [448.0, 449.0, 464.0, 470.0, 1e6]])
+    x = pts.astype(np.float32)
+    x = np.concatenate([x, np.nextafter(x, np.float32(0)), np.nextafter(x, np.float32(np.inf))])
+    x = np.concatenate([x, -x])
+    x = np.minimum(np.abs(x), np.float32(448.0)) * np.sign(x)   # the column maximum stays 448
+    x[0] = np.float32(448.0)
+    A = np.zeros((x.size, 3), dtype=np.float32)
+    A[:, 0] = x
+    A[:, 1] = -x
+    A[:, 2] = x[::-1]
+    qf = R.quantize(torch.from_numpy(A).cuda(), R.RSVD_FP8_E4M3)
+    torch.cuda.synchronize()
+    Aq, s = Qz.quantize_fp8(A)
+    assert np.all(s == 1.0)
+    assert np.array_equal(qf.data.cpu().numpy(), Aq)
+
+
 def _decoded(fmt, q):
     if fmt == 2:
         return Qz.dequantize_bf16(q.data.cpu().numpy().view(np.uint16))
