@@ -77,11 +77,15 @@ template <typename T, int L> struct Strides {
                                                : ((L % 32 == 16) ? L + 8 : L + 8);
 };
 
-template <typename T, bool TRANS, bool OMEGA, int LT>
-__global__ __launch_bounds__(256) void skinny_gemm_kernel(GemmArgs g) {
+// WAVES wavefronts of 16 RT rows each; the sketch runs 8 (two 4-wavefront
+// row tiles under one generated Omega tile: half the generator work per row).
+template <typename T, bool TRANS, bool OMEGA, int LT, int WAVES = 4>
+__global__ __launch_bounds__(64 * WAVES) void skinny_gemm_kernel(GemmArgs g) {
+    static_assert(WAVES == 4 || (WAVES == 8 && !TRANS), "the TN layout is sized for 4 wavefronts");
+    constexpr int NT = 64 * WAVES;
     constexpr int RT = GemmTile<T, LT>::RT;
     constexpr int BK = GemmTile<T, LT>::BK;
-    constexpr int BM = 64 * RT;
+    constexpr int BM = 16 * RT * WAVES;
     constexpr int L = 16 * LT;
     constexpr int VEC = Vec16<T>::n;
     using V = typename Vec16<T>::type;
@@ -89,9 +93,9 @@ __global__ __launch_bounds__(256) void skinny_gemm_kernel(GemmArgs g) {
     constexpr int SA = TRANS ? S::SA_TN : S::SA_NN;
     constexpr int SB = S::SB;
     constexpr int A_ELEMS = TRANS ? BK * SA : BM * SA;
-    constexpr int NVA = BM * BK / VEC / 256;                   // A vectors per thread
-    constexpr int NVB = (BK * L / VEC + 255) / 256;            // X vectors per thread
-    constexpr int NOB = (BK / 4 * L + 255) / 256;              // Omega blocks per thread
+    constexpr int NVA = BM * BK / VEC / NT;                    // A vectors per thread
+    constexpr int NVB = (BK * L / VEC + NT - 1) / NT;          // X vectors per thread
+    constexpr int NOB = (BK / 4 * L + NT - 1) / NT;            // Omega blocks per thread
 
     __shared__ __attribute__((aligned(16))) T As[A_ELEMS];
     __shared__ __attribute__((aligned(16))) T Bs[BK * SB];
@@ -127,7 +131,7 @@ __global__ __launch_bounds__(256) void skinny_gemm_kernel(GemmArgs g) {
         if (rows_full && k0 + BK <= kend) {
 #pragma unroll
             for (int it = 0; it < NVA; ++it) {
-                const int idx = tid + 256 * it;
+                const int idx = tid + NT * it;
                 int64_t row, col;
                 if (!TRANS) { row = row0 + idx / (BK / VEC); col = k0 + (idx % (BK / VEC)) * VEC; }
                 else        { row = k0 + idx / (BM / VEC);   col = row0 + (idx % (BM / VEC)) * VEC; }
@@ -137,7 +141,7 @@ __global__ __launch_bounds__(256) void skinny_gemm_kernel(GemmArgs g) {
         }
 #pragma unroll
         for (int it = 0; it < NVA; ++it) {
-            const int idx = tid + 256 * it;
+            const int idx = tid + NT * it;
             int64_t row, col;                   // element (row, col) of A in memory
             if (!TRANS) { row = row0 + idx / (BK / VEC); col = k0 + (idx % (BK / VEC)) * VEC; }
             else        { row = k0 + idx / (BM / VEC);   col = row0 + (idx % (BM / VEC)) * VEC; }
@@ -157,7 +161,7 @@ __global__ __launch_bounds__(256) void skinny_gemm_kernel(GemmArgs g) {
     auto store_a = [&]() {
 #pragma unroll
         for (int it = 0; it < NVA; ++it) {
-            const int idx = tid + 256 * it;
+            const int idx = tid + NT * it;
             if (!TRANS) vec_store<T>(&As[(idx / (BK / VEC)) * SA + (idx % (BK / VEC)) * VEC], ra[it]);
             else        vec_store<T>(&As[(idx / (BM / VEC)) * SA + (idx % (BM / VEC)) * VEC], ra[it]);
         }
@@ -166,7 +170,7 @@ __global__ __launch_bounds__(256) void skinny_gemm_kernel(GemmArgs g) {
         if constexpr (OMEGA) {
 #pragma unroll
             for (int it = 0; it < NOB; ++it) {
-                const int idx = tid + 256 * it;
+                const int idx = tid + NT * it;
                 const int gi = idx / L, j = idx % L;
                 const int64_t r = k0 + 4 * gi;
                 if (idx < BK / 4 * L && j < g.ncols && r < kend) {
@@ -186,7 +190,7 @@ __global__ __launch_bounds__(256) void skinny_gemm_kernel(GemmArgs g) {
             if (xvec && g.ncols == L && k0 + BK <= kend) {
 #pragma unroll
                 for (int it = 0; it < NVB; ++it) {
-                    const int idx = tid + 256 * it;
+                    const int idx = tid + NT * it;
                     if (idx < BK * L / VEC) {
                         const int rr = idx / (L / VEC), c = (idx % (L / VEC)) * VEC;
                         rb[it] = *reinterpret_cast<const V*>(X + (k0 + rr) * g.ldx + c);
@@ -196,7 +200,7 @@ __global__ __launch_bounds__(256) void skinny_gemm_kernel(GemmArgs g) {
             }
 #pragma unroll
             for (int it = 0; it < NVB; ++it) {
-                const int idx = tid + 256 * it;
+                const int idx = tid + NT * it;
                 const int rr = idx / (L / VEC), c = (idx % (L / VEC)) * VEC;
                 const int64_t r = k0 + rr;
                 V v;
@@ -215,7 +219,7 @@ __global__ __launch_bounds__(256) void skinny_gemm_kernel(GemmArgs g) {
         if constexpr (OMEGA) {
 #pragma unroll
             for (int it = 0; it < NOB; ++it) {
-                const int idx = tid + 256 * it;
+                const int idx = tid + NT * it;
                 if (idx < BK / 4 * L) {
                     const int gi = idx / L, j = idx % L;
 #pragma unroll
@@ -225,7 +229,7 @@ __global__ __launch_bounds__(256) void skinny_gemm_kernel(GemmArgs g) {
         } else {
 #pragma unroll
             for (int it = 0; it < NVB; ++it) {
-                const int idx = tid + 256 * it;
+                const int idx = tid + NT * it;
                 if (idx < BK * L / VEC) vec_store<T>(&Bs[(idx / (L / VEC)) * SB + (idx % (L / VEC)) * VEC], rb[it]);
             }
         }
@@ -341,6 +345,20 @@ static hipError_t dispatch_lt(const GemmArgs& a, int LT, dim3 grid, hipStream_t 
     return hipGetLastError();
 }
 
+// The FP32 sketch with 8 wavefronts (LT <= 8: the registers of wider tiles
+// spill at 8 wavefronts).
+static hipError_t dispatch_sketch8(const GemmArgs& a, int LT, dim3 grid, hipStream_t s) {
+#define RSVD_LT_CASE(N) \
+    case N: hipLaunchKernelGGL((skinny_gemm_kernel<float, false, true, N, 8>), grid, dim3(512), 0, s, a); break;
+    switch (LT) {
+        RSVD_LT_CASE(1) RSVD_LT_CASE(2) RSVD_LT_CASE(3) RSVD_LT_CASE(4) RSVD_LT_CASE(5) RSVD_LT_CASE(6)
+        RSVD_LT_CASE(7) RSVD_LT_CASE(8)
+        default: return hipErrorInvalidValue;
+    }
+#undef RSVD_LT_CASE
+    return hipGetLastError();
+}
+
 static int bm_of(int dtype, int LT) {
     return dtype == 0 ? 64 * GemmTile<double, 1>::RT : (LT > 9 ? 64 * GemmTile<float, 10>::RT : 64 * GemmTile<float, 1>::RT);
 }
@@ -379,12 +397,17 @@ hipError_t launch_gemm(int dtype, GemmArgs a, hipStream_t s, hipEvent_t product_
     if (omega && a.trans) return hipErrorInvalidValue;
     if (a.splits < 1 || a.splits > kMaxSplits) return hipErrorInvalidValue;
     dim3 grid(gemm_row_tiles(dtype, a.M, a.ncols) * a.splits);
+    // The FP32 sketch up to 128 columns: 8 wavefronts, twice the rows per
+    // workgroup (same slices).
+    const bool sketch8 = omega && dtype != 0 && LT <= 8;
+    const dim3 grid8((unsigned)ceil_div(a.M, 2 * bm_of(dtype, LT)) * a.splits);
     hipError_t e;
     if (dtype == 0) {
         if (a.trans) e = dispatch_lt<double, true, false>(a, LT, grid, s);
         else e = omega ? dispatch_lt<double, false, true>(a, LT, grid, s) : dispatch_lt<double, false, false>(a, LT, grid, s);
     } else {
         if (a.trans) e = dispatch_lt<float, true, false>(a, LT, grid, s);
+        else if (sketch8) e = dispatch_sketch8(a, LT, grid8, s);
         else e = omega ? dispatch_lt<float, false, true>(a, LT, grid, s) : dispatch_lt<float, false, false>(a, LT, grid, s);
     }
     if (e == hipSuccess && product_done) e = hipEventRecord(product_done, s);
