@@ -66,21 +66,54 @@ __global__ __launch_bounds__(64 * kGramWaves) void gram_kernel(const T* __restri
     const T* __restrict__ ya = Y + a * 16 + li;
     const T* __restrict__ yb = Y + b * 16 + li;
     doublex4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-    constexpr int UNR = 8;          // 8 MFMA steps (32 rows per wavefront) per batch of loads
     constexpr int STEP = 4 * kGramWaves;
-    for (int64_t k0 = r0 + 4 * wave; k0 < r1; k0 += STEP * UNR) {
-        double va[UNR], vb[UNR];
+    const int64_t range = r1 * ldy * (int64_t)sizeof(T);
+    // every lane and scalar offset below stays under 2^31
+    if (range + (int64_t)STEP * 16 * ldy * (int64_t)sizeof(T) <= 0x7fffffff) {
+        // A 1024-row chunk in one batch of loads per wavefront (each round trip
+        // to Y costs about 5 us), through a buffer descriptor whose range ends
+        // at row r1, so rows past the chunk read as zero with no per-load
+        // guard, and the loads of a batch share one lane offset and differ by
+        // a scalar offset (one address register instead of one per load).
+        constexpr int UNR = 16;
+        const __amdgpu_buffer_rsrc_t ry = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(Y), 0, (int)range, 0x00020000);
+        const int step_bytes = (int)(STEP * ldy * (int64_t)sizeof(T));
+        for (int64_t k0 = r0 + 4 * wave; k0 < r1; k0 += STEP * UNR) {
+            const int oa = (int)(((k0 + lk) * ldy + a * 16 + li) * (int64_t)sizeof(T));
+            const int ob = oa + (b - a) * 16 * (int)sizeof(T);
+            T va[UNR], vb[UNR];
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            const int64_t row = k0 + STEP * u + lk;
-            const bool ok = row < r1;
-            va[u] = ok ? (double)ya[row * ldy] : 0.0;
-            vb[u] = ok ? (double)yb[row * ldy] : 0.0;
+            for (int u = 0; u < UNR; ++u) {
+                if constexpr (sizeof(T) == 4) {
+                    va[u] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(ry, oa, u * step_bytes, 0));
+                    vb[u] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(ry, ob, u * step_bytes, 0));
+                } else {
+                    va[u] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(ry, oa, u * step_bytes, 0));
+                    vb[u] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(ry, ob, u * step_bytes, 0));
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < UNR; u += 2) {
+                acc0 = mfma16x16x4((double)va[u], (double)vb[u], acc0);
+                acc1 = mfma16x16x4((double)va[u + 1], (double)vb[u + 1], acc1);
+            }
         }
+    } else {
+        constexpr int UNR = 8;      // 8 MFMA steps (32 rows per wavefront) per batch of loads
+        for (int64_t k0 = r0 + 4 * wave; k0 < r1; k0 += STEP * UNR) {
+            double va[UNR], vb[UNR];
 #pragma unroll
-        for (int u = 0; u < UNR; u += 2) {
-            acc0 = mfma16x16x4(va[u], vb[u], acc0);
-            acc1 = mfma16x16x4(va[u + 1], vb[u + 1], acc1);
+            for (int u = 0; u < UNR; ++u) {
+                const int64_t row = k0 + STEP * u + lk;
+                const bool ok = row < r1;
+                va[u] = ok ? (double)ya[row * ldy] : 0.0;
+                vb[u] = ok ? (double)yb[row * ldy] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < UNR; u += 2) {
+                acc0 = mfma16x16x4(va[u], vb[u], acc0);
+                acc1 = mfma16x16x4(va[u + 1], vb[u + 1], acc1);
+            }
         }
     }
     // acc[v] = G[a*16 + acc_row(lk, v)][b*16 + li] restricted to this chunk.
