@@ -189,8 +189,10 @@ constexpr size_t kJacobiWorkDoubles = (size_t)kMaxL * kMaxL + kJacobiBlockSweeps
 // sweep count of the solve's small SVDs.  batch (l <= 128 only): that many
 // independent problems of the same l in one launch, one workgroup each,
 // problem b at R + b L^2, shift + b, sigma + b L, Ut + b L^2, Mv + b L^2.
+// tol: rotation threshold, a pair rotates while |x_i . x_j| > tol |x_i| |x_j|
+// (0 < tol < 1).
 hipError_t launch_jacobi(const double* R, int l, int L, const double* shift, double* sigma, double* Ut,
-                         double* Mv, DevFlags* flags, double* work, hipStream_t s, int max_sweeps = 0,
+                         double* Mv, DevFlags* flags, double* work, double tol, hipStream_t s, int max_sweeps = 0,
                          int batch = 1);
 
 // Reduce the per-block argmax partials of the V columns, choose signs,

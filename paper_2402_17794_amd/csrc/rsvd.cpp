@@ -200,6 +200,17 @@ T* at(void* base, size_t off) {
 // panels always take it.
 constexpr double kPass2SkipTauF32 = 0x1.0p-24;
 
+// Rotation threshold of the small SVD's one-sided Jacobi iteration (a pair
+// rotates while |x_i . x_j| > tol |x_i| |x_j|).  FP64 data: 1e-15, columns
+// orthogonal to the working precision.  FP32 and lower-precision data, whose
+// own rounding is at least 2^-24 relative: 2^-34, so the columns' remaining
+// non-orthogonality (which perturbs the singular values only to second order)
+// stays three decades below the data's precision; this saves the last sweep
+// of the quadratically convergent iteration.
+constexpr double kJacobiTolF64 = 1e-15;
+constexpr double kJacobiTolLow = 0x1.0p-34;
+double jacobi_tol(int dtype) { return dtype == RSVD_F64 ? kJacobiTolF64 : kJacobiTolLow; }
+
 // orth(Y) -> Q for an internal rows x L buffer (ld = L, l valid columns,
 // zero padding), with the outcome in `flags`.  Qout must not alias Y.
 // CholeskyQR2: Q1 = Y R1^{-1} is written to Qout, and the second pass
@@ -386,7 +397,7 @@ rsvd_status run_spectral(const Plan& P, void* ws, const rsvd_matrix* A, const vo
     RSVD_TRY(launch_chol(GP, P.m, b, B, at<double>(ws, P.R), at<double>(ws, P.Rinv), f2, 2, shift2,
                          at<double>(ws, P.work), 0.0, s));
     RSVD_TRY(launch_jacobi(at<double>(ws, P.R), b, B, shift2, sigma2, at<double>(ws, P.Ut), at<double>(ws, P.Mv), f2,
-                           at<double>(ws, P.work), s));
+                           at<double>(ws, P.work), jacobi_tol(dt), s));
     RSVD_TRY(launch_residual_spec_final(sigma2, out, fro_requested, s));
     return RSVD_OK;
 }
@@ -622,7 +633,7 @@ rsvd_status small_svd(rsvd_handle* hp, const Plan& P, void* ws, const double* Bt
         RSVD_TRY(hipEventRecord(jac.start, s));
     }
     RSVD_TRY(launch_jacobi(at<double>(ws, P.R), l, L, at<double>(ws, P.shift), sigma, Ut, Mv, flags,
-                           at<double>(ws, P.work), s, max_sweeps));
+                           at<double>(ws, P.work), jacobi_tol(P.dtype), s, max_sweeps));
     if (hp) {
         RSVD_TRY(hipEventRecord(jac.stop, s));
         hp->recs.push_back(jac);
@@ -649,7 +660,8 @@ rsvd_status small_svd2(rsvd_handle* hp, const Plan& P, void* ws, const double* B
         if (!jac.start || !jac.stop) return RSVD_ERR_DEVICE;
         RSVD_TRY(hipEventRecord(jac.start, s));
     }
-    RSVD_TRY(launch_jacobi(R2, l, L, shift2, sigma, Ut, Mv2, flags, at<double>(ws, P.work), s, max_sweeps, 2));
+    RSVD_TRY(launch_jacobi(R2, l, L, shift2, sigma, Ut, Mv2, flags, at<double>(ws, P.work), jacobi_tol(P.dtype), s,
+                           max_sweeps, 2));
     if (hp) {
         RSVD_TRY(hipEventRecord(jac.stop, s));
         hp->recs.push_back(jac);
@@ -727,7 +739,8 @@ rsvd_status solve_single_pass(rsvd_handle* hp, const SpLayout& S, const rsvd_mat
             RSVD_TRY(hipEventRecord(jac.start, s));
         }
         RSVD_TRY(launch_jacobi(at<double>(ws, P.R), l, L, at<double>(ws, P.shift), at<double>(ws, P.sigma),
-                               at<double>(ws, P.Ut), Mv, flags, at<double>(ws, P.work), s, sweeps));
+                               at<double>(ws, P.Ut), Mv, flags, at<double>(ws, P.work), jacobi_tol(P.dtype), s,
+                               sweeps));
         if (hp) {
             RSVD_TRY(hipEventRecord(jac.stop, s));
             hp->recs.push_back(jac);
@@ -926,8 +939,8 @@ rsvd_status solve_impl(rsvd_handle* h, const rsvd_matrix* A, const rsvd_params* 
         if (!jac.start || !jac.stop) return RSVD_ERR_DEVICE;
         RSVD_TRY(hipEventRecord(jac.start, s));
     }
-    RSVD_TRY(launch_jacobi(R, (int)P.l, L, shift, sigma, Ut, Mv, flags, at<double>(ws, P.work), s,
-                           params->jacobi_max_sweeps));
+    RSVD_TRY(launch_jacobi(R, (int)P.l, L, shift, sigma, Ut, Mv, flags, at<double>(ws, P.work), jacobi_tol(P.dtype),
+                           s, params->jacobi_max_sweeps));
     if (hp) {
         RSVD_TRY(hipEventRecord(jac.stop, s));
         h->recs.push_back(jac);
@@ -1261,7 +1274,8 @@ rsvd_status rsvd_canonical_sines(rsvd_handle* h, int32_t dtype, int64_t rows, in
     RSVD_TRY(launch_chol(GP, rows, (int)k, W.K1, at<double>(ws, W.R), at<double>(ws, W.Rinv), flags, 2,
                          at<double>(ws, W.shift), at<double>(ws, W.work), 0.0, s));
     RSVD_TRY(launch_jacobi(at<double>(ws, W.R), (int)k, W.K1, at<double>(ws, W.shift), at<double>(ws, W.sigma),
-                           at<double>(ws, W.Ut), at<double>(ws, W.Mv), flags, at<double>(ws, W.work), s));
+                           at<double>(ws, W.Ut), at<double>(ws, W.Mv), flags, at<double>(ws, W.work), kJacobiTolF64,
+                           s));
     RSVD_TRY(launch_sines(at<double>(ws, W.sigma), (int)k, sines, s));
     return RSVD_OK;
 }
@@ -1366,7 +1380,8 @@ rsvd_status rsvd_adaptive_range(rsvd_handle* h, const rsvd_matrix* A, double tol
         RSVD_TRY(launch_chol(GP, m, b, B, at<double>(ows, OP.R), at<double>(ows, OP.Rinv), flags, 2,
                              at<double>(ows, OP.shift), at<double>(ows, OP.work), 0.0, s));
         RSVD_TRY(launch_jacobi(at<double>(ows, OP.R), b, B, at<double>(ows, OP.shift), at<double>(ows, OP.sigma),
-                               at<double>(ows, OP.Ut), at<double>(ows, OP.Mv), flags, at<double>(ows, OP.work), s));
+                               at<double>(ows, OP.Ut), at<double>(ows, OP.Mv), flags, at<double>(ows, OP.work),
+                               kJacobiTolF64, s));
         RSVD_TRY(launch_adaptive_stats(GP, m, B, b, at<double>(ows, OP.sigma), kEstFactor, thr, dstats, s));
         double hst[2] = {0.0, 0.0};
         RSVD_TRY(hipMemcpyAsync(hst, dstats, sizeof(hst), hipMemcpyDeviceToHost, s));

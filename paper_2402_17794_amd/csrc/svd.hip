@@ -24,7 +24,6 @@
 namespace rsvd {
 
 constexpr int kJacobiRegMax = 128;
-constexpr double kJacobiTol = 1e-15;
 constexpr int kJacobiMaxSweeps = 60;
 
 // Sum over the 8 lanes of each eighth of a wavefront (xor 1, xor 2, then
@@ -57,9 +56,10 @@ __device__ __forceinline__ double rsq_newton(double x) {
 // g t^2 + (b - a) t - g = 0, which makes the rotated pair orthogonal.  The
 // form has no quotient that can overflow (the columns are scaled so that
 // a, b <= 1, hence |d|, |e| <= 2) and no branch.  t = 0 (and `rot`
-// untouched) when |g| <= tol sqrt(a b), the pair already orthogonal.
-__device__ __forceinline__ double jacobi_tan(double a, double b, double g, int& rot) {
-    const bool r = g * g > (kJacobiTol * kJacobiTol) * (a * b);
+// untouched) when |g| <= tol sqrt(a b), the pair already orthogonal
+// (tol2 = tol^2).
+__device__ __forceinline__ double jacobi_tan(double a, double b, double g, int& rot, double tol2) {
+    const bool r = g * g > tol2 * (a * b);
     rot |= (int)r;
     const double d = b - a, e = 2.0 * g;
     const double s2 = fma(d, d, e * e);
@@ -169,8 +169,9 @@ __global__ __launch_bounds__(256) void jacobi_oe_kernel(const double* __restrict
                                                         const double* __restrict__ shift_p,
                                                         double* __restrict__ sigma, double* __restrict__ Ut,
                                                         double* __restrict__ Mv, DevFlags* flags, int max_sweeps,
-                                                        JBatch bs) {
+                                                        JBatch bs, double tol) {
     constexpr int LPP = 8, QMAX = kJacobiRegMax / 4;
+    const double tol2 = tol * tol;
     Rm += blockIdx.x * bs.r;
     shift_p += blockIdx.x;
     sigma += blockIdx.x * bs.s;
@@ -235,7 +236,7 @@ __global__ __launch_bounds__(256) void jacobi_oe_kernel(const double* __restrict
     // takes the rotated second column.
     auto local = [&](double (&xa)[R], double (&xb)[R], JColumn& ca, JColumn& cb) {
         const double g = octet_sum(partial_dot<R>(xa, xb)) * (ca.sc * cb.sc);
-        const double t = jacobi_tan(ca.nr, cb.nr, g, rot);
+        const double t = jacobi_tan(ca.nr, cb.nr, g, rot, tol2);
         big |= (int)(fabs(t) > 0x1.0p-20);
         const JRot o = jacobi_rot(ca, cb, g, t);
 #pragma unroll
@@ -289,7 +290,7 @@ __global__ __launch_bounds__(256) void jacobi_oe_kernel(const double* __restrict
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int i = 16 * a + acc_row<double>(lk, v), j = pb;
-                    if (i < j && j < n4) bad |= (int)(acc[v] * acc[v] > (kJacobiTol * kJacobiTol) * (nrm2[i] * nrm2[j]));
+                    if (i < j && j < n4) bad |= (int)(acc[v] * acc[v] > tol2 * (nrm2[i] * nrm2[j]));
                 }
             }
             if (!__syncthreads_or(bad)) {
@@ -328,8 +329,8 @@ __global__ __launch_bounds__(256) void jacobi_oe_kernel(const double* __restrict
             const double pr = partial_dot<R>(x[3], yr), pl = partial_dot<R>(yl, x[0]);
             const double gR = octet_sum(pr) * (hasR ? c[3].sc * cr.sc : 0.0);
             const double gL = octet_sum(pl) * (hasL ? cl.sc * c[0].sc : 0.0);
-            const double tR = jacobi_tan(c[3].nr, cr.nr, gR, rot);
-            const double tL = jacobi_tan(cl.nr, c[0].nr, gL, rot);
+            const double tR = jacobi_tan(c[3].nr, cr.nr, gR, rot, tol2);
+            const double tL = jacobi_tan(cl.nr, c[0].nr, gL, rot, tol2);
             big |= (int)(fmax(fabs(tR), fabs(tL)) > 0x1.0p-20);
             const JRot oR = jacobi_rot(c[3], cr, gR, tR);
             const JRot oL = jacobi_rot(cl, c[0], gL, tL);
@@ -451,8 +452,9 @@ __global__ __launch_bounds__(1024) void jacobi_blk_prep_kernel(const double* __r
 
 template <int R>
 __global__ __launch_bounds__(kBlkLpp * kBlkGroups) void jacobi_blk_pair_kernel(double* __restrict__ work, int nb2,
-                                                                                int round, int sweep) {
+                                                                                int round, int sweep, double tol) {
     constexpr int LPP = kBlkLpp, G = kBlkGroups;
+    const double tol2 = tol * tol;
     __shared__ double xch[2 * R * G * LPP];          // [side][k][group][lane]
     __shared__ JColumn xcol[2][G];
     double* X = work;
@@ -483,7 +485,7 @@ __global__ __launch_bounds__(kBlkLpp * kBlkGroups) void jacobi_blk_pair_kernel(d
     for (int h = 0; h < G; ++h) {
         {   // even round: pair (2g, 2g + 1); position 2g takes the rotated second column
             const double g = quarter_sum(partial_dot<R>(x0, x1)) * (c0.sc * c1.sc);
-            const double t = jacobi_tan(c0.nr, c1.nr, g, rot);
+            const double t = jacobi_tan(c0.nr, c1.nr, g, rot, tol2);
             const JRot o = jacobi_rot(c0, c1, g, t);
 #pragma unroll
             for (int k = 0; k < R; ++k) {
@@ -517,8 +519,8 @@ __global__ __launch_bounds__(kBlkLpp * kBlkGroups) void jacobi_blk_pair_kernel(d
         const double pr = partial_dot<R>(x1, yr), pl = partial_dot<R>(yl, x0);
         const double gR = hasR ? quarter_sum(pr) * (c1.sc * cr.sc) : 0.0;
         const double gL = hasL ? quarter_sum(pl) * (cl.sc * c0.sc) : 0.0;
-        const double tR = jacobi_tan(c1.nr, cr.nr, gR, rot);
-        const double tL = jacobi_tan(cl.nr, c0.nr, gL, rot);
+        const double tR = jacobi_tan(c1.nr, cr.nr, gR, rot, tol2);
+        const double tL = jacobi_tan(cl.nr, c0.nr, gL, rot, tol2);
         const JRot oR = jacobi_rot(c1, cr, gR, tR);
         const JRot oL = jacobi_rot(cl, c0, gL, tL);
 #pragma unroll
@@ -584,29 +586,31 @@ __global__ __launch_bounds__(512) void jacobi_blk_finish_kernel(const double* __
 
 template <int R>
 static void launch_jacobi_blk(const double* Rm, int l, int L, const double* shift, double* sigma, double* Ut,
-                              double* Mv, DevFlags* flags, double* work, hipStream_t s, int sweeps) {
+                              double* Mv, DevFlags* flags, double* work, hipStream_t s, int sweeps, double tol) {
     const int nb = (l + 15) / 16, nb2 = nb + (nb & 1);
     hipLaunchKernelGGL(jacobi_blk_prep_kernel, dim3(1), dim3(1024), 0, s, Rm, l, L, work);
     for (int sweep = 0; sweep < sweeps; ++sweep)
         for (int r = 0; r < nb2 - 1; ++r)
             hipLaunchKernelGGL(jacobi_blk_pair_kernel<R>, dim3(nb2 / 2), dim3(kBlkLpp * kBlkGroups), 0, s, work, nb2,
-                               r, sweep);
+                               r, sweep, tol);
     hipLaunchKernelGGL(jacobi_blk_finish_kernel, dim3(1), dim3(512), 0, s, work, l, L, shift, sigma, Ut, Mv, flags,
                        sweeps);
 }
 
 template <int R>
 static void launch_jacobi_oe(const double* Rm, int l, int L, const double* shift, double* sigma, double* Ut,
-                             double* Mv, DevFlags* flags, hipStream_t s, int sweeps, int batch, JBatch bs) {
+                             double* Mv, DevFlags* flags, hipStream_t s, int sweeps, int batch, JBatch bs,
+                             double tol) {
     const int groups = ((l + 3) & ~3) / 4;
     const int threads = (int)round_up(groups * 8, kWave);
     hipLaunchKernelGGL(jacobi_oe_kernel<R>, dim3(batch), dim3(threads), 0, s, Rm, l, L, shift, sigma, Ut, Mv, flags,
-                       sweeps, bs);
+                       sweeps, bs, tol);
 }
 
 hipError_t launch_jacobi(const double* R, int l, int L, const double* shift, double* sigma, double* Ut, double* Mv,
-                         DevFlags* flags, double* work, hipStream_t s, int max_sweeps, int batch) {
-    if (l < 1 || l > kMaxL || L < l || max_sweeps < 0 || batch < 1) return hipErrorInvalidValue;
+                         DevFlags* flags, double* work, double tol, hipStream_t s, int max_sweeps, int batch) {
+    if (l < 1 || l > kMaxL || L < l || max_sweeps < 0 || batch < 1 || !(tol > 0.0 && tol < 1.0))
+        return hipErrorInvalidValue;
     if (batch > 1 && l > kJacobiRegMax) return hipErrorInvalidValue;
     const JBatch bs{(int64_t)L * L, (int64_t)L * L, L};
     const int oe_sweeps = max_sweeps ? max_sweeps : kJacobiMaxSweeps;
@@ -614,28 +618,28 @@ hipError_t launch_jacobi(const double* R, int l, int L, const double* shift, dou
     if (l <= kJacobiRegMax) {
         // rows per lane and column: 2 ceil(l / 16), so 8 lanes cover ceil(l / 16) * 16 >= l rows
         switch ((l + 15) / 16) {
-            case 1: launch_jacobi_oe<2>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps, batch, bs); break;
-            case 2: launch_jacobi_oe<4>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps, batch, bs); break;
-            case 3: launch_jacobi_oe<6>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps, batch, bs); break;
-            case 4: launch_jacobi_oe<8>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps, batch, bs); break;
-            case 5: launch_jacobi_oe<10>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps, batch, bs); break;
-            case 6: launch_jacobi_oe<12>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps, batch, bs); break;
-            case 7: launch_jacobi_oe<14>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps, batch, bs); break;
-            default: launch_jacobi_oe<16>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps, batch, bs); break;
+            case 1: launch_jacobi_oe<2>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps, batch, bs, tol); break;
+            case 2: launch_jacobi_oe<4>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps, batch, bs, tol); break;
+            case 3: launch_jacobi_oe<6>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps, batch, bs, tol); break;
+            case 4: launch_jacobi_oe<8>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps, batch, bs, tol); break;
+            case 5: launch_jacobi_oe<10>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps, batch, bs, tol); break;
+            case 6: launch_jacobi_oe<12>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps, batch, bs, tol); break;
+            case 7: launch_jacobi_oe<14>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps, batch, bs, tol); break;
+            default: launch_jacobi_oe<16>(R, l, L, shift, sigma, Ut, Mv, flags, s, oe_sweeps, batch, bs, tol); break;
         }
     } else {
         // rows per lane and column: ceil(l / 16), 16 lanes per column pair
         switch ((l + 15) / 16) {
-            case 9: launch_jacobi_blk<9>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps); break;
-            case 10: launch_jacobi_blk<10>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps); break;
-            case 11: launch_jacobi_blk<11>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps); break;
-            case 12: launch_jacobi_blk<12>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps); break;
-            case 13: launch_jacobi_blk<13>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps); break;
-            case 14: launch_jacobi_blk<14>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps); break;
-            case 15: launch_jacobi_blk<15>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps); break;
-            case 16: launch_jacobi_blk<16>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps); break;
-            case 17: launch_jacobi_blk<17>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps); break;
-            default: launch_jacobi_blk<18>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps); break;
+            case 9: launch_jacobi_blk<9>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps, tol); break;
+            case 10: launch_jacobi_blk<10>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps, tol); break;
+            case 11: launch_jacobi_blk<11>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps, tol); break;
+            case 12: launch_jacobi_blk<12>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps, tol); break;
+            case 13: launch_jacobi_blk<13>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps, tol); break;
+            case 14: launch_jacobi_blk<14>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps, tol); break;
+            case 15: launch_jacobi_blk<15>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps, tol); break;
+            case 16: launch_jacobi_blk<16>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps, tol); break;
+            case 17: launch_jacobi_blk<17>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps, tol); break;
+            default: launch_jacobi_blk<18>(R, l, L, shift, sigma, Ut, Mv, flags, work, s, blk_sweeps, tol); break;
         }
     }
     return hipGetLastError();
