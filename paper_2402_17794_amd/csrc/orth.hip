@@ -1371,46 +1371,65 @@ __device__ void hh_grid_sync(DevFlags* flags, int nblocks) {
     __syncthreads();
 }
 
-// Inner products and updates of one column c with the current reflector v
-// (v[i * vst], rows j..nr-1: in LDS with vst = 1, or in place in the tile
-// with vst = L), lanes striding the rows with four independent loads in
-// flight: w = v^T X[:, c] summed over the wavefront, then X[:, c] -= (tau w) v.
-__device__ __forceinline__ void hh_reflect_column(double* X, const double* v, int vst, int j, int nr, int L, int c,
-                                                  double tj) {
-    const int lane = threadIdx.x & 63;
+// X <- (I - tau v v^T) X on rows j..nr-1 and columns c0..l-1 of X (row
+// stride L), the reflector v in v[i * vst] (in LDS with vst = 1, or in place
+// in the tile with vst = L): w = tau v^T X, then X -= v w.  The workgroup
+// works on 128 columns at a time, one column per lane, so every load and
+// store of a row is contiguous across the lanes; the kHhThreads / 128 row
+// groups take rows j + g, j + g + groups, ... with four loads in flight, and
+// their partial inner products are summed in group order through wbuf
+// (kHhThreads doubles of LDS).  Every thread of the workgroup calls this.
+__device__ void hh_reflect_block(double* X, const double* v, int vst, int j, int nr, int L, int c0, int l, double tj,
+                                 double* wbuf) {
+    constexpr int CG = 128;
+    const int tid = threadIdx.x, cl = tid % CG, rg = tid / CG, nrg = blockDim.x / CG;
     const int64_t sv = vst;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int i = j + lane;
-    for (; i + 192 < nr; i += 256) {
-        const double x0 = X[(int64_t)i * L + c], x1 = X[(int64_t)(i + 64) * L + c];
-        const double x2 = X[(int64_t)(i + 128) * L + c], x3 = X[(int64_t)(i + 192) * L + c];
-        a0 = fma(v[i * sv], x0, a0);
-        a1 = fma(v[(i + 64) * sv], x1, a1);
-        a2 = fma(v[(i + 128) * sv], x2, a2);
-        a3 = fma(v[(i + 192) * sv], x3, a3);
+    for (int cb = c0; cb < l; cb += CG) {
+        const int c = cb + cl;
+        const bool act = c < l;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        if (act) {
+            int i = j + rg;
+            for (; i + 3 * nrg < nr; i += 4 * nrg) {
+                const double x0 = X[(int64_t)i * L + c], x1 = X[(int64_t)(i + nrg) * L + c];
+                const double x2 = X[(int64_t)(i + 2 * nrg) * L + c], x3 = X[(int64_t)(i + 3 * nrg) * L + c];
+                a0 = fma(v[i * sv], x0, a0);
+                a1 = fma(v[(i + nrg) * sv], x1, a1);
+                a2 = fma(v[(i + 2 * nrg) * sv], x2, a2);
+                a3 = fma(v[(i + 3 * nrg) * sv], x3, a3);
+            }
+            for (; i < nr; i += nrg) a0 = fma(v[i * sv], X[(int64_t)i * L + c], a0);
+        }
+        wbuf[rg * CG + cl] = (a0 + a1) + (a2 + a3);
+        __syncthreads();
+        double w = 0.0;
+        for (int g = 0; g < nrg; ++g) w += wbuf[g * CG + cl];
+        w *= tj;
+        if (act) {
+            int i = j + rg;
+            for (; i + 3 * nrg < nr; i += 4 * nrg) {
+                const double x0 = X[(int64_t)i * L + c], x1 = X[(int64_t)(i + nrg) * L + c];
+                const double x2 = X[(int64_t)(i + 2 * nrg) * L + c], x3 = X[(int64_t)(i + 3 * nrg) * L + c];
+                X[(int64_t)i * L + c] = fma(-w, v[i * sv], x0);
+                X[(int64_t)(i + nrg) * L + c] = fma(-w, v[(i + nrg) * sv], x1);
+                X[(int64_t)(i + 2 * nrg) * L + c] = fma(-w, v[(i + 2 * nrg) * sv], x2);
+                X[(int64_t)(i + 3 * nrg) * L + c] = fma(-w, v[(i + 3 * nrg) * sv], x3);
+            }
+            for (; i < nr; i += nrg) X[(int64_t)i * L + c] = fma(-w, v[i * sv], X[(int64_t)i * L + c]);
+        }
+        __syncthreads();                            // wbuf is reused by the next block of columns
     }
-    for (; i < nr; i += 64) a0 = fma(v[i * sv], X[(int64_t)i * L + c], a0);
-    const double w = wave_sum((a0 + a1) + (a2 + a3)) * tj;
-    i = j + lane;
-    for (; i + 192 < nr; i += 256) {
-        const double x0 = X[(int64_t)i * L + c], x1 = X[(int64_t)(i + 64) * L + c];
-        const double x2 = X[(int64_t)(i + 128) * L + c], x3 = X[(int64_t)(i + 192) * L + c];
-        X[(int64_t)i * L + c] = fma(-w, v[i * sv], x0);
-        X[(int64_t)(i + 64) * L + c] = fma(-w, v[(i + 64) * sv], x1);
-        X[(int64_t)(i + 128) * L + c] = fma(-w, v[(i + 128) * sv], x2);
-        X[(int64_t)(i + 192) * L + c] = fma(-w, v[(i + 192) * sv], x3);
-    }
-    for (; i < nr; i += 64) X[(int64_t)i * L + c] = fma(-w, v[i * sv], X[(int64_t)i * L + c]);
 }
 
 // Householder QR in place of the tile T (nr rows, row stride L, FP64): for
 // column j < min(nr, l), the reflector v (v_0 on the diagonal, the rest
 // below it) with tau_j = 2 / v^T v maps the trailing part of column j onto
-// beta_j e_1; the trailing columns c < l are updated (one wavefront per
-// column).  Above the diagonal T then holds R; beta holds its diagonal.
-// vs: LDS for nr doubles.
-__device__ void hh_factor_tile(double* T, int nr, int L, int l, double* tau, double* beta, double* red, double* vs) {
-    const int tid = threadIdx.x, wave = tid >> 6, nw = blockDim.x >> 6;
+// beta_j e_1; the trailing columns c < l are updated by the whole workgroup
+// (hh_reflect_block).  Above the diagonal T then holds R; beta holds its
+// diagonal.  vs: LDS for nr doubles; wbuf: LDS for blockDim.x doubles.
+__device__ void hh_factor_tile(double* T, int nr, int L, int l, double* tau, double* beta, double* red, double* vs,
+                               double* wbuf) {
+    const int tid = threadIdx.x;
     const int jmax = min(nr, l);
     const bool in_lds = nr <= kHhVsMax;
     for (int j = 0; j < jmax; ++j) {
@@ -1440,15 +1459,16 @@ __device__ void hh_factor_tile(double* T, int nr, int L, int l, double* tau, dou
         }
         __syncthreads();
         const double* v = in_lds ? vs : T + j;
-        for (int c = j + 1 + wave; c < l; c += nw) hh_reflect_column(T, v, in_lds ? 1 : L, j, nr, L, c, tj);
-        __syncthreads();
+        hh_reflect_block(T, v, in_lds ? 1 : L, j, nr, L, j + 1, l, tj, wbuf);
     }
 }
 
 // Z (nr x L) <- H_0 H_1 ... H_{jmax-1} Z with the reflectors of tile T (as
-// left by hh_factor_tile), columns c < l only.  vs: LDS for nr doubles.
-__device__ void hh_apply_tile(const double* T, int nr, int L, int l, const double* tau, double* Z, double* vs) {
-    const int tid = threadIdx.x, wave = tid >> 6, nw = blockDim.x >> 6;
+// left by hh_factor_tile), columns c < l only.  vs: LDS for nr doubles;
+// wbuf: LDS for blockDim.x doubles.
+__device__ void hh_apply_tile(const double* T, int nr, int L, int l, const double* tau, double* Z, double* vs,
+                              double* wbuf) {
+    const int tid = threadIdx.x;
     const int jmax = min(nr, l);
     const bool in_lds = nr <= kHhVsMax;
     for (int j = jmax - 1; j >= 0; --j) {
@@ -1458,8 +1478,7 @@ __device__ void hh_apply_tile(const double* T, int nr, int L, int l, const doubl
             for (int i = j + tid; i < nr; i += blockDim.x) vs[i] = T[(int64_t)i * L + j];
         __syncthreads();
         const double* v = in_lds ? vs : T + j;
-        for (int c = wave; c < l; c += nw) hh_reflect_column(Z, v, in_lds ? 1 : L, j, nr, L, c, tj);
-        __syncthreads();
+        hh_reflect_block(Z, v, in_lds ? 1 : L, j, nr, L, 0, l, tj, wbuf);
     }
 }
 
@@ -1472,6 +1491,7 @@ __global__ __launch_bounds__(kHhThreads) void householder_kernel(const T* __rest
     if (!force && !flags->orth_fail) return;
     __shared__ double red[kHhThreads / 64];
     __shared__ double vs[kHhVsMax];                 // the current reflector (tile rows <= kHhVsMax)
+    __shared__ double wbuf[kHhThreads];             // partial inner products of hh_reflect_block
     const int tid = threadIdx.x, b = blockIdx.x, G = gridDim.x;
     auto chunk = [&](int c) { return (int64_t)c * rows / tr.n[1]; };     // level-1 chunk c: rows [chunk(c), chunk(c+1))
     auto tile_rows = [&](int h, int t) -> int {                           // rows of tile t at level h >= 2
@@ -1501,7 +1521,7 @@ __global__ __launch_bounds__(kHhThreads) void householder_kernel(const T* __rest
             }
             double* tau = up + tr.t_off[h] + (int64_t)b * L;
             double* beta = tau + (int64_t)tr.n[h] * L;
-            hh_factor_tile(Tt, nr, L, l, tau, beta, red, vs);
+            hh_factor_tile(Tt, nr, L, l, tau, beta, red, vs, wbuf);
             if (h < tr.nlev) {                          // R of this tile -> block b of the level h + 1 stack
                 double* Rp = up + tr.s_off[h + 1] + (int64_t)b * L * L;
                 for (int idx = tid; idx < L * L; idx += kHhThreads) {
@@ -1530,7 +1550,7 @@ __global__ __launch_bounds__(kHhThreads) void householder_kernel(const T* __rest
             }
             __syncthreads();
             const double* tau = up + tr.t_off[h] + (int64_t)b * L;
-            hh_apply_tile(tile_base(h, b), nr, L, l, tau, Z, vs);
+            hh_apply_tile(tile_base(h, b), nr, L, l, tau, Z, vs, wbuf);
             if (h == 1) {                               // this chunk's rows of Q, signs from the root's R
                 const int64_t r0 = chunk(b);
                 for (int64_t idx = tid; idx < (int64_t)nr * L; idx += kHhThreads) {
