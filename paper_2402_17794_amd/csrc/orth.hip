@@ -1295,12 +1295,12 @@ hipError_t launch_apply(int dtype, const void* in, int64_t ldi, int64_t rows, in
 // The levels are separated by a grid-wide barrier (one counter and one
 // generation word in the flags block, counter zero between barriers), so
 // the kernel is launched with one workgroup per level-1 chunk (<= 64
-// workgroups of 512 threads, all resident at once on 256 compute units);
+// workgroups of 1024 threads, all resident at once on 256 compute units);
 // the waits are bounded, and a barrier that does not complete sets
 // RSVD_INFO_FALLBACK_TIMEOUT instead of hanging.  When the CholeskyQR
 // passes succeeded (and the fallback is not forced) every workgroup returns
 // at once.
-constexpr int kHhThreads = 512;
+constexpr int kHhThreads = 1024;
 constexpr int kHhMaxChunks = 64;
 constexpr int kHhFanIn = 4;
 constexpr int kHhMaxLevels = 4;             // 64 -> 16 -> 4 -> 1
@@ -1376,44 +1376,44 @@ __device__ void hh_grid_sync(DevFlags* flags, int nblocks) {
 // in the tile with vst = L): w = tau v^T X, then X -= v w.  The workgroup
 // works on 128 columns at a time, one column per lane, so every load and
 // store of a row is contiguous across the lanes; the kHhThreads / 128 row
-// groups take rows j + g, j + g + groups, ... with four loads in flight, and
+// groups take rows j + g, j + g + groups, ... with eight loads in flight, and
 // their partial inner products are summed in group order through wbuf
 // (kHhThreads doubles of LDS).  Every thread of the workgroup calls this.
 __device__ void hh_reflect_block(double* X, const double* v, int vst, int j, int nr, int L, int c0, int l, double tj,
                                  double* wbuf) {
-    constexpr int CG = 128;
+    constexpr int CG = 128, U = 8;
     const int tid = threadIdx.x, cl = tid % CG, rg = tid / CG, nrg = blockDim.x / CG;
     const int64_t sv = vst;
     for (int cb = c0; cb < l; cb += CG) {
         const int c = cb + cl;
         const bool act = c < l;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        double a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) a[u] = 0.0;
         if (act) {
             int i = j + rg;
-            for (; i + 3 * nrg < nr; i += 4 * nrg) {
-                const double x0 = X[(int64_t)i * L + c], x1 = X[(int64_t)(i + nrg) * L + c];
-                const double x2 = X[(int64_t)(i + 2 * nrg) * L + c], x3 = X[(int64_t)(i + 3 * nrg) * L + c];
-                a0 = fma(v[i * sv], x0, a0);
-                a1 = fma(v[(i + nrg) * sv], x1, a1);
-                a2 = fma(v[(i + 2 * nrg) * sv], x2, a2);
-                a3 = fma(v[(i + 3 * nrg) * sv], x3, a3);
+            for (; i + (U - 1) * nrg < nr; i += U * nrg) {
+                double x[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) x[u] = X[(int64_t)(i + u * nrg) * L + c];
+#pragma unroll
+                for (int u = 0; u < U; ++u) a[u] = fma(v[(i + u * nrg) * sv], x[u], a[u]);
             }
-            for (; i < nr; i += nrg) a0 = fma(v[i * sv], X[(int64_t)i * L + c], a0);
+            for (; i < nr; i += nrg) a[0] = fma(v[i * sv], X[(int64_t)i * L + c], a[0]);
         }
-        wbuf[rg * CG + cl] = (a0 + a1) + (a2 + a3);
+        wbuf[rg * CG + cl] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
         __syncthreads();
         double w = 0.0;
         for (int g = 0; g < nrg; ++g) w += wbuf[g * CG + cl];
         w *= tj;
         if (act) {
             int i = j + rg;
-            for (; i + 3 * nrg < nr; i += 4 * nrg) {
-                const double x0 = X[(int64_t)i * L + c], x1 = X[(int64_t)(i + nrg) * L + c];
-                const double x2 = X[(int64_t)(i + 2 * nrg) * L + c], x3 = X[(int64_t)(i + 3 * nrg) * L + c];
-                X[(int64_t)i * L + c] = fma(-w, v[i * sv], x0);
-                X[(int64_t)(i + nrg) * L + c] = fma(-w, v[(i + nrg) * sv], x1);
-                X[(int64_t)(i + 2 * nrg) * L + c] = fma(-w, v[(i + 2 * nrg) * sv], x2);
-                X[(int64_t)(i + 3 * nrg) * L + c] = fma(-w, v[(i + 3 * nrg) * sv], x3);
+            for (; i + (U - 1) * nrg < nr; i += U * nrg) {
+                double x[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) x[u] = X[(int64_t)(i + u * nrg) * L + c];
+#pragma unroll
+                for (int u = 0; u < U; ++u) X[(int64_t)(i + u * nrg) * L + c] = fma(-w, v[(i + u * nrg) * sv], x[u]);
             }
             for (; i < nr; i += nrg) X[(int64_t)i * L + c] = fma(-w, v[i * sv], X[(int64_t)i * L + c]);
         }
