@@ -1282,8 +1282,11 @@ hipError_t launch_apply(int dtype, const void* in, int64_t ldi, int64_t rows, in
 // cannot factor (rank-deficient, zero, or too ill-conditioned), as a TSQR
 // tree on many workgroups.  Level 1 splits the rows into G1 <= 64 chunks of
 // at least L rows; each workgroup factors its chunk Y_c = Q_c R_c.  Each
-// higher level stacks up to 8 of the R factors below it and factors the
-// stack, until one factor R remains (the root).  Q is then formed top down:
+// higher level stacks up to 4 of the R factors below it and factors the
+// stack, until one factor R remains (the root).  A stack of upper-triangular
+// L x L blocks keeps that form under its own reflections, so reflector j of
+// a stack touches only row j of the first block and rows 0..j of the others
+// (HhRows), about a third of the stack's rows on average.  Q is then formed top down:
 // the root's reflectors applied to the first l columns of the identity give
 // M (a stack of L x L blocks); each tile below applies its reflectors to
 // [its block of M; 0], and at level 1 that is the tile's rows of Q.  Columns
@@ -1295,12 +1298,12 @@ hipError_t launch_apply(int dtype, const void* in, int64_t ldi, int64_t rows, in
 // The levels are separated by a grid-wide barrier (one counter and one
 // generation word in the flags block, counter zero between barriers), so
 // the kernel is launched with one workgroup per level-1 chunk (<= 64
-// workgroups of 1024 threads, all resident at once on 256 compute units);
+// workgroups of 512 threads, all resident at once on 256 compute units);
 // the waits are bounded, and a barrier that does not complete sets
 // RSVD_INFO_FALLBACK_TIMEOUT instead of hanging.  When the CholeskyQR
 // passes succeeded (and the fallback is not forced) every workgroup returns
 // at once.
-constexpr int kHhThreads = 1024;
+constexpr int kHhThreads = 512;
 constexpr int kHhMaxChunks = 64;
 constexpr int kHhFanIn = 4;
 constexpr int kHhMaxLevels = 4;             // 64 -> 16 -> 4 -> 1
@@ -1371,19 +1374,37 @@ __device__ void hh_grid_sync(DevFlags* flags, int nblocks) {
     __syncthreads();
 }
 
-// X <- (I - tau v v^T) X on rows j..nr-1 and columns c0..l-1 of X (row
-// stride L), the reflector v in v[i * vst] (in LDS with vst = 1, or in place
-// in the tile with vst = L): w = tau v^T X, then X -= v w.  The workgroup
-// works on 128 columns at a time, one column per lane, so every load and
-// store of a row is contiguous across the lanes; the kHhThreads / 128 row
-// groups take rows j + g, j + g + groups, ... with eight loads in flight, and
+// The rows of reflector j of a tile (nr rows, row stride L): rows j..nr-1 of
+// a dense tile (level 1), or, in a stack of upper-triangular L x L blocks
+// (the higher levels), row j of the first block and rows 0..j of each of
+// the others, where every other entry of the reflector's column and of the
+// columns it updates is zero.  Rows are numbered s = 0 .. count() - 1.
+struct HhRows {
+    int j, nr, L;
+    bool stk;
+    __device__ int count() const { return stk ? 1 + (nr / L - 1) * (j + 1) : nr - j; }
+    __device__ int row(int s) const {
+        if (!stk) return j + s;
+        if (s == 0) return j;
+        const int t = s - 1;
+        return (1 + t / (j + 1)) * L + t % (j + 1);
+    }
+};
+
+// X <- (I - tau v v^T) X on the rows rs of reflector j and columns c0..l-1
+// of X (row stride L), the reflector v in v[i * vst] (in LDS with vst = 1, or
+// in place in the tile with vst = L): w = tau v^T X, then X -= v w.  The
+// workgroup works on 128 columns at a time, one column per lane, so every
+// load and store of a row is contiguous across the lanes; the kHhThreads /
+// 128 row groups take rows s = g, g + groups, ... of rs with eight loads in flight, and
 // their partial inner products are summed in group order through wbuf
 // (kHhThreads doubles of LDS).  Every thread of the workgroup calls this.
-__device__ void hh_reflect_block(double* X, const double* v, int vst, int j, int nr, int L, int c0, int l, double tj,
+__device__ void hh_reflect_block(double* X, const double* v, int vst, const HhRows& rs, int c0, int l, double tj,
                                  double* wbuf) {
     constexpr int CG = 128, U = 8;
     const int tid = threadIdx.x, cl = tid % CG, rg = tid / CG, nrg = blockDim.x / CG;
-    const int64_t sv = vst;
+    const int64_t sv = vst, L = rs.L;
+    const int n = rs.count();
     for (int cb = c0; cb < l; cb += CG) {
         const int c = cb + cl;
         const bool act = c < l;
@@ -1391,15 +1412,21 @@ __device__ void hh_reflect_block(double* X, const double* v, int vst, int j, int
 #pragma unroll
         for (int u = 0; u < U; ++u) a[u] = 0.0;
         if (act) {
-            int i = j + rg;
-            for (; i + (U - 1) * nrg < nr; i += U * nrg) {
+            int s = rg;
+            for (; s + (U - 1) * nrg < n; s += U * nrg) {
+                int i[U];
                 double x[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) x[u] = X[(int64_t)(i + u * nrg) * L + c];
+                for (int u = 0; u < U; ++u) i[u] = rs.row(s + u * nrg);
 #pragma unroll
-                for (int u = 0; u < U; ++u) a[u] = fma(v[(i + u * nrg) * sv], x[u], a[u]);
+                for (int u = 0; u < U; ++u) x[u] = X[i[u] * L + c];
+#pragma unroll
+                for (int u = 0; u < U; ++u) a[u] = fma(v[i[u] * sv], x[u], a[u]);
             }
-            for (; i < nr; i += nrg) a[0] = fma(v[i * sv], X[(int64_t)i * L + c], a[0]);
+            for (; s < n; s += nrg) {
+                const int i = rs.row(s);
+                a[0] = fma(v[i * sv], X[i * L + c], a[0]);
+            }
         }
         wbuf[rg * CG + cl] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
         __syncthreads();
@@ -1407,15 +1434,21 @@ __device__ void hh_reflect_block(double* X, const double* v, int vst, int j, int
         for (int g = 0; g < nrg; ++g) w += wbuf[g * CG + cl];
         w *= tj;
         if (act) {
-            int i = j + rg;
-            for (; i + (U - 1) * nrg < nr; i += U * nrg) {
+            int s = rg;
+            for (; s + (U - 1) * nrg < n; s += U * nrg) {
+                int i[U];
                 double x[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) x[u] = X[(int64_t)(i + u * nrg) * L + c];
+                for (int u = 0; u < U; ++u) i[u] = rs.row(s + u * nrg);
 #pragma unroll
-                for (int u = 0; u < U; ++u) X[(int64_t)(i + u * nrg) * L + c] = fma(-w, v[(i + u * nrg) * sv], x[u]);
+                for (int u = 0; u < U; ++u) x[u] = X[i[u] * L + c];
+#pragma unroll
+                for (int u = 0; u < U; ++u) X[i[u] * L + c] = fma(-w, v[i[u] * sv], x[u]);
             }
-            for (; i < nr; i += nrg) X[(int64_t)i * L + c] = fma(-w, v[i * sv], X[(int64_t)i * L + c]);
+            for (; s < n; s += nrg) {
+                const int i = rs.row(s);
+                X[i * L + c] = fma(-w, v[i * sv], X[i * L + c]);
+            }
         }
         __syncthreads();                            // wbuf is reused by the next block of columns
     }
@@ -1427,14 +1460,17 @@ __device__ void hh_reflect_block(double* X, const double* v, int vst, int j, int
 // beta_j e_1; the trailing columns c < l are updated by the whole workgroup
 // (hh_reflect_block).  Above the diagonal T then holds R; beta holds its
 // diagonal.  vs: LDS for nr doubles; wbuf: LDS for blockDim.x doubles.
-__device__ void hh_factor_tile(double* T, int nr, int L, int l, double* tau, double* beta, double* red, double* vs,
-                               double* wbuf) {
+__device__ void hh_factor_tile(double* T, int nr, int L, int l, bool stk, double* tau, double* beta, double* red,
+                               double* vs, double* wbuf) {
     const int tid = threadIdx.x;
     const int jmax = min(nr, l);
     const bool in_lds = nr <= kHhVsMax;
     for (int j = 0; j < jmax; ++j) {
+        const HhRows rs{j, nr, L, stk};
+        const int n = rs.count();
         double s = 0.0;
-        for (int i = j + tid; i < nr; i += blockDim.x) {
+        for (int q = tid; q < n; q += blockDim.x) {
+            const int i = rs.row(q);
             const double x = T[(int64_t)i * L + j];
             if (in_lds) vs[i] = x;
             s = fma(x, x, s);
@@ -1459,26 +1495,30 @@ __device__ void hh_factor_tile(double* T, int nr, int L, int l, double* tau, dou
         }
         __syncthreads();
         const double* v = in_lds ? vs : T + j;
-        hh_reflect_block(T, v, in_lds ? 1 : L, j, nr, L, j + 1, l, tj, wbuf);
+        hh_reflect_block(T, v, in_lds ? 1 : L, rs, j + 1, l, tj, wbuf);
     }
 }
 
 // Z (nr x L) <- H_0 H_1 ... H_{jmax-1} Z with the reflectors of tile T (as
 // left by hh_factor_tile), columns c < l only.  vs: LDS for nr doubles;
 // wbuf: LDS for blockDim.x doubles.
-__device__ void hh_apply_tile(const double* T, int nr, int L, int l, const double* tau, double* Z, double* vs,
-                              double* wbuf) {
+__device__ void hh_apply_tile(const double* T, int nr, int L, int l, bool stk, const double* tau, double* Z,
+                              double* vs, double* wbuf) {
     const int tid = threadIdx.x;
     const int jmax = min(nr, l);
     const bool in_lds = nr <= kHhVsMax;
     for (int j = jmax - 1; j >= 0; --j) {
         const double tj = tau[j];
         if (tj == 0.0) continue;                    // same value in every thread
+        const HhRows rs{j, nr, L, stk};
         if (in_lds)
-            for (int i = j + tid; i < nr; i += blockDim.x) vs[i] = T[(int64_t)i * L + j];
+            for (int q = tid; q < rs.count(); q += blockDim.x) {
+                const int i = rs.row(q);
+                vs[i] = T[(int64_t)i * L + j];
+            }
         __syncthreads();
         const double* v = in_lds ? vs : T + j;
-        hh_reflect_block(Z, v, in_lds ? 1 : L, j, nr, L, 0, l, tj, wbuf);
+        hh_reflect_block(Z, v, in_lds ? 1 : L, rs, 0, l, tj, wbuf);
     }
 }
 
@@ -1521,7 +1561,7 @@ __global__ __launch_bounds__(kHhThreads) void householder_kernel(const T* __rest
             }
             double* tau = up + tr.t_off[h] + (int64_t)b * L;
             double* beta = tau + (int64_t)tr.n[h] * L;
-            hh_factor_tile(Tt, nr, L, l, tau, beta, red, vs, wbuf);
+            hh_factor_tile(Tt, nr, L, l, h > 1, tau, beta, red, vs, wbuf);
             if (h < tr.nlev) {                          // R of this tile -> block b of the level h + 1 stack
                 double* Rp = up + tr.s_off[h + 1] + (int64_t)b * L * L;
                 for (int idx = tid; idx < L * L; idx += kHhThreads) {
@@ -1550,7 +1590,7 @@ __global__ __launch_bounds__(kHhThreads) void householder_kernel(const T* __rest
             }
             __syncthreads();
             const double* tau = up + tr.t_off[h] + (int64_t)b * L;
-            hh_apply_tile(tile_base(h, b), nr, L, l, tau, Z, vs, wbuf);
+            hh_apply_tile(tile_base(h, b), nr, L, l, h > 1, tau, Z, vs, wbuf);
             if (h == 1) {                               // this chunk's rows of Q, signs from the root's R
                 const int64_t r0 = chunk(b);
                 for (int64_t idx = tid; idx < (int64_t)nr * L; idx += kHhThreads) {
