@@ -391,65 +391,73 @@ __global__ __launch_bounds__(1024) void chol_blk_kernel(const double* __restrict
         }
         if (tid == 0) s_broke = 0;
         __syncthreads();
-        for (int p = 0; p < nt; ++p) {
-            const int j0 = 16 * p;
-            if (wid == 0) {
-                // 1. Diagonal block in registers, lane = column of [A_pp | I]
-                // (chol_tile16_lanes); the identity half becomes R_pp^{-T}.
-                const int c = lane & 15;
-                double x[16];
+        // 1. Diagonal block p in registers (wavefront 0), lane = column of
+        // [A_pp | I] (chol_tile16_lanes); the identity half becomes R_pp^{-T}.
+        auto factor_diag = [&](int p) {
+            const int j0 = 16 * p, c = lane & 15;
+            double x[16];
 #pragma unroll
-                for (int r = 0; r < 16; ++r)
-                    x[r] = lane < 16 ? (r <= c ? A[(size_t)(j0 + r) * L + j0 + c] : 0.0)
-                                     : (lane < 32 && r == c ? 1.0 : 0.0);
-                const bool bad = chol_tile16_lanes(x, dg + j0, l - j0, rel, shift);
-                if (!bad) {
-                    if (lane < 16) {        // R_pp (upper) back into A for the mode-2 output
+            for (int r = 0; r < 16; ++r)
+                x[r] = lane < 16 ? (r <= c ? A[(size_t)(j0 + r) * L + j0 + c] : 0.0)
+                                 : (lane < 32 && r == c ? 1.0 : 0.0);
+            const bool bad = chol_tile16_lanes(x, dg + j0, l - j0, rel, shift);
+            if (!bad) {
+                if (lane < 16) {        // R_pp (upper) back into A for the mode-2 output
 #pragma unroll
-                        for (int r = 0; r < 16; ++r)
-                            if (r <= c) A[(size_t)(j0 + r) * L + j0 + c] = x[r];
-                    } else if (lane < 32) { // R_pp^{-1}, row-major: column c of R_pp^{-T} is its row c
+                    for (int r = 0; r < 16; ++r)
+                        if (r <= c) A[(size_t)(j0 + r) * L + j0 + c] = x[r];
+                } else if (lane < 32) { // R_pp^{-1}, row-major: column c of R_pp^{-T} is its row c
 #pragma unroll
-                        for (int r = 0; r < 16; ++r) Dinv[p][c * 16 + r] = x[r];
+                    for (int r = 0; r < 16; ++r) Dinv[p][c * 16 + r] = x[r];
+                }
+            } else if (lane == 0) {
+                s_broke = 1;
+            }
+        };
+        // p = -1 only factors the first diagonal block (one call site keeps
+        // the register demand of a single inlined factorisation).
+        for (int p = -1; p < nt && !s_broke; ++p) {
+            if (p >= 0) {
+                const int j0 = 16 * p;
+                // 2. Panel row tiles: R_pq = R_pp^{-T} A_pq.
+                for (int q = p + 1 + wid; q < nt; q += 16) {
+                    doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int st = 0; st < 4; ++st) {
+                        const int k = 4 * st + lk;
+                        acc = mfma16x16x4(Dinv[p][k * 16 + li], A[(size_t)(j0 + k) * L + q * 16 + li], acc);
                     }
-                } else if (lane == 0) {
-                    s_broke = 1;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int r = lk + 4 * v;
+                        A[(size_t)(j0 + r) * L + q * 16 + li] = acc[v];
+                        Prow[r * kCholBlkLd + q * 16 + li] = acc[v];
+                    }
+                }
+                __syncthreads();
+                // 3. Trailing update of the tiles (q, r), p < q <= r.  Wavefront 0
+                // takes the next diagonal tile (t = 0) and factors it at once while
+                // the others share the remaining tiles (look-ahead).
+                const int nr = nt - p - 1, ntr = nr * (nr + 1) / 2;
+                for (int t = wid; t < (wid == 0 ? min(1, ntr) : ntr); t += wid == 0 ? 1 : 15) {
+                    int qq = 0, tt = t;
+                    while (tt >= nr - qq) { tt -= nr - qq; ++qq; }
+                    const int q = p + 1 + qq, r = q + tt;
+                    doublex4 acc;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[v] = A[(size_t)(q * 16 + lk + 4 * v) * L + r * 16 + li];
+#pragma unroll
+                    for (int st = 0; st < 4; ++st) {
+                        const int k = 4 * st + lk;
+                        acc = mfma16x16x4(-Prow[k * kCholBlkLd + q * 16 + li], Prow[k * kCholBlkLd + r * 16 + li], acc);
+                    }
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) A[(size_t)(q * 16 + lk + 4 * v) * L + r * 16 + li] = acc[v];
                 }
             }
-            __syncthreads();
-            if (s_broke) break;
-            // 2. Panel row tiles: R_pq = R_pp^{-T} A_pq.
-            for (int q = p + 1 + wid; q < nt; q += 16) {
-                doublex4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int st = 0; st < 4; ++st) {
-                    const int k = 4 * st + lk;
-                    acc = mfma16x16x4(Dinv[p][k * 16 + li], A[(size_t)(j0 + k) * L + q * 16 + li], acc);
-                }
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int r = lk + 4 * v;
-                    A[(size_t)(j0 + r) * L + q * 16 + li] = acc[v];
-                    Prow[r * kCholBlkLd + q * 16 + li] = acc[v];
-                }
-            }
-            __syncthreads();
-            // 3. Trailing update of the tiles (q, r), p < q <= r.
-            const int nr = nt - p - 1, ntr = nr * (nr + 1) / 2;
-            for (int t = wid; t < ntr; t += 16) {
-                int qq = 0, tt = t;
-                while (tt >= nr - qq) { tt -= nr - qq; ++qq; }
-                const int q = p + 1 + qq, r = q + tt;
-                doublex4 acc;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[v] = A[(size_t)(q * 16 + lk + 4 * v) * L + r * 16 + li];
-#pragma unroll
-                for (int st = 0; st < 4; ++st) {
-                    const int k = 4 * st + lk;
-                    acc = mfma16x16x4(-Prow[k * kCholBlkLd + q * 16 + li], Prow[k * kCholBlkLd + r * 16 + li], acc);
-                }
-#pragma unroll
-                for (int v = 0; v < 4; ++v) A[(size_t)(q * 16 + lk + 4 * v) * L + r * 16 + li] = acc[v];
+            if (wid == 0 && p + 1 < nt) {
+                __threadfence_block();      // the tile's stores before its lanes read it back
+                factor_diag(p + 1);
             }
             __syncthreads();
         }
