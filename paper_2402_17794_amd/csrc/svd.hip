@@ -539,6 +539,74 @@ __global__ __launch_bounds__(kBlkLpp * kBlkGroups) void jacobi_blk_pair_kernel(d
     if (__syncthreads_or(rot) && tid == 0) atomicOr(&rotw[sweep], 1);
 }
 
+// The later block rounds of a sweep: the block pair's 256 cross pairs (one
+// column of each block) in 16 rounds instead of a full sweep over its 32
+// columns.  Group g keeps column g of the first block and meets column
+// (g + r) mod 16 of the second in round r; the second block's columns move
+// one group down the ring through LDS after each round (two buffers, one
+// barrier per round).  The pairs inside a block meet in the first block
+// round of every sweep (jacobi_blk_pair_kernel, where each block takes part
+// once), so every pair of columns still meets once per sweep.
+template <int R>
+__global__ __launch_bounds__(kBlkLpp * kBlkGroups) void jacobi_blk_cross_kernel(double* __restrict__ work, int nb2,
+                                                                                 int round, int sweep, double tol) {
+    constexpr int LPP = kBlkLpp, G = kBlkGroups;
+    const double tol2 = tol * tol;
+    __shared__ double xch[2 * R * G * LPP];          // [buffer][k][group][lane]
+    __shared__ JColumn xcol[2][G];
+    double* X = work;
+    int* rotw = reinterpret_cast<int*>(work + (size_t)kMaxL * kMaxL);
+    if (sweep > 0 && rotw[sweep - 1] == 0) return;   // the previous sweep rotated nothing
+    const int tid = threadIdx.x, gi = tid / LPP, e = tid % LPP;
+    auto xidx = [&](int buf, int k, int g) { return ((buf * R + k) * G + g) * LPP + e; };
+    int p1, p2;
+    rr_pair(round, blockIdx.x, nb2, p1, p2);
+    const int b0 = min(p1, p2), b1 = max(p1, p2);
+    double x0[R], x1[R];                             // column gi of block b0; the visiting column of b1
+    JColumn c0, c1;
+    c0.id = 16 * b0 + gi;
+    c1.id = 16 * b1 + gi;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        x0[k] = X[(int64_t)c0.id * kMaxL + e + LPP * k];
+        x1[k] = X[(int64_t)c1.id * kMaxL + e + LPP * k];
+    }
+    c0.sc = c1.sc = c0.isc = c1.isc = 1.0;
+    c0.nr = quarter_sum(partial_dot<R>(x0, x0));
+    c1.nr = quarter_sum(partial_dot<R>(x1, x1));
+    const int gn = (gi + 1) % G;                     // the group whose column arrives next
+    int rot = 0;
+    for (int r = 0; r < G; ++r) {
+        const double g = quarter_sum(partial_dot<R>(x0, x1)) * (c0.sc * c1.sc);
+        const double t = jacobi_tan(c0.nr, c1.nr, g, rot, tol2);
+        const JRot o = jacobi_rot(c0, c1, g, t);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const double yi = x0[k], yj = x1[k];
+            x0[k] = fma(-o.tr, yj, yi);
+            x1[k] = fma(o.tir, yi, yj);
+        }
+        c0 = o.ci;
+        c1 = o.cj;
+        if (r + 1 < G) {
+            const int buf = r & 1;
+#pragma unroll
+            for (int k = 0; k < R; ++k) xch[xidx(buf, k, gi)] = x1[k];
+            if (e == 0) xcol[buf][gi] = c1;
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < R; ++k) x1[k] = xch[xidx(buf, k, gn)];
+            c1 = xcol[buf][gn];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        X[(int64_t)c0.id * kMaxL + e + LPP * k] = x0[k] * c0.sc;
+        X[(int64_t)c1.id * kMaxL + e + LPP * k] = x1[k] * c1.sc;
+    }
+    if (__syncthreads_or(rot) && tid == 0) atomicOr(&rotw[sweep], 1);
+}
+
 // Column norms of the final X, sorted singular values, U~ and M = U~ Sigma^-1
 // (as at the end of the other forms); the sweep cap flag.
 __global__ __launch_bounds__(512) void jacobi_blk_finish_kernel(const double* __restrict__ work, int l, int L,
@@ -589,10 +657,13 @@ static void launch_jacobi_blk(const double* Rm, int l, int L, const double* shif
                               double* Mv, DevFlags* flags, double* work, hipStream_t s, int sweeps, double tol) {
     const int nb = (l + 15) / 16, nb2 = nb + (nb & 1);
     hipLaunchKernelGGL(jacobi_blk_prep_kernel, dim3(1), dim3(1024), 0, s, Rm, l, L, work);
-    for (int sweep = 0; sweep < sweeps; ++sweep)
-        for (int r = 0; r < nb2 - 1; ++r)
-            hipLaunchKernelGGL(jacobi_blk_pair_kernel<R>, dim3(nb2 / 2), dim3(kBlkLpp * kBlkGroups), 0, s, work, nb2,
-                               r, sweep, tol);
+    for (int sweep = 0; sweep < sweeps; ++sweep) {
+        hipLaunchKernelGGL(jacobi_blk_pair_kernel<R>, dim3(nb2 / 2), dim3(kBlkLpp * kBlkGroups), 0, s, work, nb2, 0,
+                           sweep, tol);
+        for (int r = 1; r < nb2 - 1; ++r)
+            hipLaunchKernelGGL(jacobi_blk_cross_kernel<R>, dim3(nb2 / 2), dim3(kBlkLpp * kBlkGroups), 0, s, work,
+                               nb2, r, sweep, tol);
+    }
     hipLaunchKernelGGL(jacobi_blk_finish_kernel, dim3(1), dim3(512), 0, s, work, l, L, shift, sigma, Ut, Mv, flags,
                        sweeps);
 }
