@@ -411,11 +411,14 @@ __device__ __forceinline__ void rr_pair(int r, int s, int n2, int& p1, int& p2) 
 // splits the columns into blocks of 16 (a zero block is added when their
 // number is odd) and orders the block pairs round-robin: a round is one
 // launch in which every workgroup takes one pair of blocks, loads its 32
-// columns into registers (16 lanes per column pair, rows e + 16 k), runs one
-// odd-even transposition sweep over them (every pair of the 32 columns meets
-// once, the ordering of jacobi_oe_kernel) and writes them back.  The launches
-// of a sweep together meet every pair of columns at least once; the kernel
-// boundaries order the rounds, so no workgroup waits for another.  A word per
+// columns into registers (16 lanes per column, rows e + 16 k), rotates them
+// and writes them back.  The first round of a sweep runs one odd-even
+// transposition sweep over the 32 columns (every pair of them meets once,
+// the ordering of jacobi_oe_kernel), which covers the pairs inside every
+// block; the later rounds meet only the cross pairs of their two blocks
+// (jacobi_blk_cross_kernel).  The launches of a sweep together meet every
+// pair of columns once; the kernel boundaries order the rounds, so no
+// workgroup waits for another.  A word per
 // sweep records whether any pair rotated; the launches of a sweep return at
 // once when the previous sweep rotated nothing.  X is kept with column
 // stride kMaxL; rows >= l are zero and stay zero.
